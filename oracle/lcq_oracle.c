@@ -1,0 +1,536 @@
+/*
+ * lcq_oracle.c -- plain single-threaded CPU oracle of the guaranteed-error-
+ * bound quantizers of Fallin & Burtscher (CoDaC'24).
+ *
+ * TEST INFRASTRUCTURE ONLY: called by the tests, the smoke check and the
+ * benchmark's CPU-baseline leg; never by the product path.  It shares no
+ * code with the HIP library.
+ *
+ * The method is an encoding with free choices (which bin, when to fall back),
+ * so this file walks the algorithm's steps in the paper's order, one value at
+ * a time, with every free choice fixed the same way the library fixes it:
+ *
+ *   1. derive the field's parameters from the user's bound          (sec. 2.1)
+ *   2. per value: special values are stored losslessly         (sec. 2.2, 3.1)
+ *   3.            bin: ABS/NOA round x/(2e); REL rounds an approximate
+ *                 log2 of |x| (sec. 2.2; the log2 of sec. 3.2)
+ *   4.            bin range check done without abs() on INT_MIN     (sec. 3.3)
+ *   5.            reconstruct exactly as the decoder will       (sec. 3.1, 3.2)
+ *   6.            verify the bound on that reconstruction; on failure store
+ *                 the value losslessly ("double-checking", sec. 3.1)
+ *   7. outliers go to a separate list in input order, a sentinel code marks
+ *      their place (the separate-list layout the paper contrasts with its
+ *      in-line one, sec. 3.1)
+ *
+ * Compiled with -ffp-contract=off and no fast-math (sec. 3.2: no FMA, only
+ * IEEE-754 operations), SSE arithmetic, round-to-nearest-even.
+ *
+ * Stream layout (little-endian):
+ *   [0,64)          header: u32 magic "LCQ1", u8 version=1, u8 dtype,
+ *                   u8 quantizer, u8 log2(CHUNK)=10, u64 n, u64 n_outliers,
+ *                   f64 eb as passed, then step, bound, aux0, aux1 as raw
+ *                   bits of the field type zero-extended to 64 bits
+ *   [64, 64+4n)     int32 code per value (SENT = INT32_MIN marks an outlier)
+ *   ct  = align16(64+4n):    u64 per CHUNK of values: outliers before it
+ *   out = align16(ct + 8*C): raw bits of each outlier, in input order
+ *   total size = out + n_outliers * sizeof(T); every padding byte is zero
+ */
+#include "lcq_oracle.h"
+
+#include <math.h>
+#include <stddef.h>
+#include <stdint.h>
+#include <string.h>
+#include <xmmintrin.h>
+
+#define CHUNK 1024u
+#define LOG2_CHUNK 10u
+#define SENT ((int32_t)INT32_MIN)
+#define MAXBIN 1073741824.0 /* 2^30: valid bins are -(2^30-1) .. 2^30-1 */
+#define MAGIC 0x3151434Cu   /* bytes 'L','C','Q','1' */
+
+/* ---------------------------------------------------------------- bits --- */
+static uint32_t bits32(float x) { uint32_t u; memcpy(&u, &x, 4); return u; }
+static float from32(uint32_t u) { float x; memcpy(&x, &u, 4); return x; }
+static uint64_t bits64(double x) { uint64_t u; memcpy(&u, &x, 8); return u; }
+static double from64(uint64_t u) { double x; memcpy(&x, &u, 8); return x; }
+
+static void put_u32(uint8_t *p, uint32_t v) { memcpy(p, &v, 4); }
+static void put_u64(uint8_t *p, uint64_t v) { memcpy(p, &v, 8); }
+static uint32_t get_u32(const uint8_t *p) { uint32_t v; memcpy(&v, p, 4); return v; }
+static uint64_t get_u64(const uint8_t *p) { uint64_t v; memcpy(&v, p, 8); return v; }
+
+static uint64_t align16(uint64_t v) { return (v + 15u) & ~(uint64_t)15u; }
+
+/* The arithmetic below must be IEEE-754 binary32/binary64 with round-to-
+ * nearest-even and subnormals kept (sec. 3.2).  MXCSR: RC bits 13-14 = 0,
+ * FTZ bit 15 = 0, DAZ bit 6 = 0. */
+static int fpenv_ok(void) {
+  unsigned csr = _mm_getcsr();
+  return (csr & ((3u << 13) | (1u << 15) | (1u << 6))) == 0;
+}
+
+/* ------------------------------------------------------------ layout ----- */
+static uint64_t n_chunks(uint64_t n) { return (n + CHUNK - 1) / CHUNK; }
+static uint64_t ct_offset(uint64_t n) { return align16(64 + 4 * n); }
+static uint64_t out_offset(uint64_t n) { return align16(ct_offset(n) + 8 * n_chunks(n)); }
+
+uint64_t orc_max_stream_bytes(int dtype, uint64_t n) {
+  uint64_t s = dtype == ORC_F64 ? 8 : 4;
+  return out_offset(n) + s * n;
+}
+
+/* ------------------------------------------- section 3.2 approximations -- */
+/* Approximate log2 of a non-negative float (Mitchell's piecewise-linear
+ * log2).  With E the biased exponent field and F the fraction field, the
+ * value 1.F is rebuilt as a float in [1,2) and the de-biased exponent minus
+ * one is added, in float arithmetic: 1.F + (E - 128).  The sign bit is
+ * ignored. */
+static float log2approx_f32(float a) {
+  uint32_t u = bits32(a);
+  uint32_t E = (u >> 23) & 0xFFu;
+  uint32_t F = u & 0x007FFFFFu;
+  float one_dot_f = from32((127u << 23) | F);
+  float e_minus = (float)((int32_t)E - 128);
+  return one_dot_f + e_minus;
+}
+
+static double log2approx_f64(double a) {
+  uint64_t u = bits64(a);
+  uint64_t E = (u >> 52) & 0x7FFu;
+  uint64_t F = u & 0x000FFFFFFFFFFFFFull;
+  double one_dot_f = from64((1023ull << 52) | F);
+  double e_minus = (double)((int64_t)E - 1024);
+  return one_dot_f + e_minus;
+}
+
+/* Approximate 2^y, the inverse of the above: t = y + 127 re-biases; its
+ * integer part k is the exponent field; t - (k - 1) lies in [1,2) and its
+ * fraction bits become the fraction field.  t is first clamped to
+ * [0, 255] (NaN -> 0) so the conversion to int is always defined; every
+ * code the encoder emits already lies inside that range. */
+static float pow2approx_f32(float y) {
+  float t = y + 127.0f;
+  if (!(t >= 0.0f)) t = 0.0f;
+  if (t > 255.0f) t = 255.0f;
+  int32_t k = (int32_t)t;
+  float g = t - (float)(k - 1);
+  return from32(((uint32_t)k << 23) | (bits32(g) & 0x007FFFFFu));
+}
+
+static double pow2approx_f64(double y) {
+  double t = y + 1023.0;
+  if (!(t >= 0.0)) t = 0.0;
+  if (t > 2047.0) t = 2047.0;
+  int64_t k = (int64_t)t;
+  double g = t - (double)(k - 1);
+  return from64(((uint64_t)k << 52) | (bits64(g) & 0x000FFFFFFFFFFFFFull));
+}
+
+void orc_log2approx_f32(const float *in, float *out, uint64_t n) {
+  for (uint64_t i = 0; i < n; i++) out[i] = log2approx_f32(in[i]);
+}
+void orc_pow2approx_f32(const float *in, float *out, uint64_t n) {
+  for (uint64_t i = 0; i < n; i++) out[i] = pow2approx_f32(in[i]);
+}
+void orc_log2approx_f64(const double *in, double *out, uint64_t n) {
+  for (uint64_t i = 0; i < n; i++) out[i] = log2approx_f64(in[i]);
+}
+void orc_pow2approx_f64(const double *in, double *out, uint64_t n) {
+  for (uint64_t i = 0; i < n; i++) out[i] = pow2approx_f64(in[i]);
+}
+
+/* ------------------------------------------------ parameter derivation --- */
+/* Largest float not above the positive double v (the user's bound is a
+ * decimal double; rounding it down keeps the guarantee for that value). */
+static float round_down_f32(double v) {
+  float t = (float)v;
+  if ((double)t > v) t = nextafterf(t, -INFINITY);
+  return t;
+}
+
+/* Exact test of c*(1+eps) <= eps for 0 < eps < 1 and c > 0.  For c in
+ * [eps/2, eps] the difference eps - c is exact (Sterbenz) and c*eps is exact
+ * in binary128 (106 significant bits), so the comparison is exact. */
+static int quot_le(double c, double eps) {
+  if (c > eps) return 0;
+  if (c < 0.5 * eps) return 1;
+  double d = eps - c;
+  return (__float128)c * (__float128)eps <= (__float128)d;
+}
+
+/* Largest double not above eps/(1+eps). */
+static double rel_low_double(double eps) {
+  double c = eps / (1.0 + eps);
+  while (!quot_le(c, eps)) c = nextafter(c, 0.0);
+  while (quot_le(nextafter(c, INFINITY), eps)) c = nextafter(c, INFINITY);
+  return c;
+}
+
+typedef struct {
+  int q;
+  int degenerate;
+  double step, inv, bound, aux0, aux1, lambda; /* f64 fields */
+  float stepf, invf, boundf, aux0f, aux1f, lambdaf;
+} params_t;
+
+/* NOA range (sec. 2.1.3): smallest and largest finite value; -0 counts as
+ * +0 so the result does not depend on visiting order. */
+static void noa_range_f32(const float *x, uint64_t n, float *lo, float *hi) {
+  float l = INFINITY, h = -INFINITY;
+  for (uint64_t i = 0; i < n; i++) {
+    float v = x[i];
+    if (!isfinite(v)) continue;
+    if (v == 0.0f) v = 0.0f;
+    if (v < l) l = v;
+    if (v > h) h = v;
+  }
+  *lo = l; *hi = h;
+}
+
+static void noa_range_f64(const double *x, uint64_t n, double *lo, double *hi) {
+  double l = INFINITY, h = -INFINITY;
+  for (uint64_t i = 0; i < n; i++) {
+    double v = x[i];
+    if (!isfinite(v)) continue;
+    if (v == 0.0) v = 0.0;
+    if (v < l) l = v;
+    if (v > h) h = v;
+  }
+  *lo = l; *hi = h;
+}
+
+static int derive_f32(int q, double eb, const float *x, uint64_t n, params_t *p) {
+  memset(p, 0, sizeof *p);
+  p->q = q;
+  if (q == ORC_ABS) {
+    /* sec. 2.2: bins of width 2e, value -> nearest bin centre */
+    float e = round_down_f32(eb);
+    p->boundf = e;
+    p->stepf = e + e;
+    p->invf = 1.0f / p->stepf;
+  } else if (q == ORC_REL) {
+    /* Upper side |x'| <= |x|(1+eb) is checked against eh = RD(eb), the
+     * lower side |x'| >= |x|/(1+eb) against el = RD(eb/(1+eb)) (sec. 2.1.2,
+     * the second, stricter form).  Bins of width 2*lambda in approximate-
+     * log2 space with lambda = log2approx(1 + eh). */
+    float eh = round_down_f32(eb);
+    float el = round_down_f32(rel_low_double(eb));
+    float lam = log2approx_f32(1.0f + eh);
+    p->boundf = eh;
+    p->aux0f = el;
+    p->lambdaf = lam;
+    p->stepf = lam + lam;
+    p->invf = 1.0f / p->stepf;
+  } else {
+    /* sec. 2.1.3: bound eb * R with R = max - min; each rounded step is
+     * followed by one step down so that ebR <= eb * R holds exactly. */
+    float lo, hi;
+    noa_range_f32(x, n, &lo, &hi);
+    float r = hi - lo;
+    if (r == INFINITY) r = 3.40282346638528859812e+38f;
+    if (r > 0.0f) r = nextafterf(r, 0.0f);
+    float b = round_down_f32(eb) * r;
+    float ebr = b;
+    if (b > 0.0f) ebr = nextafterf(b, 0.0f);
+    p->aux0f = lo;
+    p->aux1f = hi;
+    if (ebr > 0.0f) {
+      p->boundf = ebr;
+      p->stepf = ebr + ebr;
+      p->invf = 1.0f / p->stepf;
+    } else {
+      p->degenerate = 1;
+      p->boundf = 0.0f;
+      p->stepf = 0.0f;
+      p->invf = 0.0f;
+    }
+  }
+  return ORC_OK;
+}
+
+static int derive_f64(int q, double eb, const double *x, uint64_t n, params_t *p) {
+  memset(p, 0, sizeof *p);
+  p->q = q;
+  if (q == ORC_ABS) {
+    double e = eb;
+    p->bound = e;
+    p->step = e + e;
+    p->inv = 1.0 / p->step;
+  } else if (q == ORC_REL) {
+    double eh = eb;
+    double el = rel_low_double(eb);
+    double lam = log2approx_f64(1.0 + eh);
+    p->bound = eh;
+    p->aux0 = el;
+    p->lambda = lam;
+    p->step = lam + lam;
+    p->inv = 1.0 / p->step;
+  } else {
+    double lo, hi;
+    noa_range_f64(x, n, &lo, &hi);
+    double r = hi - lo;
+    if (r == INFINITY) r = 1.79769313486231570815e+308;
+    if (r > 0.0) r = nextafter(r, 0.0);
+    double b = eb * r;
+    double ebr = b;
+    if (b > 0.0) ebr = nextafter(b, 0.0);
+    p->aux0 = lo;
+    p->aux1 = hi;
+    if (ebr > 0.0) {
+      p->bound = ebr;
+      p->step = ebr + ebr;
+      p->inv = 1.0 / p->step;
+    } else {
+      p->degenerate = 1;
+      p->bound = 0.0;
+      p->step = 0.0;
+      p->inv = 0.0;
+    }
+  }
+  return ORC_OK;
+}
+
+static int check_args(int q, int dtype, double eb) {
+  if (q != ORC_ABS && q != ORC_REL && q != ORC_NOA) return ORC_ERR_ARG;
+  if (dtype != ORC_F32 && dtype != ORC_F64) return ORC_ERR_ARG;
+  if (!(eb > 0.0) || !isfinite(eb)) return ORC_ERR_ARG;
+  if (q == ORC_REL && !(eb < 1.0)) return ORC_ERR_ARG;
+  return ORC_OK;
+}
+
+static void export_params(int dtype, const params_t *p, orc_params *o) {
+  memset(o, 0, sizeof *o);
+  if (dtype == ORC_F32) {
+    o->step = bits32(p->stepf);
+    o->inv = bits32(p->invf);
+    o->bound = bits32(p->boundf);
+    o->aux0 = bits32(p->aux0f);
+    o->aux1 = bits32(p->aux1f);
+    o->lambda = bits32(p->lambdaf);
+  } else {
+    o->step = bits64(p->step);
+    o->inv = bits64(p->inv);
+    o->bound = bits64(p->bound);
+    o->aux0 = bits64(p->aux0);
+    o->aux1 = bits64(p->aux1);
+    o->lambda = bits64(p->lambda);
+  }
+  o->degenerate = p->degenerate;
+}
+
+int orc_params_derive(int q, int dtype, double eb, const void *in, uint64_t n,
+                      orc_params *out) {
+  if (!fpenv_ok()) return ORC_ERR_FPENV;
+  int st = check_args(q, dtype, eb);
+  if (st) return st;
+  if (q == ORC_NOA && n > 0 && !in) return ORC_ERR_ARG;
+  params_t p;
+  if (dtype == ORC_F32) derive_f32(q, eb, (const float *)in, n, &p);
+  else derive_f64(q, eb, (const double *)in, n, &p);
+  export_params(dtype, &p, out);
+  return ORC_OK;
+}
+
+/* ------------------------------------------------------ one value -------- */
+/* Returns 1 if x must be stored losslessly, else 0 with its code in *code. */
+static int encode_f32(const params_t *p, float x, int32_t *code) {
+  uint32_t u = bits32(x);
+  uint32_t E = (u >> 23) & 0xFFu;
+  uint32_t F = u & 0x007FFFFFu;
+
+  /* special values: INF/NaN, denormals; REL also zeros (sec. 2.2, 3.1) */
+  if (E == 0xFFu) return 1;
+  if (E == 0 && F != 0) return 1;
+  if (p->q == ORC_REL && E == 0) return 1;
+  if (p->q == ORC_NOA && p->degenerate) return 1;
+
+  if (p->q == ORC_REL) {
+    float a = from32(u & 0x7FFFFFFFu);
+    float lg = log2approx_f32(a);
+    float qf = rintf(lg * p->invf);
+    /* sec. 3.3: two one-sided range tests, here on the float so that no
+     * out-of-range float-to-int conversion ever happens */
+    if (!(qf > -(float)MAXBIN && qf < (float)MAXBIN)) return 1;
+    int32_t b = (int32_t)qf;
+    float rec = pow2approx_f32((float)b * p->stepf);
+    /* sec. 3.1 double-check, against the sec. 2.1.2 range */
+    int ok;
+    if (rec >= a) ok = (rec - a) < (p->boundf * a);
+    else ok = (a - rec) < (p->aux0f * a);
+    if (!ok) return 1;
+    *code = (int32_t)(((uint32_t)b << 1) | (u >> 31));
+    return 0;
+  }
+
+  float qf = rintf(x * p->invf);
+  if (!(qf > -(float)MAXBIN && qf < (float)MAXBIN)) return 1;
+  int32_t b = (int32_t)qf;
+  float rec = (float)b * p->stepf;
+  if (!(fabsf(x - rec) <= p->boundf)) return 1;
+  *code = b;
+  return 0;
+}
+
+static int encode_f64(const params_t *p, double x, int32_t *code) {
+  uint64_t u = bits64(x);
+  uint64_t E = (u >> 52) & 0x7FFu;
+  uint64_t F = u & 0x000FFFFFFFFFFFFFull;
+
+  if (E == 0x7FFu) return 1;
+  if (E == 0 && F != 0) return 1;
+  if (p->q == ORC_REL && E == 0) return 1;
+  if (p->q == ORC_NOA && p->degenerate) return 1;
+
+  if (p->q == ORC_REL) {
+    double a = from64(u & 0x7FFFFFFFFFFFFFFFull);
+    double lg = log2approx_f64(a);
+    double qd = rint(lg * p->inv);
+    if (!(qd > -MAXBIN && qd < MAXBIN)) return 1;
+    int32_t b = (int32_t)qd;
+    double rec = pow2approx_f64((double)b * p->step);
+    int ok;
+    if (rec >= a) ok = (rec - a) < (p->bound * a);
+    else ok = (a - rec) < (p->aux0 * a);
+    if (!ok) return 1;
+    *code = (int32_t)(((uint32_t)b << 1) | (uint32_t)(u >> 63));
+    return 0;
+  }
+
+  double qd = rint(x * p->inv);
+  if (!(qd > -MAXBIN && qd < MAXBIN)) return 1;
+  int32_t b = (int32_t)qd;
+  double rec = (double)b * p->step;
+  if (!(fabs(x - rec) <= p->bound)) return 1;
+  *code = b;
+  return 0;
+}
+
+/* Decoder side of one non-sentinel code. */
+static float decode_f32(int q, float step, int32_t c) {
+  if (q == ORC_REL) {
+    int32_t sgn = c & 1;
+    int32_t b = (c - sgn) / 2; /* exact: c - sgn is even */
+    float a = pow2approx_f32((float)b * step);
+    return from32(bits32(a) | ((uint32_t)sgn << 31));
+  }
+  return (float)c * step;
+}
+
+static double decode_f64(int q, double step, int32_t c) {
+  if (q == ORC_REL) {
+    int32_t sgn = c & 1;
+    int32_t b = (c - sgn) / 2;
+    double a = pow2approx_f64((double)b * step);
+    return from64(bits64(a) | ((uint64_t)sgn << 63));
+  }
+  return (double)c * step;
+}
+
+/* --------------------------------------------------------- quantize ------ */
+int orc_quantize(int q, int dtype, double eb, const void *in, uint64_t n,
+                 void *stream, uint64_t cap, uint64_t *stream_bytes) {
+  if (!fpenv_ok()) return ORC_ERR_FPENV;
+  int st = check_args(q, dtype, eb);
+  if (st) return st;
+  if (!stream || !stream_bytes || (n > 0 && !in)) return ORC_ERR_ARG;
+  if (n > (1ull << 38)) return ORC_ERR_ARG;
+  if (cap < orc_max_stream_bytes(dtype, n)) return ORC_ERR_CAPACITY;
+
+  const uint64_t s = dtype == ORC_F64 ? 8 : 4;
+  uint8_t *S = (uint8_t *)stream;
+  const uint64_t ct = ct_offset(n), out = out_offset(n);
+
+  params_t p;
+  if (dtype == ORC_F32) derive_f32(q, eb, (const float *)in, n, &p);
+  else derive_f64(q, eb, (const double *)in, n, &p);
+
+  uint64_t k = 0; /* outliers so far */
+  for (uint64_t i = 0; i < n; i++) {
+    if (i % CHUNK == 0) put_u64(S + ct + 8 * (i / CHUNK), k);
+    int32_t code = 0;
+    int outlier;
+    if (dtype == ORC_F32) {
+      float x;
+      memcpy(&x, (const uint8_t *)in + 4 * i, 4);
+      outlier = encode_f32(&p, x, &code);
+    } else {
+      double x;
+      memcpy(&x, (const uint8_t *)in + 8 * i, 8);
+      outlier = encode_f64(&p, x, &code);
+    }
+    if (outlier) {
+      /* raw bits, never through a float register (keeps NaN payloads) */
+      memcpy(S + out + s * k, (const uint8_t *)in + s * i, s);
+      k++;
+      code = SENT;
+    }
+    memcpy(S + 64 + 4 * i, &code, 4);
+  }
+
+  /* zero padding after the codes and after the chunk table */
+  memset(S + 64 + 4 * n, 0, ct - (64 + 4 * n));
+  memset(S + ct + 8 * n_chunks(n), 0, out - (ct + 8 * n_chunks(n)));
+
+  orc_params o;
+  export_params(dtype, &p, &o);
+  memset(S, 0, 64);
+  put_u32(S + 0, MAGIC);
+  S[4] = 1;
+  S[5] = (uint8_t)dtype;
+  S[6] = (uint8_t)q;
+  S[7] = (uint8_t)LOG2_CHUNK;
+  put_u64(S + 8, n);
+  put_u64(S + 16, k);
+  memcpy(S + 24, &eb, 8);
+  put_u64(S + 32, o.step);
+  put_u64(S + 40, o.bound);
+  put_u64(S + 48, o.aux0);
+  put_u64(S + 56, o.aux1);
+
+  *stream_bytes = out + s * k;
+  return ORC_OK;
+}
+
+/* ------------------------------------------------------- dequantize ------ */
+int orc_dequantize(int dtype, const void *stream, uint64_t bytes, void *out_v,
+                   uint64_t n) {
+  if (!fpenv_ok()) return ORC_ERR_FPENV;
+  if (dtype != ORC_F32 && dtype != ORC_F64) return ORC_ERR_ARG;
+  if (!stream || (n > 0 && !out_v)) return ORC_ERR_ARG;
+  if (bytes < 64) return ORC_ERR_STREAM;
+  const uint8_t *S = (const uint8_t *)stream;
+  const uint64_t s = dtype == ORC_F64 ? 8 : 4;
+
+  if (get_u32(S) != MAGIC || S[4] != 1 || S[5] != dtype || S[6] > 2 ||
+      S[7] != LOG2_CHUNK)
+    return ORC_ERR_STREAM;
+  if (get_u64(S + 8) != n) return ORC_ERR_STREAM;
+  const int q = S[6];
+  const uint64_t k = get_u64(S + 16);
+  const uint64_t ct = ct_offset(n), out = out_offset(n);
+  if (k > n || bytes < out + s * k) return ORC_ERR_STREAM;
+  const uint64_t stepbits = get_u64(S + 32);
+
+  uint64_t cursor = 0;
+  for (uint64_t i = 0; i < n; i++) {
+    if (i % CHUNK == 0 && get_u64(S + ct + 8 * (i / CHUNK)) != cursor)
+      return ORC_ERR_STREAM;
+    int32_t c;
+    memcpy(&c, S + 64 + 4 * i, 4);
+    uint8_t *dst = (uint8_t *)out_v + s * i;
+    if (c == SENT) {
+      if (cursor >= k) return ORC_ERR_STREAM;
+      memcpy(dst, S + out + s * cursor, s);
+      cursor++;
+    } else if (dtype == ORC_F32) {
+      float v = decode_f32(q, from32((uint32_t)stepbits), c);
+      memcpy(dst, &v, 4);
+    } else {
+      double v = decode_f64(q, from64(stepbits), c);
+      memcpy(dst, &v, 8);
+    }
+  }
+  if (cursor != k) return ORC_ERR_STREAM;
+  return ORC_OK;
+}

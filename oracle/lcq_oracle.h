@@ -1,0 +1,75 @@
+/*
+ * lcq_oracle.h -- the CPU oracle of the guaranteed-error-bound quantizers
+ * (Fallin & Burtscher, "Lessons Learned on the Path to Guaranteeing the
+ * Error Bound in Lossy Quantizers", CoDaC'24).
+ *
+ * TEST INFRASTRUCTURE ONLY.  This library is a plain, slow, single-threaded
+ * C implementation that the tests, the smoke check and the benchmark's CPU
+ * baseline compare the HIP library against.  The product path never links,
+ * loads or calls it.  It shares no code, header or constant with the HIP
+ * library: both are written independently from the same definitions.
+ *
+ * Status codes, enums and the stream layout are restated here on purpose
+ * (they are a file format, so they must agree byte for byte).
+ *
+ * Every function is synchronous, uses host pointers only and allocates
+ * nothing.  It refuses to run (ORC_ERR_FPENV) unless the x87/SSE control
+ * state is round-to-nearest with flush-to-zero and denormals-are-zero off,
+ * so that every float operation is the IEEE-754 one the paper relies on
+ * (section 3.2).
+ */
+#ifndef LCQ_ORACLE_H
+#define LCQ_ORACLE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum { ORC_F32 = 0, ORC_F64 = 1 };
+enum { ORC_ABS = 0, ORC_REL = 1, ORC_NOA = 2 };
+enum { ORC_OK = 0, ORC_ERR_ARG = 1, ORC_ERR_CAPACITY = 2, ORC_ERR_STREAM = 3,
+       ORC_ERR_FPENV = 5 };
+
+/* Per-field parameters after derivation (all floating values as raw bits of
+ * the field type, zero-extended to 64 bits). */
+typedef struct {
+  uint64_t step;      /* bin width in the quantized domain                     */
+  uint64_t inv;       /* 1 / step                                              */
+  uint64_t bound;     /* ABS: e; NOA: ebR; REL: eh                             */
+  uint64_t aux0;      /* NOA: lo; REL: el; ABS: 0                              */
+  uint64_t aux1;      /* NOA: hi; otherwise 0                                  */
+  uint64_t lambda;    /* REL: half bin width in log2 space; otherwise 0        */
+  int32_t degenerate; /* NOA with no usable range: every value stored lossless */
+  int32_t pad;
+} orc_params;
+
+/* Worst-case stream size (every value an outlier). */
+uint64_t orc_max_stream_bytes(int dtype, uint64_t n);
+
+/* Parameter derivation only (NOA reads the input for its range). */
+int orc_params_derive(int q, int dtype, double eb, const void *in, uint64_t n,
+                      orc_params *out);
+
+/* Quantize n values of dtype at in[] into stream[0..cap); writes the stream
+ * size to *stream_bytes. */
+int orc_quantize(int q, int dtype, double eb, const void *in, uint64_t n,
+                 void *stream, uint64_t cap, uint64_t *stream_bytes);
+
+/* Decode a stream produced by orc_quantize (or by anything that follows the
+ * same format) into out[0..n). */
+int orc_dequantize(int dtype, const void *stream, uint64_t bytes, void *out,
+                   uint64_t n);
+
+/* The two approximations of section 3.2, element-wise over arrays, exposed
+ * so the tests can pin them. */
+void orc_log2approx_f32(const float *in, float *out, uint64_t n);
+void orc_pow2approx_f32(const float *in, float *out, uint64_t n);
+void orc_log2approx_f64(const double *in, double *out, uint64_t n);
+void orc_pow2approx_f64(const double *in, double *out, uint64_t n);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,204 @@
+"""Seeded synthetic inputs shared by the tests, the smoke check and the bench.
+
+These stand in for the SDRBench single-precision suites the paper measures on
+(section 5, Table 2), which are not available here, and for the paper's
+generated special-value inputs (section 5).  Nothing in this module performs
+the quantizers' arithmetic: it only draws numbers.  All draws use numpy's
+PCG64 generator with an explicit seed, are computed in float64 and cast to the
+field type with round-to-nearest-even.
+
+Workloads:
+  sines_1d        1-D sum of 8 sines plus N(0, 0.01) noise (2^20 float32)
+  grf_3d          3-D Gaussian random field, power spectrum k^-3, unit variance
+  rel_variant     sign * 10^(-30 + 60 Phi(g)) of a field g, 1 % exact zeros
+  inject_specials NaN (quiet, signalling with payload), +-INF, +-0, denormals,
+                  values next to half-bin borders, values whose bin overflows
+  adversarial_abs values at (2k+1) e and one ulp either side (ABS/NOA borders)
+  adversarial_rel values at Mitchell-antilog bin borders and one ulp either side
+"""
+import math
+
+import numpy as np
+
+__all__ = ["sines_1d", "grf_3d", "rel_variant", "inject_specials", "n_specials",
+           "adversarial_abs", "adversarial_rel", "special_classes"]
+
+
+def _rng(seed):
+    return np.random.Generator(np.random.PCG64(seed))
+
+
+def sines_1d(n=1 << 20, seed=0, dtype=np.float32):
+    """x[i] = sum_k A_k sin(2 pi f_k i / n + phi_k) + N(0, 0.01)."""
+    rng = _rng(seed)
+    amp = rng.uniform(0.1, 10.0, 8)
+    freq = np.exp(rng.uniform(0.0, math.log(max(n / 16.0, 1.0)), 8))
+    phase = rng.uniform(0.0, 2 * math.pi, 8)
+    t = np.arange(n, dtype=np.float64) / n
+    x = np.zeros(n, dtype=np.float64)
+    for a, f, p in zip(amp, freq, phase):
+        x += a * np.sin(2 * math.pi * f * t + p)
+    x += rng.normal(0.0, 0.01, n)
+    return x.astype(dtype)
+
+
+def grf_3d(N, seed, dtype=np.float32, workers=None):
+    """Gaussian random field on an N^3 grid with power spectrum ~ |k|^-3
+    (amplitude |k|^-3/2, zero mean mode), normalised to mean 0, variance 1.
+    Returns a flat array of N^3 values (C order)."""
+    import scipy.fft as sfft
+    if workers is None:
+        import os
+        workers = max(1, min(16, os.cpu_count() or 1))
+    rng = _rng(seed)
+    w = rng.standard_normal((N, N, N))
+    spec = sfft.rfftn(w, workers=workers)
+    del w
+    k0 = np.fft.fftfreq(N) * N
+    k2 = np.fft.rfftfreq(N) * N
+    kk = (k0[:, None, None] ** 2 + k0[None, :, None] ** 2)
+    # multiply plane by plane to bound memory
+    for i in range(N):
+        mag = np.sqrt(kk[i] + k2[None, :] ** 2)
+        with np.errstate(divide="ignore"):
+            amp = np.where(mag > 0, mag ** -1.5, 0.0)
+        spec[i] *= amp
+    g = sfft.irfftn(spec, s=(N, N, N), workers=workers).reshape(-1)
+    del spec
+    g -= g.mean()
+    g /= g.std()
+    return g.astype(dtype)
+
+
+def rel_variant(g, seed, dtype=None, zero_frac=0.01):
+    """Lognormal-magnitude variant for REL: x = s * 10^(-30 + 60 Phi(g)) with
+    i.i.d. random signs s and zero_frac of positions set to exactly +0, so
+    log10|x| ~ U(-30, 30) while the field stays spatially smooth."""
+    from scipy.special import ndtr
+    dtype = dtype or g.dtype
+    rng = _rng(seed)
+    u = ndtr(np.asarray(g, dtype=np.float64))
+    x = np.power(10.0, -30.0 + 60.0 * u)
+    sign = rng.integers(0, 2, x.size, dtype=np.int8)
+    x[sign == 1] *= -1.0
+    nz = int(round(zero_frac * x.size))
+    if nz:
+        x[rng.choice(x.size, nz, replace=False)] = 0.0
+    return x.astype(dtype)
+
+
+def n_specials(n, frac):
+    return int(round(n * frac))
+
+
+def special_classes(dtype):
+    return ["qnan+", "qnan-", "snan", "inf+", "inf-", "zero+", "zero-",
+            "den_min+", "den_min-", "den_max+", "den_max-", "den_rand+", "den_rand-",
+            "half_prev", "half_at", "half_next", "overflow", "fmax+", "fmax-"]
+
+
+def _bits_view(dtype):
+    return np.uint32 if np.dtype(dtype) == np.float32 else np.uint64
+
+
+def _special_value(cls, dtype, rng, eb):
+    dtype = np.dtype(dtype)
+    f32 = dtype == np.float32
+    ut = _bits_view(dtype)
+    mbits = 23 if f32 else 52
+    ebits = 8 if f32 else 11
+    expmask = ((1 << ebits) - 1) << mbits
+    sign = 1 << (mbits + ebits)
+    fmax = np.finfo(dtype).max
+
+    def from_bits(b):
+        return np.array([b], dtype=ut).view(dtype)[0]
+    if cls in ("qnan+", "qnan-"):
+        b = expmask | (1 << (mbits - 1)) | int(rng.integers(0, 1 << 8))
+        return from_bits(b | (sign if cls == "qnan-" else 0))
+    if cls == "snan":  # quiet bit clear, non-zero payload
+        return from_bits(expmask | int(rng.integers(1, 1 << (mbits - 1))))
+    if cls == "inf+":
+        return dtype.type(np.inf)
+    if cls == "inf-":
+        return dtype.type(-np.inf)
+    if cls == "zero+":
+        return dtype.type(0.0)
+    if cls == "zero-":
+        return dtype.type(-0.0)
+    if cls.startswith("den_"):
+        s = sign if cls.endswith("-") else 0
+        if cls.startswith("den_min"):
+            return from_bits(1 | s)
+        if cls.startswith("den_max"):
+            return from_bits(((1 << mbits) - 1) | s)
+        return from_bits(int(rng.integers(1, 1 << mbits)) | s)
+    if cls.startswith("half_"):
+        k = int(rng.integers(-10000, 10001))
+        v = dtype.type((2 * k + 1) * eb)
+        if cls == "half_prev":
+            return np.nextafter(v, dtype.type(-np.inf))
+        if cls == "half_next":
+            return np.nextafter(v, dtype.type(np.inf))
+        return v
+    if cls == "overflow":  # |x| / (2 eb) beyond the 2^30 bin range
+        lo = math.log(min(2.0 ** 31 * eb, float(fmax) / 2))
+        hi = math.log(float(fmax))
+        v = math.exp(rng.uniform(lo, hi))
+        return dtype.type(v if rng.integers(0, 2) else -v)
+    if cls == "fmax+":
+        return dtype.type(fmax)
+    if cls == "fmax-":
+        return dtype.type(-fmax)
+    raise ValueError(cls)
+
+
+def inject_specials(x, count, seed, eb):
+    """Replace `count` positions of x (chosen without replacement) by special
+    values; the classes are assigned round-robin over the sorted positions.
+    Returns (x_copy, positions, class_names)."""
+    x = np.array(x, copy=True)
+    rng = _rng(seed)
+    count = min(count, x.size)
+    pos = np.sort(rng.choice(x.size, count, replace=False)) if count else np.zeros(0, np.int64)
+    classes = special_classes(x.dtype)
+    names = []
+    for j, p in enumerate(pos):
+        c = classes[j % len(classes)]
+        x[p] = _special_value(c, x.dtype, rng, eb)
+        names.append(c)
+    return x, pos, names
+
+
+def adversarial_abs(m, eb, seed, dtype):
+    """m values at (2k + 1) * eb (an ABS/NOA bin border for bound eb) and one
+    ulp below / above, k ~ U{-2^20, 2^20}."""
+    rng = _rng(seed)
+    dtype = np.dtype(dtype)
+    k = rng.integers(-(1 << 20), (1 << 20) + 1, m)
+    sgn = np.where(rng.integers(0, 2, m) == 1, 1.0, -1.0)
+    v = (2.0 * k + sgn) * eb
+    v = v.astype(dtype)
+    j = rng.integers(-1, 2, m)
+    v = np.where(j < 0, np.nextafter(v, dtype.type(-np.inf)), v)
+    v = np.where(j > 0, np.nextafter(v, dtype.type(np.inf)), v)
+    return v.astype(dtype)
+
+
+def adversarial_rel(m, eb, seed, dtype):
+    """m values at the Mitchell antilog of (k +- 1/2) * 2 eb (an approximate
+    REL bin border for bound eb) and one ulp either side, random signs."""
+    rng = _rng(seed)
+    dtype = np.dtype(dtype)
+    step = 2.0 * eb
+    lim = 100.0 if dtype == np.float32 else 900.0
+    k = rng.integers(int(-lim / step), int(lim / step), m)
+    y = (k + np.where(rng.integers(0, 2, m) == 1, 0.5, -0.5)) * step
+    fl = np.floor(y)
+    v = np.ldexp(1.0 + (y - fl), fl.astype(np.int64))
+    v = v.astype(dtype)
+    j = rng.integers(-1, 2, m)
+    v = np.where(j < 0, np.nextafter(v, dtype.type(-np.inf)), v)
+    v = np.where(j > 0, np.nextafter(v, dtype.type(np.inf)), v)
+    v = np.where(rng.integers(0, 2, m) == 1, -v, v)
+    return v.astype(dtype)
