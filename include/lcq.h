@@ -1,0 +1,116 @@
+/*
+ * lcq.h -- C ABI of the MI355X (gfx950) guaranteed-error-bound quantizers.
+ *
+ * Implements the quantizer stage of Fallin & Burtscher, "Lessons Learned on
+ * the Path to Guaranteeing the Error Bound in Lossy Quantizers" (CoDaC'24):
+ * point-wise ABS (section 2.1.1), REL (section 2.1.2) and NOA (section 2.1.3)
+ * bounds for float32 / float64 arrays.  Every value is binned, reconstructed
+ * exactly as the decoder will reconstruct it, checked against the bound and
+ * stored losslessly when the check fails, when its bin leaves the valid range
+ * (section 3.3) or when it is NaN, INF or denormal (sections 2.2, 3.1).  REL
+ * bins an approximate log2 and reconstructs with the matching approximate
+ * 2^y (section 3.2); no floating-point contraction is used anywhere
+ * (section 3.2), so the output is a pure function of the input bits.
+ *
+ * Conventions for every entry point:
+ *  - Pointers named d_* are device pointers (HIP device memory) owned by the
+ *    caller; the library keeps no reference to them after the call returns.
+ *    They must be 16-byte aligned, else LCQ_ERR_ARG.
+ *  - Calls are asynchronous on the given HIP stream (0 = null stream) and
+ *    allocate no memory.  Calls on different streams must use different
+ *    workspaces; calls that share a workspace must be ordered (same stream).
+ *  - Argument errors are detected on the host before anything is launched
+ *    and leave every buffer untouched.  LCQ_ERR_HIP reports a failed launch.
+ *  - The library never reads or writes outside the ranges the sizes below
+ *    describe, whatever the data or stream contents.
+ *
+ * Stream format (byte-exact, identical for any launch configuration):
+ *   [0,64)   header, little-endian: u32 magic "LCQ1", u8 version (1),
+ *            u8 dtype, u8 quantizer, u8 log2(chunk) (10), u64 n,
+ *            u64 n_outliers, f64 eb as passed, then four u64 words holding
+ *            the raw bits (zero-extended) of the field type's step, bound,
+ *            aux0 (NOA: range minimum; REL: lower-side bound) and aux1
+ *            (NOA: range maximum; otherwise 0)
+ *   [64, 64+4n)              int32 code per value; INT32_MIN marks a value
+ *                            stored losslessly ("outlier")
+ *   ct = align16(64+4n)      u64 per 1024-value chunk: outliers before it
+ *   out = align16(ct + 8*ceil(n/1024))
+ *                            raw bits of the outliers, in input order
+ *   size = out + n_outliers * sizeof(T); all padding bytes are zero.
+ */
+#ifndef LCQ_H
+#define LCQ_H
+
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum { LCQ_F32 = 0, LCQ_F64 = 1 } lcq_dtype;
+typedef enum { LCQ_ABS = 0, LCQ_REL = 1, LCQ_NOA = 2 } lcq_quantizer;
+typedef enum {
+  LCQ_OK = 0,
+  LCQ_ERR_ARG = 1,      /* bad enum, null / misaligned pointer, bad bound   */
+  LCQ_ERR_CAPACITY = 2, /* output or workspace smaller than required        */
+  LCQ_ERR_STREAM = 3,   /* stream header or structure does not match        */
+  LCQ_ERR_HIP = 4       /* a HIP runtime call failed                        */
+} lcq_status;
+
+/* Largest n any entry point accepts (2^38 values). */
+#define LCQ_MAX_N (1ull << 38)
+
+/* Worst-case size in bytes of a stream of n values (every value an outlier);
+ * the capacity lcq_quantize requires.  Returns 0 for a bad dtype or n. */
+uint64_t lcq_max_stream_bytes(lcq_dtype t, uint64_t n);
+
+/* Bytes of device workspace lcq_quantize / lcq_dequantize need for n values
+ * of type t under quantizer q.  The workspace needs no initialisation; its
+ * first 8 bytes hold the status word of the last lcq_dequantize. */
+uint64_t lcq_workspace_bytes(lcq_quantizer q, lcq_dtype t, uint64_t n);
+
+/* Quantize d_in[0..n) of type t under bound eb (sections 2.1, 3.1-3.3).
+ *  eb:        the user's bound; must be finite and > 0, and < 1 for REL.
+ *             ABS guarantees |x - x'| <= eb, NOA |x - x'| <= eb * R with R the
+ *             range of the finite values, REL same sign and
+ *             |x| / (1+eb) <= |x'| <= |x| (1+eb).
+ *  d_stream:  receives the stream; stream_cap >= lcq_max_stream_bytes(t, n).
+ *  d_stream_bytes: device u64 that receives the stream's size (written by
+ *             the last kernel; read it after the stream is synchronised).
+ *  d_ws:      workspace of ws_bytes >= lcq_workspace_bytes(q, t, n).
+ * Never fails because of the data: every value has an encoding. */
+lcq_status lcq_quantize(lcq_quantizer q, lcq_dtype t, double eb,
+                        const void *d_in, uint64_t n,
+                        void *d_stream, uint64_t stream_cap,
+                        uint64_t *d_stream_bytes,
+                        void *d_ws, uint64_t ws_bytes, hipStream_t stream);
+
+/* Decode a stream into d_out[0..n) of type t (the decoder has no
+ * double-check, section 6).  stream_bytes is the number of valid bytes at
+ * d_stream; the host checks that the codes and chunk table of n values fit.
+ * The header, the outlier count and the chunk table are validated on the
+ * device; a mismatch is recorded in the workspace status word (read it with
+ * lcq_stream_status) and leaves d_out unspecified but nothing outside it is
+ * written.  d_ws needs at least 8 bytes. */
+lcq_status lcq_dequantize(lcq_dtype t, const void *d_stream, uint64_t stream_bytes,
+                          void *d_out, uint64_t n,
+                          void *d_ws, uint64_t ws_bytes, hipStream_t stream);
+
+/* Synchronises `stream` and stores in *h_err the status (LCQ_OK or
+ * LCQ_ERR_STREAM) of the last lcq_dequantize that used d_ws. */
+lcq_status lcq_stream_status(const void *d_ws, hipStream_t stream, int32_t *h_err);
+
+/* Static description of a status code. */
+const char *lcq_status_string(lcq_status s);
+
+/* Measurement hook: when set (non-null), every following lcq_quantize /
+ * lcq_dequantize call made from the calling host thread records `before`
+ * immediately before and `after` immediately after the launch of its main
+ * kernel (the per-value pass), on the call's stream.  Pass nulls to clear. */
+void lcq_profile_events(hipEvent_t before, hipEvent_t after);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,149 @@
+"""Guaranteed-error-bound ABS / REL / NOA quantizers for MI355X (gfx950).
+
+A thin ctypes binding of liblcq.so (C ABI in include/lcq.h): it only checks
+and marshals arguments.  Every step of quantize / dequantize runs in the
+library's HIP kernels; PyTorch provides device memory and streams.  There is
+no CPU fallback: if the library is missing, importing this package fails.
+"""
+import ctypes
+import os
+
+__all__ = ["ABS", "REL", "NOA", "F32", "F64", "LCQError", "lib", "max_stream_bytes",
+           "workspace_bytes", "quantize", "dequantize", "stream_status", "profile_events",
+           "SO_PATH"]
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+SO_PATH = os.path.join(HERE, "liblcq.so")
+
+F32, F64 = 0, 1
+ABS, REL, NOA = 0, 1, 2
+OK, ERR_ARG, ERR_CAPACITY, ERR_STREAM, ERR_HIP = 0, 1, 2, 3, 4
+_QNAMES = {"abs": ABS, "rel": REL, "noa": NOA}
+
+if not os.path.exists(SO_PATH):
+    raise ImportError(f"{SO_PATH} is missing: build it with "
+                      "`python -c 'import __graft_entry__ as g; g.build()'` "
+                      "(or python paper_2407_15037_amd/build.py)")
+
+_lib = ctypes.CDLL(SO_PATH)
+_u64, _vp, _i32, _dbl = ctypes.c_uint64, ctypes.c_void_p, ctypes.c_int, ctypes.c_double
+_lib.lcq_max_stream_bytes.argtypes = [_i32, _u64]
+_lib.lcq_max_stream_bytes.restype = _u64
+_lib.lcq_workspace_bytes.argtypes = [_i32, _i32, _u64]
+_lib.lcq_workspace_bytes.restype = _u64
+_lib.lcq_quantize.argtypes = [_i32, _i32, _dbl, _vp, _u64, _vp, _u64, _vp, _vp, _u64, _vp]
+_lib.lcq_quantize.restype = _i32
+_lib.lcq_dequantize.argtypes = [_i32, _vp, _u64, _vp, _u64, _vp, _u64, _vp]
+_lib.lcq_dequantize.restype = _i32
+_lib.lcq_stream_status.argtypes = [_vp, _vp, ctypes.POINTER(ctypes.c_int32)]
+_lib.lcq_stream_status.restype = _i32
+_lib.lcq_status_string.argtypes = [_i32]
+_lib.lcq_status_string.restype = ctypes.c_char_p
+_lib.lcq_profile_events.argtypes = [_vp, _vp]
+_lib.lcq_profile_events.restype = None
+
+
+def lib():
+    return _lib
+
+
+class LCQError(RuntimeError):
+    def __init__(self, status, what):
+        msg = _lib.lcq_status_string(status).decode()
+        super().__init__(f"{what}: {msg} (status {status})")
+        self.status = status
+
+
+def _check(st, what):
+    if st != OK:
+        raise LCQError(st, what)
+
+
+def _q(q):
+    return _QNAMES[q] if isinstance(q, str) else int(q)
+
+
+def _dtype_code(dtype):
+    import torch
+    if dtype == torch.float32:
+        return F32
+    if dtype == torch.float64:
+        return F64
+    raise TypeError(f"unsupported dtype {dtype}")
+
+
+def _stream_handle(stream):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def max_stream_bytes(dtype, n):
+    return int(_lib.lcq_max_stream_bytes(_dtype_code(dtype), n))
+
+
+def workspace_bytes(q, dtype, n):
+    return int(_lib.lcq_workspace_bytes(_q(q), _dtype_code(dtype), n))
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else ctypes.c_void_p(0)
+
+
+def quantize(x, q, eb, *, out=None, nbytes=None, ws=None, stream=None):
+    """Quantize the contiguous CUDA tensor x (float32 / float64).
+
+    Returns (stream, nbytes): `stream` is a uint8 device tensor of capacity
+    max_stream_bytes, `nbytes` a one-element int64 device tensor receiving the
+    stream's size.  Buffers may be passed in to avoid allocation."""
+    import torch
+    if not x.is_cuda or not x.is_contiguous():
+        raise ValueError("x must be a contiguous CUDA tensor")
+    dt = _dtype_code(x.dtype)
+    n = x.numel()
+    cap = int(_lib.lcq_max_stream_bytes(dt, n))
+    if out is None:
+        out = torch.empty(cap, dtype=torch.uint8, device=x.device)
+    if nbytes is None:
+        nbytes = torch.empty(1, dtype=torch.int64, device=x.device)
+    if ws is None:
+        ws = torch.empty(int(_lib.lcq_workspace_bytes(_q(q), dt, n)), dtype=torch.uint8,
+                         device=x.device)
+    st = _lib.lcq_quantize(_q(q), dt, float(eb), _ptr(x) if n else None, n, _ptr(out),
+                           out.numel(), _ptr(nbytes), _ptr(ws), ws.numel(),
+                           _stream_handle(stream))
+    _check(st, "lcq_quantize")
+    return out, nbytes
+
+
+def dequantize(stream_buf, dtype, n, *, stream_bytes=None, out=None, ws=None, stream=None):
+    """Decode a stream (uint8 CUDA tensor) into a new (or given) tensor of n
+    values.  stream_bytes defaults to the tensor's size."""
+    import torch
+    dt = _dtype_code(dtype)
+    if out is None:
+        out = torch.empty(n, dtype=dtype, device=stream_buf.device)
+    if ws is None:
+        ws = torch.empty(64, dtype=torch.uint8, device=stream_buf.device)
+    sb = stream_buf.numel() if stream_bytes is None else int(stream_bytes)
+    st = _lib.lcq_dequantize(dt, _ptr(stream_buf), sb, _ptr(out) if n else None, n, _ptr(ws),
+                             ws.numel(), _stream_handle(stream))
+    _check(st, "lcq_dequantize")
+    return out
+
+
+def stream_status(ws, stream=None):
+    """Status (OK / ERR_STREAM) of the last dequantize that used ws; syncs."""
+    err = ctypes.c_int32(0)
+    _check(_lib.lcq_stream_status(_ptr(ws), _stream_handle(stream), ctypes.byref(err)),
+           "lcq_stream_status")
+    return int(err.value)
+
+
+def profile_events(before=None, after=None):
+    """Record torch.cuda.Event pairs around the main kernel of every following
+    quantize / dequantize call from this thread (None clears)."""
+    b = ctypes.c_void_p(before.cuda_event) if before is not None else None
+    a = ctypes.c_void_p(after.cuda_event) if after is not None else None
+    _lib.lcq_profile_events(b, a)

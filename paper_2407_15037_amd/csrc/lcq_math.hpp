@@ -1,0 +1,151 @@
+// lcq_math.hpp -- per-value arithmetic of the quantizers, shared by the host
+// parameter derivation and the gfx950 kernels of this library.
+//
+// Everything here is IEEE-754 binary32/binary64 with round-to-nearest-even and
+// subnormals kept; the translation unit is compiled with -ffp-contract=off and
+// '#pragma clang fp contract(off)' so that no multiply-add is fused
+// (section 3.2 of the paper: FMA contraction makes CPU and GPU disagree).
+#pragma once
+#include <stdint.h>
+
+#pragma clang fp contract(off)
+
+#define LCQ_HD __host__ __device__ __forceinline__
+
+namespace lcq {
+
+constexpr uint32_t kChunk = 1024;  // values per chunk-table entry
+constexpr uint32_t kLog2Chunk = 10;
+constexpr int32_t kSent = INT32_MIN;  // code of a value stored losslessly
+constexpr uint32_t kMagic = 0x3151434Cu;  // "LCQ1"
+constexpr double kMaxBin = 1073741824.0;  // 2^30; bins lie in (-2^30, 2^30)
+
+template <typename T> struct FT;
+template <> struct FT<float> {
+  using U = uint32_t;
+  static constexpr int kMant = 23;
+  static constexpr U kExpMask = 0xFFu;
+  static constexpr U kFracMask = 0x007FFFFFu;
+  static constexpr U kSign = 0x80000000u;
+  static constexpr int kBias = 127;
+};
+template <> struct FT<double> {
+  using U = uint64_t;
+  static constexpr int kMant = 52;
+  static constexpr U kExpMask = 0x7FFu;
+  static constexpr U kFracMask = 0x000FFFFFFFFFFFFFull;
+  static constexpr U kSign = 0x8000000000000000ull;
+  static constexpr int kBias = 1023;
+};
+
+LCQ_HD uint32_t to_bits(float x) { return __builtin_bit_cast(uint32_t, x); }
+LCQ_HD uint64_t to_bits(double x) { return __builtin_bit_cast(uint64_t, x); }
+LCQ_HD float from_bits(uint32_t u) { return __builtin_bit_cast(float, u); }
+LCQ_HD double from_bits(uint64_t u) { return __builtin_bit_cast(double, u); }
+
+LCQ_HD float rint_t(float x) { return __builtin_rintf(x); }
+LCQ_HD double rint_t(double x) { return __builtin_rint(x); }
+LCQ_HD float abs_t(float x) { return __builtin_fabsf(x); }
+LCQ_HD double abs_t(double x) { return __builtin_fabs(x); }
+
+// Next value toward zero of a positive value (positive infinity steps to the
+// largest finite value).
+template <typename T> LCQ_HD T step_down(T v) { return from_bits(to_bits(v) - 1); }
+
+// Approximate log2 of section 3.2 (Mitchell): for |a| = 2^e (1 + m) it is
+// e + m, computed as the float 1.m plus the float (E - bias - 1), where E is
+// the biased exponent field.  The sign bit is ignored.
+template <typename T> LCQ_HD T log2approx(T a) {
+  using F = FT<T>;
+  using U = typename F::U;
+  const U u = to_bits(a);
+  const int E = (int)((u >> F::kMant) & F::kExpMask);
+  const T mant = from_bits((U)((U)F::kBias << F::kMant) | (u & F::kFracMask));
+  return mant + (T)(E - (F::kBias + 1));
+}
+
+// Approximate 2^y of section 3.2, the inverse of log2approx: t = y + bias,
+// k = trunc(t) is the exponent field, t - (k - 1) in [1,2) gives the fraction
+// field.  t is clamped to [0, max exponent field] (NaN -> 0) first so the
+// conversion is always defined; every code the encoder emits is inside.
+template <typename T> LCQ_HD T pow2approx(T y) {
+  using F = FT<T>;
+  using U = typename F::U;
+  T t = y + (T)F::kBias;
+  t = (t >= (T)0) ? t : (T)0;
+  t = (t > (T)F::kExpMask) ? (T)F::kExpMask : t;
+  const int k = (int)t;
+  const T g = t - (T)(k - 1);
+  return from_bits((U)(((U)k << F::kMant) | (to_bits(g) & F::kFracMask)));
+}
+
+// Parameters of one field in the field's type.
+template <typename T> struct FieldParams {
+  T step;   // bin width
+  T inv;    // 1 / step
+  T bound;  // ABS: e, NOA: ebR, REL: upper-side relative bound eh
+  T low;    // REL: lower-side relative bound el; otherwise unused
+  int lossless_all;  // NOA field with no usable range: every value lossless
+};
+
+enum : int { kABS = 0, kREL = 1, kNOA = 2 };
+
+// One value -> its int32 code, or kSent if it must be stored losslessly.
+// Evaluates every step for every lane (no data-dependent branches) and only
+// converts the bin to int where it is in range.
+template <typename T, int Q> LCQ_HD int32_t encode(T x, const FieldParams<T> &p) {
+  using F = FT<T>;
+  using U = typename F::U;
+  const U u = to_bits(x);
+  const U E = (u >> F::kMant) & F::kExpMask;
+  const U frac = u & F::kFracMask;
+  // section 2.2 / 3.1: INF, NaN and denormals (REL: also zeros) are lossless
+  bool ok = (E != F::kExpMask) && (E != 0 || (Q != kREL && frac == 0));
+  if (Q == kNOA) ok = ok && !p.lossless_all;
+
+  if (Q == kREL) {
+    const T a = from_bits((U)(u & ~F::kSign));
+    const T q = rint_t(log2approx(a) * p.inv);
+    // section 3.3: both range tests, on the float, before any conversion
+    ok = ok && (q > (T)-kMaxBin) && (q < (T)kMaxBin);
+    const int32_t b = (int32_t)(ok ? q : (T)0);
+    const T rec = pow2approx((T)b * p.step);
+    // section 3.1 double-check against both sides of the section 2.1.2 range
+    const bool up = rec >= a;
+    const T diff = up ? (rec - a) : (a - rec);
+    const T lim = (up ? p.bound : p.low) * a;
+    ok = ok && (diff < lim);
+    const uint32_t code = ((uint32_t)b << 1) | (uint32_t)(u >> (sizeof(T) * 8 - 1));
+    return ok ? (int32_t)code : kSent;
+  } else {
+    const T q = rint_t(x * p.inv);
+    ok = ok && (q > (T)-kMaxBin) && (q < (T)kMaxBin);
+    const int32_t b = (int32_t)(ok ? q : (T)0);
+    const T rec = (T)b * p.step;
+    ok = ok && (abs_t(x - rec) <= p.bound);
+    return ok ? b : kSent;
+  }
+}
+
+// One non-sentinel code -> its value (the decoder side of encode).
+template <typename T> LCQ_HD T decode(int32_t c, T step, bool rel) {
+  using F = FT<T>;
+  using U = typename F::U;
+  if (rel) {
+    const U sgn = (U)(c & 1);
+    const int32_t b = c >> 1;  // arithmetic shift: c = 2b + sign
+    const T a = pow2approx((T)b * step);
+    return from_bits((U)(to_bits(a) | (sgn << (sizeof(T) * 8 - 1))));
+  }
+  return (T)c * step;
+}
+
+// Stream layout.
+LCQ_HD uint64_t align16(uint64_t v) { return (v + 15u) & ~(uint64_t)15u; }
+LCQ_HD uint64_t n_chunks(uint64_t n) { return (n + kChunk - 1) / kChunk; }
+LCQ_HD uint64_t chunk_table_offset(uint64_t n) { return align16(64 + 4 * n); }
+LCQ_HD uint64_t outlier_offset(uint64_t n) {
+  return align16(chunk_table_offset(n) + 8 * n_chunks(n));
+}
+
+}  // namespace lcq

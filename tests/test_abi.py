@@ -1,0 +1,107 @@
+"""CPU checks of the C ABI library: it loads, exports every function that
+include/lcq.h declares, rejects bad arguments on the host without touching a
+GPU, and its gfx950 code keeps the parity rules of section 3.2 (no fused
+multiply-add and no packed-FP32 arithmetic in the per-value kernels,
+float32 subnormals kept)."""
+import ctypes
+import os
+import re
+import subprocess
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "lcq.h")
+
+
+def declared_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(lcq_[a-z0-9_]+)\s*\(", src)))
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for want in ("lcq_quantize", "lcq_dequantize", "lcq_max_stream_bytes",
+                 "lcq_workspace_bytes", "lcq_stream_status"):
+        assert want in names
+
+
+def test_library_exports_every_declared_symbol():
+    import paper_2407_15037_amd as lcq
+    out = subprocess.run(["nm", "-D", "--defined-only", lcq.SO_PATH], capture_output=True,
+                         text=True, check=True).stdout
+    exported = set(re.findall(r" T (\w+)$", out, flags=re.M))
+    missing = [f for f in declared_functions() if f not in exported]
+    assert not missing, missing
+    for f in declared_functions():
+        assert hasattr(lcq.lib(), f)
+
+
+def test_sizes_and_host_argument_errors():
+    import paper_2407_15037_amd as lcq
+    L = lcq.lib()
+    # layout arithmetic (no GPU involved)
+    assert L.lcq_max_stream_bytes(0, 0) == 64
+    assert L.lcq_max_stream_bytes(0, 1) == 64 + 16 + 16 + 4
+    n = 1 << 20
+    ct = (64 + 4 * n + 15) // 16 * 16
+    out = (ct + 8 * (n // 1024) + 15) // 16 * 16
+    assert L.lcq_max_stream_bytes(0, n) == out + 4 * n
+    assert L.lcq_max_stream_bytes(1, n) == out + 8 * n
+    assert L.lcq_max_stream_bytes(2, n) == 0
+    assert L.lcq_workspace_bytes(0, 0, n) > 0 and L.lcq_workspace_bytes(3, 0, n) == 0
+    vp = ctypes.c_void_p
+    fake = vp(1 << 20)  # never dereferenced: every call below fails on the host
+    cases = [
+        (7, 0, 1e-3), (0, 9, 1e-3), (0, 0, 0.0), (0, 0, -1.0), (0, 0, float("nan")),
+        (0, 0, float("inf")), (1, 0, 1.0), (1, 0, 1.5),
+    ]
+    for q, t, eb in cases:
+        st = L.lcq_quantize(q, t, eb, fake, 16, fake, 1 << 30, fake, fake, 1 << 30, None)
+        assert st == lcq.ERR_ARG, (q, t, eb, st)
+    # misaligned pointer
+    st = L.lcq_quantize(0, 0, 1e-3, vp((1 << 20) + 4), 16, fake, 1 << 30, fake, fake, 1 << 30, None)
+    assert st == lcq.ERR_ARG
+    # capacity
+    st = L.lcq_quantize(0, 0, 1e-3, fake, 1000, fake, 100, fake, fake, 1 << 30, None)
+    assert st == lcq.ERR_CAPACITY
+    st = L.lcq_quantize(0, 0, 1e-3, fake, 1000, fake, 1 << 30, fake, fake, 8, None)
+    assert st == lcq.ERR_CAPACITY
+    # dequantize: stream too short for the codes of n values
+    st = L.lcq_dequantize(0, fake, 100, fake, 1000, fake, 64, None)
+    assert st == lcq.ERR_STREAM
+    assert L.lcq_dequantize(5, fake, 1 << 20, fake, 10, fake, 64, None) == lcq.ERR_ARG
+    assert L.lcq_status_string(3).decode().startswith("stream")
+
+
+@pytest.fixture(scope="module")
+def device_asm(tmp_path_factory):
+    from paper_2407_15037_amd import build
+    path = str(tmp_path_factory.mktemp("asm") / "lcq.s")
+    build.asm(path)
+    return open(path).read()
+
+
+def kernel_bodies(asm):
+    bodies = {}
+    for m in re.finditer(r"^(_Z\w+):[^\n]*$(.*?)^\.Lfunc_end", asm, flags=re.M | re.S):
+        bodies[m.group(1)] = m.group(2)
+    return bodies
+
+
+def test_per_value_kernels_have_no_fused_or_packed_fp(device_asm):
+    bodies = kernel_bodies(device_asm)
+    per_value = {k: v for k, v in bodies.items() if "k_quantize" in k or "k_dequantize" in k}
+    assert len(per_value) >= 8, sorted(bodies)
+    # floating-point multiply-adds of any form (integer address mads are fine)
+    bad = re.compile(r"^\s*(v_(?:fma|fmac|mad|mac)\w*_f(?:16|32|64)\w*|v_mad_legacy\w*|"
+                     r"v_fma_legacy\w*|v_pk_fma_f32|v_pk_mul_f32|v_pk_add_f32)\b", flags=re.M)
+    for name, body in per_value.items():
+        hits = bad.findall(body)
+        assert not hits, (name, hits[:5])
+
+
+def test_float32_subnormals_kept(device_asm):
+    modes = re.findall(r"\.amdhsa_float_denorm_mode_32\s+(\d+)", device_asm)
+    assert modes and all(m == "3" for m in modes), modes

@@ -1,0 +1,176 @@
+"""GPU vs oracle parity: the HIP library's stream and decode must equal the
+CPU oracle's byte for byte (integer / byte work: bit-exact), on the same
+seeded inputs, across dtypes, quantizers, bounds, tile-spanning sizes with
+ragged tails and the edge cases of the method."""
+import numpy as np
+import pytest
+
+import oracle as O
+import synth
+from gpu_util import announce, bits, first_diff, gpu_decode, gpu_roundtrip
+from streamcheck import SENT, abs_violations, check_structure, finite_range, parse, rel_violations
+
+pytestmark = pytest.mark.gpu
+
+DTYPES = [np.float32, np.float64]
+
+
+def _parity(q, x, eb, label=""):
+    announce("parity", q, x.dtype, x.size, eb, label)
+    st_g, dec_g = gpu_roundtrip(q, x, eb)
+    st_o = O.quantize(q, x, eb)
+    diff = first_diff(st_g, st_o)
+    assert diff is None, f"{label} {q} {x.dtype} n={x.size} eb={eb}: stream {diff}"
+    dec_o = O.dequantize(st_o, x.dtype, x.size)
+    diff = first_diff(bits(dec_g), bits(dec_o))
+    assert diff is None, f"{label} {q} {x.dtype} n={x.size} eb={eb}: decode {diff}"
+    return st_g, dec_g
+
+
+def _field(dt, n, seed, eb, q):
+    x = synth.sines_1d(n, seed, dtype=dt)
+    x, _, _ = synth.inject_specials(x, max(19, n // 1000), seed + 1, eb)
+    if q == "rel":
+        x = synth.rel_variant(np.nan_to_num(x.astype(np.float64)), seed + 2, dtype=dt)
+        x, _, _ = synth.inject_specials(x, max(19, n // 1000), seed + 3, eb)
+    return x
+
+
+@pytest.mark.parametrize("dt", DTYPES, ids=["f32", "f64"])
+@pytest.mark.parametrize("q,eb", [("abs", 1e-3), ("abs", 1e-6), ("noa", 1e-4),
+                                  ("rel", 1e-2), ("rel", 1e-3)])
+def test_parity_mixed(dt, q, eb):
+    # several tiles plus a ragged tail, specials, bin-border adversarial values
+    n = 5 * 4096 + 777
+    x = _field(dt, n, 11, eb, q)
+    adv = synth.adversarial_rel(3000, eb, 12, dt) if q == "rel" else synth.adversarial_abs(3000, eb, 12, dt)
+    x = np.concatenate([x, adv]).astype(dt)
+    _parity(q, x, eb)
+
+
+@pytest.mark.parametrize("dt", DTYPES, ids=["f32", "f64"])
+@pytest.mark.parametrize("n", [0, 1, 2, 3, 5, 1023, 1024, 1025, 2047, 2048, 2049, 4095, 4096,
+                               4097, 8191, 12289, 65536 + 13])
+def test_parity_sizes(dt, n):
+    x = synth.sines_1d(max(n, 1), 21, dtype=dt)[:n]
+    for q, eb in (("abs", 1e-3), ("noa", 1e-3), ("rel", 1e-3)):
+        y = x if q != "rel" else synth.rel_variant(x.astype(np.float64), 22, dtype=dt)
+        _parity(q, y, eb, f"n={n}")
+
+
+@pytest.mark.parametrize("dt", DTYPES, ids=["f32", "f64"])
+def test_parity_all_specials(dt):
+    base = synth.sines_1d(9000, 31, dtype=dt)
+    x, _, _ = synth.inject_specials(base, 9000, 32, 1e-3)  # every value special
+    for q in ("abs", "rel", "noa"):
+        st, dec = _parity(q, x, 1e-3, "all-specials")
+        P = parse(st, dt)
+        assert not check_structure(P, x, dt)
+
+
+@pytest.mark.parametrize("dt", DTYPES, ids=["f32", "f64"])
+def test_parity_degenerate_noa(dt):
+    x = np.full(10000, 3.5, dt)
+    x[17] = np.inf
+    st, dec = _parity("noa", x, 1e-2, "constant")
+    assert np.all(parse(st, dt)["codes"] == SENT)
+    x = np.full(5000, np.nan, dt)
+    _parity("noa", x, 1e-2, "no-finite")
+
+
+@pytest.mark.parametrize("dt", DTYPES, ids=["f32", "f64"])
+def test_parity_bin_range(dt):
+    # every value's bin near +-2^30 and beyond, and values that need INT_MIN
+    rng = np.random.default_rng(41)
+    t = rng.uniform(-2.0 ** 31.5, 2.0 ** 31.5, 20000)
+    t[:8] = [2.0 ** 30, -(2.0 ** 30), 2.0 ** 31, -(2.0 ** 31), 2.0 ** 30 - 64,
+             -(2.0 ** 30) + 64, 2.0 ** 30 + 64, -(2.0 ** 30) - 64]
+    x = t.astype(dt)  # eb = 0.5 -> step 1, bin = rint(x)
+    _parity("abs", x, 0.5, "bin-range")
+    fmax = np.finfo(dt).max
+    y = np.array([fmax, -fmax, fmax / 2, -fmax / 3, 1.0, -1.0] * 700, dt)
+    for q in ("abs", "noa", "rel"):
+        _parity(q, y, 1e-3 if q != "abs" else 1e-30, "huge")
+
+
+@pytest.mark.parametrize("eb", [1e-1, 1e-3, 1e-5, 1e-7, 0.5, 0.999])
+def test_parity_rel_bounds(eb):
+    for dt in DTYPES:
+        mag = np.power(10.0, np.random.default_rng(51).uniform(-37, 37, 30000))
+        x = (mag * np.where(np.arange(mag.size) % 3 == 0, -1, 1)).astype(dt)
+        _parity("rel", x, eb, "rel-eb")
+
+
+def test_decode_oracle_stream_and_errors():
+    """The GPU decoder reads oracle-made streams, and rejects broken ones."""
+    for dt in DTYPES:
+        x = _field(dt, 3 * 4096 + 5, 61, 1e-3, "abs")
+        st = O.quantize("abs", x, 1e-3)
+        ref = O.dequantize(st, dt, x.size)
+        announce("decode-oracle", dt)
+        got, status = gpu_decode(st, dt, x.size)
+        assert status == 0 and first_diff(bits(got), bits(ref)) is None
+        bad = st.copy(); bad[0] ^= 0xFF
+        announce("decode-bad-magic", dt)
+        _, status = gpu_decode(bad, dt, x.size)
+        assert status == 3
+        bad = st.copy()
+        ct = (64 + 4 * x.size + 15) // 16 * 16
+        bad[ct + 8] ^= 0x01  # chunk table entry 1
+        announce("decode-bad-chunk", dt)
+        _, status = gpu_decode(bad, dt, x.size)
+        assert status == 3
+        announce("decode-truncated", dt)
+        _, status = gpu_decode(st[: st.size - 1], dt, x.size) if parse(st, dt)["hdr"]["k"] else (None, 3)
+        assert status == 3
+        # a good decode after an error reports OK again
+        got, status = gpu_decode(st, dt, x.size)
+        assert status == 0
+
+
+def test_bounds_hold_on_gpu_output():
+    """Independent of the oracle: GPU decodes satisfy the bound exactly."""
+    for dt in DTYPES:
+        for q, eb in (("abs", 1e-4), ("noa", 1e-3), ("rel", 1e-3)):
+            x = _field(dt, 2 * 4096 + 99, 71, eb, q)
+            announce("bound", q, dt)
+            st, dec = gpu_roundtrip(q, x, eb)
+            if q == "rel":
+                bad, bsp = rel_violations(x, dec, eb)
+            else:
+                from fractions import Fraction
+                bound = Fraction(eb)
+                if q == "noa":
+                    lo, hi = finite_range(x)
+                    bound *= Fraction(hi) - Fraction(lo)
+                bad, bsp = abs_violations(x, dec, bound)
+            assert bad.size == 0 and bsp.size == 0
+            assert not check_structure(parse(st, dt), x, dt)
+
+
+def test_stream_reuse_and_determinism():
+    """Same input twice (buffers and workspace reused) -> identical bytes;
+    a smaller call after a larger one is unaffected by leftovers."""
+    import torch
+    import paper_2407_15037_amd as lcq
+    x = _field(np.float32, 7 * 4096 + 3, 81, 1e-3, "abs")
+    xt = torch.from_numpy(x).cuda()
+    ws = torch.empty(lcq.workspace_bytes("noa", torch.float32, x.size), dtype=torch.uint8, device="cuda")
+    out = torch.empty(lcq.max_stream_bytes(torch.float32, x.size), dtype=torch.uint8, device="cuda")
+    nb = torch.empty(1, dtype=torch.int64, device="cuda")
+    sizes = []
+    streams = []
+    announce("reuse")
+    for xi in (xt, xt, xt[: 4096 + 1]):
+        for q in ("abs", "noa", "rel"):
+            lcq.quantize(xi, q, 1e-3, out=out[: lcq.max_stream_bytes(torch.float32, xi.numel())],
+                         nbytes=nb, ws=ws)
+            torch.cuda.synchronize()
+            s = int(nb.item())
+            sizes.append(s)
+            streams.append(out[:s].cpu().numpy().copy())
+    for i in range(3):
+        assert np.array_equal(streams[i], streams[3 + i])
+    xs = x[: 4096 + 1]
+    for i, q in enumerate(("abs", "noa", "rel")):
+        assert np.array_equal(streams[6 + i], O.quantize(q, xs, 1e-3))
