@@ -110,6 +110,13 @@ const char *lcq_status_string(lcq_status s);
  * kernel (the per-value pass), on the call's stream.  Pass nulls to clear. */
 void lcq_profile_events(hipEvent_t before, hipEvent_t after);
 
+/* Testing hook for the quantize kernel's outlier-offset scan.  A workgroup
+ * waits for the outlier counts of the tiles before it; after `polls` polls
+ * without an answer it counts the missing tile's outliers from the input
+ * itself (same result, more work).  Default 4096; 0 makes every wait fall
+ * back immediately.  Process-wide; affects launches made after the call. */
+void lcq_debug_set_lookback_spin(uint32_t polls);
+
 #ifdef __cplusplus
 }
 #endif

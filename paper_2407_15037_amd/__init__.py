@@ -10,6 +10,7 @@ import os
 
 __all__ = ["ABS", "REL", "NOA", "F32", "F64", "LCQError", "lib", "max_stream_bytes",
            "workspace_bytes", "quantize", "dequantize", "stream_status", "profile_events",
+           "set_lookback_spin",
            "SO_PATH"]
 
 HERE = os.path.dirname(os.path.abspath(__file__))
@@ -41,6 +42,8 @@ _lib.lcq_status_string.argtypes = [_i32]
 _lib.lcq_status_string.restype = ctypes.c_char_p
 _lib.lcq_profile_events.argtypes = [_vp, _vp]
 _lib.lcq_profile_events.restype = None
+_lib.lcq_debug_set_lookback_spin.argtypes = [ctypes.c_uint32]
+_lib.lcq_debug_set_lookback_spin.restype = None
 
 
 def lib():
@@ -139,6 +142,12 @@ def stream_status(ws, stream=None):
     _check(_lib.lcq_stream_status(_ptr(ws), _stream_handle(stream), ctypes.byref(err)),
            "lcq_stream_status")
     return int(err.value)
+
+
+def set_lookback_spin(polls):
+    """Testing hook: polls before the quantize look-back counts a missing
+    predecessor tile from its input (default 4096; 0 = always)."""
+    _lib.lcq_debug_set_lookback_spin(int(polls))
 
 
 def profile_events(before=None, after=None):

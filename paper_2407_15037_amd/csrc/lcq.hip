@@ -7,12 +7,13 @@
 //                  also clears the look-back state
 //   k_noa_params   NOA pass 2 (one block): reduce the block results, derive
 //                  ebR, step and 1/step on the device (no host round trip)
-//   k_quantize     one tile per workgroup: 128-bit loads, classify / bin /
+//   k_quantize     one tile per workgroup (tile = workgroup index, no
+//                  atomic counter): 128-bit loads, classify / bin /
 //                  reconstruct / verify per value (sections 2.2, 3.1-3.3),
 //                  int32 code stores, ballot + LDS block scan of the outlier
-//                  flags, single-pass decoupled look-back for the tile's
-//                  outlier offset, chunk-table entries, outlier scatter; the
-//                  last tile writes the header and the stream size
+//                  flags, single-pass decoupled look-back (bounded wait) for
+//                  the tile's outlier offset, chunk-table entries, outlier
+//                  scatter; the last tile writes the header and stream size
 //   k_dequantize   one tile per workgroup, independent tiles: 128-bit code
 //                  loads, chunk-table base + ballot rank for the outliers,
 //                  reconstruction (section 3.2 for REL), 128-bit stores
@@ -34,11 +35,9 @@ namespace {
 // ------------------------------------------------------------ workspace ---
 // [0,8)      status word of the last dequantize: (epoch << 16) | status
 // [64,128)   NOA parameters written by k_noa_params (DevParams)
-// [248,256)  tile counter of the running quantize
-// [256, ...) look-back state, one u64 per tile
+// [256, ...) look-back state, one u64 per tile (cleared before each quantize)
 // then       NOA per-block (min, max) pairs
 constexpr uint64_t kWsParams = 64;
-constexpr uint64_t kWsCounter = 248;
 constexpr uint64_t kWsState = 256;
 constexpr int kMinmaxBlocks = 2048;
 constexpr int kBlock = 256;   // threads per workgroup (4 wave64)
@@ -60,6 +59,7 @@ constexpr uint64_t kValMask = (1ull << 62) - 1;
 
 thread_local hipEvent_t g_ev_before = nullptr, g_ev_after = nullptr;
 std::atomic<uint64_t> g_epoch{0};
+std::atomic<unsigned> g_spin_limit{4096};
 
 template <typename T> struct Vec;
 template <> struct Vec<float> { using type = float4; };
@@ -78,12 +78,33 @@ __device__ __forceinline__ uint64_t wave_sum(uint64_t v) {
   return v;
 }
 
-// Exclusive outlier prefix of `tile` (> 0), by wave 0 of the workgroup.
-// Lane l inspects tile (pos - l); a window ends at the nearest tile that has
-// published its inclusive prefix.  Every predecessor obtained its tile index
-// from the same counter earlier, is resident or finished, and publishes its
-// own count before it looks back, so every wait ends.
-__device__ uint64_t look_back(uint64_t *state, uint64_t tile, int lane) {
+// Outliers among the values of tile `u`, counted by one wave from the input
+// (encode is a pure function of the value bits, so this equals what the
+// tile's own workgroup counts).
+template <typename T, int Q, uint64_t TILE>
+__device__ uint64_t wave_count_tile(const T *in, uint64_t n, uint64_t u, const FieldParams<T> &p,
+                                    int lane) {
+  uint64_t cnt = 0;
+  const uint64_t base = u * TILE;
+  for (uint64_t i = lane; i < TILE; i += 64) {
+    const uint64_t g = base + i;
+    if (g < n) cnt += (encode<T, Q>(in[g], p) == kSent);
+  }
+  return wave_sum(cnt);
+}
+
+// Exclusive outlier prefix of `tile` (> 0), computed by wave 0 of the
+// workgroup (decoupled look-back).  Lane l inspects tile (pos - l); a window
+// ends at the nearest tile that has published its inclusive prefix.  Tiles
+// are workgroup indices; the hardware dispatches workgroups in index order,
+// so a predecessor is normally resident or finished and publishes its own
+// count before it looks back.  The wait is nevertheless bounded: a
+// predecessor that has published nothing after `spin_limit` polls has its
+// count computed here from its input instead, so no order of dispatch can
+// make a workgroup wait forever.
+template <typename T, int Q, uint64_t TILE>
+__device__ uint64_t look_back(uint64_t *state, uint64_t tile, int lane, unsigned spin_limit,
+                              const T *in, uint64_t n, const FieldParams<T> &p) {
   uint64_t excl = 0;
   int64_t pos = (int64_t)tile - 1;
   while (true) {
@@ -91,10 +112,17 @@ __device__ uint64_t look_back(uint64_t *state, uint64_t tile, int lane) {
     uint64_t s = kFlagIncl;  // before tile 0: inclusive prefix 0
     if (idx >= 0) {
       s = load_state(state + idx);
-      while ((s >> 62) == 0) {
+      for (unsigned polls = 0; (s >> 62) == 0 && polls < spin_limit; polls++) {
         __builtin_amdgcn_s_sleep(1);
         s = load_state(state + idx);
       }
+    }
+    uint64_t pending = __ballot((s >> 62) == 0);
+    while (pending) {
+      const int l = __ffsll((unsigned long long)pending) - 1;
+      const uint64_t c = wave_count_tile<T, Q, TILE>(in, n, (uint64_t)(pos - l), p, lane);
+      if (lane == l) s = kFlagAgg | c;
+      pending &= pending - 1;
     }
     const uint64_t incl = __ballot((s >> 62) == 2);
     uint64_t v = s & kValMask;
@@ -126,7 +154,7 @@ struct QuantArgs {
   uint8_t *stream;
   uint64_t *stream_bytes;
   uint64_t *state;
-  unsigned int *counter;
+  unsigned spin_limit;    // look-back polls before counting a predecessor directly
   const DevParams *noa;   // NOA only: parameters computed on the device
   uint64_t ntiles;
   double eb;
@@ -147,17 +175,13 @@ __global__ __launch_bounds__(kBlock) void k_quantize(QuantArgs a) {
   constexpr int CHUNKS_PER_TILE = (int)(TILE / kChunk);
   static_assert(kChunk % SLOT == 0 && TILE % kChunk == 0, "tile must cover whole chunks");
 
-  __shared__ unsigned int s_tile;
   __shared__ unsigned int s_wtot[kSlots][NWAVE];
   __shared__ uint64_t s_prefix;
 
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = tid >> 6;
-
-  if (tid == 0) s_tile = atomicAdd(a.counter, 1u);
-  __syncthreads();
-  const uint64_t tile = s_tile;
+  const uint64_t tile = blockIdx.x;
   const uint64_t base = tile * TILE;
   const uint64_t n = a.n;
 
@@ -257,7 +281,7 @@ __global__ __launch_bounds__(kBlock) void k_quantize(QuantArgs a) {
   } else {
     if (tid == 0) store_state(a.state + tile, kFlagAgg | tile_total);
     if (wave == 0) {
-      const uint64_t excl = look_back(a.state, tile, lane);
+      const uint64_t excl = look_back<T, Q, TILE>(a.state, tile, lane, a.spin_limit, in, n, p);
       if (lane == 0) {
         store_state(a.state + tile, kFlagIncl | (excl + tile_total));
         s_prefix = excl;
@@ -539,7 +563,6 @@ __global__ __launch_bounds__(kBlock) void k_dequantize(DeqArgs a) {
   const bool tile_any = __syncthreads_or(any);
   unsigned int lane_pre[kSlots];
   uint64_t first = 0;
-  unsigned int tile_total = 0;
   if (tile_any) {
     const uint64_t lt = __lanemask_lt();
 #pragma unroll
@@ -555,17 +578,26 @@ __global__ __launch_bounds__(kBlock) void k_dequantize(DeqArgs a) {
       if (lane == 0) s_wtot[j][wave] = tot;
     }
     __syncthreads();
-    for (int j = 0; j < kSlots; j++)
-      for (int w = 0; w < NWAVE; w++) tile_total += s_wtot[j][w];
   }
-  // chunk-table consistency at both ends of the tile
+  // chunk-table consistency: every entry of this tile, and the next tile's
+  // first entry (or the outlier count after the last tile), must equal the
+  // outliers counted before it (a dequantize slot is exactly one chunk)
+  static_assert((uint64_t)kBlock * 4 == kChunk, "one dequantize slot per chunk");
   first = chunk_tab[tile * CHUNKS_PER_TILE];
-  if (tid == 0) {
-    const uint64_t next_chunk = (tile + 1) * CHUNKS_PER_TILE;
-    const uint64_t want = (next_chunk * kChunk < n) ? chunk_tab[next_chunk] : k;
-    if (first + tile_total != want || first > k)
+  if (tid <= CHUNKS_PER_TILE) {
+    const uint64_t cidx = tile * CHUNKS_PER_TILE + tid;
+    uint64_t before = first;
+    if (tile_any)
+      for (int j = 0; j < tid; j++)
+        for (int w = 0; w < NWAVE; w++) before += s_wtot[j][w];
+    if (cidx * kChunk < n) {
+      if (chunk_tab[cidx] != before) atomicMax(a.status, tag | (unsigned long long)LCQ_ERR_STREAM);
+    } else if ((cidx - 1) * kChunk < n && before != k) {
+      // first chunk past the end: the tile's total must close the count
       atomicMax(a.status, tag | (unsigned long long)LCQ_ERR_STREAM);
+    }
   }
+  if (first > k && tid == 0) atomicMax(a.status, tag | (unsigned long long)LCQ_ERR_STREAM);
 
   uint64_t slot_base = first;
 #pragma unroll
@@ -703,7 +735,7 @@ lcq_status run_quantize(double eb, const void *d_in, uint64_t n, void *d_stream,
   a.stream = static_cast<uint8_t *>(d_stream);
   a.stream_bytes = d_bytes;
   a.state = reinterpret_cast<uint64_t *>(ws + kWsState);
-  a.counter = reinterpret_cast<unsigned int *>(ws + kWsCounter);
+  a.spin_limit = g_spin_limit.load(std::memory_order_relaxed);
   a.noa = reinterpret_cast<const DevParams *>(ws + kWsParams);
   a.eb = eb;
   a.step = hp.step;
@@ -714,8 +746,8 @@ lcq_status run_quantize(double eb, const void *d_in, uint64_t n, void *d_stream,
   a.aux1 = hp.aux1;
   const uint64_t tile = quant_tile<T>();
   a.ntiles = (n + tile - 1) / tile;
-  const uint64_t clear_words = 1 + a.ntiles;  // counter + state
-  uint64_t *clear_ptr = reinterpret_cast<uint64_t *>(ws + kWsCounter);
+  const uint64_t clear_words = a.ntiles;
+  uint64_t *clear_ptr = reinterpret_cast<uint64_t *>(ws + kWsState);
 
   if (Q == kNOA) {
     uint64_t poff = ((kWsState + 8 * a.ntiles + 255) & ~255ull);
@@ -831,6 +863,8 @@ const char *lcq_status_string(lcq_status s) {
   }
   return "unknown status";
 }
+
+void lcq_debug_set_lookback_spin(uint32_t polls) { g_spin_limit.store(polls); }
 
 void lcq_profile_events(hipEvent_t before, hipEvent_t after) {
   g_ev_before = before;

@@ -174,3 +174,18 @@ def test_stream_reuse_and_determinism():
     xs = x[: 4096 + 1]
     for i, q in enumerate(("abs", "noa", "rel")):
         assert np.array_equal(streams[6 + i], O.quantize(q, xs, 1e-3))
+
+
+def test_lookback_fallback_same_bytes():
+    """With the look-back wait forced to zero polls, every workgroup counts
+    unfinished predecessor tiles from their input itself; the stream must not
+    change."""
+    import paper_2407_15037_amd as lcq
+    try:
+        lcq.set_lookback_spin(0)
+        for dt in DTYPES:
+            for q, eb in (("abs", 1e-3), ("noa", 1e-3), ("rel", 1e-2)):
+                x = _field(dt, 9 * 4096 + 1234, 91, eb, q)
+                _parity(q, x, eb, "spin0")
+    finally:
+        lcq.set_lookback_spin(4096)
