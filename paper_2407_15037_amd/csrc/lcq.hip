@@ -760,7 +760,7 @@ lcq_status run_quantize(double eb, const void *d_in, uint64_t n, void *d_stream,
     hipLaunchKernelGGL(k_noa_params<T>, dim3(1), dim3(kBlock), 0, s, partials, nb,
                        from_bits((typename FT<T>::U)hp.eb_down),
                        reinterpret_cast<DevParams *>(ws + kWsParams));
-  } else {
+  } else if (clear_words) {
     const int nb = (int)std::min<uint64_t>((clear_words + kBlock - 1) / kBlock, 1024);
     hipLaunchKernelGGL(k_clear, dim3(nb), dim3(kBlock), 0, s, clear_ptr, clear_words);
   }
