@@ -65,6 +65,8 @@ def main():
     ap.add_argument("--eb", type=float, default=1e-3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-verify", action="store_true")
+    ap.add_argument("--no-tune", action="store_true",
+                    help="skip the launch-shape autotuner (use variant 0)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build measures one GPU; the quantizer path has no "
@@ -78,6 +80,10 @@ def main():
 
     dev = torch.device("cuda:0")
     eb = args.eb
+    tuned = None
+    if not args.no_tune:
+        from paper_2407_15037_amd import autotune
+        tuned = autotune.tune(log=log)
     x, xr = make_inputs(args.grid, eb)
     n = x.size
     s = 4
@@ -158,6 +164,7 @@ def main():
                     "alg_GBs": round(v["gbs_hbm"], 1)} for k, v in sorted(kern.items())},
         "outlier_fraction": {q: ks[q] / n for q in order_q},
         "stream_bytes": sizes,
+        "autotune": tuned,
         "roofline": {"kernel": dom_name, "bound": "hbm", "achieved": round(dom["gbs_hbm"], 1),
                      "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(dom["gbs_hbm"] / HBM_PEAK_GBS, 4), "traffic": None,

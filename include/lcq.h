@@ -110,6 +110,16 @@ const char *lcq_status_string(lcq_status s);
  * kernel (the per-value pass), on the call's stream.  Pass nulls to clear. */
 void lcq_profile_events(hipEvent_t before, hipEvent_t after);
 
+/* Launch-shape tuning.  Each per-value kernel comes in lcq_tune_variants()
+ * shapes (loads in flight per thread x rounds per tile); all produce the
+ * same bytes.  op 0 = quantize, 1 = dequantize.  Process-wide; the tuner
+ * (paper_2407_15037_amd/autotune.py) measures them and sets the fastest.
+ * lcq_tune_set returns LCQ_ERR_ARG for a bad op, dtype or variant;
+ * lcq_tune_get returns -1 for a bad op or dtype. */
+int32_t lcq_tune_variants(void);
+lcq_status lcq_tune_set(int32_t op, lcq_dtype t, int32_t variant);
+int32_t lcq_tune_get(int32_t op, lcq_dtype t);
+
 /* Testing hook for the quantize kernel's outlier-offset scan.  A workgroup
  * waits for the outlier counts of the tiles before it; after `polls` polls
  * without an answer it counts the missing tile's outliers from the input

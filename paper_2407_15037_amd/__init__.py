@@ -10,7 +10,7 @@ import os
 
 __all__ = ["ABS", "REL", "NOA", "F32", "F64", "LCQError", "lib", "max_stream_bytes",
            "workspace_bytes", "quantize", "dequantize", "stream_status", "profile_events",
-           "set_lookback_spin",
+           "set_lookback_spin", "tune_variants", "tune_set", "tune_get",
            "SO_PATH"]
 
 HERE = os.path.dirname(os.path.abspath(__file__))
@@ -20,6 +20,7 @@ F32, F64 = 0, 1
 ABS, REL, NOA = 0, 1, 2
 OK, ERR_ARG, ERR_CAPACITY, ERR_STREAM, ERR_HIP = 0, 1, 2, 3, 4
 _QNAMES = {"abs": ABS, "rel": REL, "noa": NOA}
+_OPS = {"quantize": 0, "dequantize": 1}
 
 if not os.path.exists(SO_PATH):
     raise ImportError(f"{SO_PATH} is missing: build it with "
@@ -44,6 +45,12 @@ _lib.lcq_profile_events.argtypes = [_vp, _vp]
 _lib.lcq_profile_events.restype = None
 _lib.lcq_debug_set_lookback_spin.argtypes = [ctypes.c_uint32]
 _lib.lcq_debug_set_lookback_spin.restype = None
+_lib.lcq_tune_variants.argtypes = []
+_lib.lcq_tune_variants.restype = ctypes.c_int32
+_lib.lcq_tune_set.argtypes = [ctypes.c_int32, _i32, ctypes.c_int32]
+_lib.lcq_tune_set.restype = _i32
+_lib.lcq_tune_get.argtypes = [ctypes.c_int32, _i32]
+_lib.lcq_tune_get.restype = ctypes.c_int32
 
 
 def lib():
@@ -142,6 +149,21 @@ def stream_status(ws, stream=None):
     _check(_lib.lcq_stream_status(_ptr(ws), _stream_handle(stream), ctypes.byref(err)),
            "lcq_stream_status")
     return int(err.value)
+
+
+def tune_variants():
+    """Number of launch-shape variants of each per-value kernel."""
+    return int(_lib.lcq_tune_variants())
+
+
+def tune_set(op, dtype, variant):
+    """Select launch-shape `variant` for op 'quantize' / 'dequantize' and a
+    torch dtype (process-wide; every variant gives the same bytes)."""
+    _check(_lib.lcq_tune_set(_OPS[op], _dtype_code(dtype), int(variant)), "lcq_tune_set")
+
+
+def tune_get(op, dtype):
+    return int(_lib.lcq_tune_get(_OPS[op], _dtype_code(dtype)))
 
 
 def set_lookback_spin(polls):

@@ -1,0 +1,539 @@
+// lcq_tile.hpp -- workgroup-level building blocks shared by the plain and the
+// batched kernels: one quantize tile (with its outlier-offset look-back), one
+// dequantize tile, one NOA range slice, and the NOA parameter derivation.
+//
+// A tile is ROUNDS x SLOTS "slots"; a slot is one 128-bit load per thread of
+// a 256-thread workgroup (1024 float32 / 512 float64 values, 1024 codes),
+// laid out so a wavefront reads 1 KiB contiguous bytes per load.  Input
+// order inside a tile is slot-major, then thread, then element, which is
+// the order the outlier ranks follow.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "lcq_math.hpp"
+
+#pragma clang fp contract(off)
+
+namespace lcq {
+
+constexpr int kBlock = 256;  // threads per workgroup (4 wave64)
+constexpr int kWaves = kBlock / 64;
+
+// look-back state word: 2-bit flag | 62-bit count
+constexpr uint64_t kFlagAgg = 1ull << 62;   // the tile's own outlier count
+constexpr uint64_t kFlagIncl = 2ull << 62;  // outliers up to and including the tile
+constexpr uint64_t kValMask = (1ull << 62) - 1;
+
+template <typename T> struct Vec;
+template <> struct Vec<float> { using type = float4; };
+template <> struct Vec<double> { using type = double2; };
+template <typename T> constexpr int vec_elems() { return 16 / (int)sizeof(T); }
+
+// Field parameters produced on the device (NOA), as raw bits of the type.
+struct DevParams {
+  uint64_t step, inv, bound, lo, hi;
+  int32_t lossless_all, ready;
+};
+
+__device__ __forceinline__ uint64_t load_state(const uint64_t *p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void store_state(uint64_t *p, uint64_t v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ uint64_t wave_sum(uint64_t v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+template <typename T> __device__ __forceinline__ FieldParams<T> params_from(const DevParams &d) {
+  using U = typename FT<T>::U;
+  FieldParams<T> p;
+  p.step = from_bits((U)d.step);
+  p.inv = from_bits((U)d.inv);
+  p.bound = from_bits((U)d.bound);
+  p.low = (T)0;
+  p.lossless_all = d.lossless_all;
+  return p;
+}
+
+// Everything a workgroup needs to quantize one tile of one field.
+template <typename T> struct QField {
+  const T *in;
+  uint64_t n;
+  uint8_t *stream;
+  uint64_t *stream_bytes;  // written by the field's last tile
+  uint64_t *state;         // one look-back word per tile of this field
+  uint64_t ntiles;
+  FieldParams<T> p;
+  uint64_t hdr[8];         // header words; word 2 (outlier count) is filled in
+};
+
+template <typename T, int SLOTS, int ROUNDS> struct QuantShape {
+  static constexpr int W = vec_elems<T>();
+  static constexpr int NSLOT = SLOTS * ROUNDS;
+  static constexpr uint64_t SLOT = (uint64_t)kBlock * W;  // values per slot
+  static constexpr uint64_t TILE = SLOT * NSLOT;
+  static constexpr int SLOTS_PER_CHUNK = (int)(kChunk / SLOT);
+  static constexpr int CHUNKS = (int)(TILE / kChunk);
+  static_assert(kChunk % SLOT == 0, "a chunk is a whole number of slots");
+  static_assert(TILE % kChunk == 0, "a tile is a whole number of chunks");
+  static_assert(NSLOT * W <= 64, "outlier flags of a thread fit 64 bits");
+  static_assert(NSLOT <= 64, "slot totals are scanned by one wavefront");
+};
+
+// Outliers among the values of tile u, counted by one wavefront straight
+// from the input (encode is a pure function of the value bits, so this is
+// what the tile's own workgroup counts).
+template <typename T, int Q>
+__device__ uint64_t wave_count_tile(const T *in, uint64_t n, uint64_t u, uint64_t tile_len,
+                                    const FieldParams<T> &p, int lane) {
+  uint64_t cnt = 0;
+  const uint64_t base = u * tile_len;
+  for (uint64_t i = lane; i < tile_len; i += 64) {
+    const uint64_t g = base + i;
+    if (g < n) cnt += (encode<T, Q>(in[g], p) == kSent);
+  }
+  return wave_sum(cnt);
+}
+
+// Exclusive outlier prefix of `tile` (> 0) by one wavefront: decoupled
+// look-back.  Each round issues kLookDepth loads per lane, so one memory
+// round trip inspects the kLookDepth * 64 nearest unvisited predecessors
+// (batch j, lane l: tile pos - 64 j - l); the batches are then taken nearest
+// first, and the look-back ends at the nearest tile that has published its
+// inclusive prefix.  A tile that has published nothing after `spin_limit`
+// polls has its count computed here from its input instead, so the wait
+// ends whatever the dispatch order.
+constexpr int kLookDepth = 8;
+
+template <typename T, int Q>
+__device__ uint64_t look_back(uint64_t *state, uint64_t tile, uint64_t tile_len, int lane,
+                              unsigned spin_limit, const T *in, uint64_t n,
+                              const FieldParams<T> &p) {
+  uint64_t excl = 0;
+  int64_t pos = (int64_t)tile - 1;
+  while (true) {
+    uint64_t s[kLookDepth];
+#pragma unroll
+    for (int j = 0; j < kLookDepth; j++) {
+      const int64_t idx = pos - 64 * j - lane;
+      s[j] = idx >= 0 ? load_state(state + idx) : kFlagIncl;  // before tile 0: prefix 0
+    }
+#pragma unroll
+    for (int j = 0; j < kLookDepth; j++) {
+      const int64_t idx = pos - 64 * j - lane;
+      uint64_t sj = s[j];
+      for (unsigned polls = 0; (sj >> 62) == 0 && polls < spin_limit; polls++) {
+        __builtin_amdgcn_s_sleep(1);
+        sj = load_state(state + idx);
+      }
+      uint64_t pending = __ballot((sj >> 62) == 0);
+      while (pending) {
+        const int l = __ffsll((unsigned long long)pending) - 1;
+        const uint64_t c =
+            wave_count_tile<T, Q>(in, n, (uint64_t)(pos - 64 * j - l), tile_len, p, lane);
+        if (lane == l) sj = kFlagAgg | c;
+        pending &= pending - 1;
+      }
+      const uint64_t incl = __ballot((sj >> 62) == 2);
+      uint64_t v = sj & kValMask;
+      if (incl) {
+        const int first = __ffsll((unsigned long long)incl) - 1;
+        if (lane > first) v = 0;
+        return excl + wave_sum(v);
+      }
+      excl += wave_sum(v);
+    }
+    pos -= 64 * kLookDepth;
+  }
+}
+
+// Exclusive scan over `count` (<= 64) per-slot totals by wavefront 0;
+// writes spre[0..count] (spre[count] = total) and returns the total to
+// every lane.
+__device__ __forceinline__ unsigned wave_scan_slots(const unsigned (*wtot)[kWaves], int count,
+                                                    unsigned *spre, int lane) {
+  unsigned v = 0;
+  if (lane < count)
+    for (int w = 0; w < kWaves; w++) v += wtot[lane][w];
+  unsigned incl = v;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const unsigned t = __shfl_up(incl, o, 64);
+    if (lane >= o) incl += t;
+  }
+  if (lane < count) spre[lane] = incl - v;
+  if (lane == count - 1) spre[count] = incl;
+  return __shfl(incl, count - 1, 64);
+}
+
+// Quantize one tile of a field: per value classify / bin / reconstruct /
+// verify (sections 2.2, 3.1-3.3), code stores, in-tile outlier ranks, the
+// tile's outlier offset by look-back, chunk-table entries and the outliers'
+// raw bits.  The field's last tile also writes the header and the size.
+template <typename T, int Q, int SLOTS, int ROUNDS>
+__device__ void quant_tile(const QField<T> &f, uint64_t tile, unsigned spin_limit) {
+  using F = FT<T>;
+  using U = typename F::U;
+  using V = typename Vec<T>::type;
+  using S = QuantShape<T, SLOTS, ROUNDS>;
+  constexpr int W = S::W;
+  constexpr int NSLOT = S::NSLOT;
+
+  __shared__ unsigned s_wtot[NSLOT][kWaves];
+  __shared__ unsigned s_spre[NSLOT + 1];
+  __shared__ uint64_t s_prefix;
+
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const uint64_t n = f.n;
+  const uint64_t base = tile * S::TILE;
+  int32_t *codes = reinterpret_cast<int32_t *>(f.stream + 64);
+
+  uint64_t omask = 0;
+#pragma unroll
+  for (int r = 0; r < ROUNDS; r++) {
+    V v[SLOTS];
+#pragma unroll
+    for (int j = 0; j < SLOTS; j++) {
+      const uint64_t i0 = base + ((uint64_t)(r * SLOTS + j) * kBlock + tid) * W;
+      if (i0 + W <= n) {
+        v[j] = *reinterpret_cast<const V *>(f.in + i0);
+      } else {
+        T tmp[W];
+#pragma unroll
+        for (int e = 0; e < W; e++) tmp[e] = (i0 + e < n) ? f.in[i0 + e] : (T)0;
+        __builtin_memcpy(&v[j], tmp, sizeof(V));
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < SLOTS; j++) {
+      const int s = r * SLOTS + j;
+      const uint64_t i0 = base + ((uint64_t)s * kBlock + tid) * W;
+      T x[W];
+      __builtin_memcpy(x, &v[j], sizeof(V));
+      int32_t c[W];
+#pragma unroll
+      for (int e = 0; e < W; e++) {
+        c[e] = encode<T, Q>(x[e], f.p);
+        if (c[e] == kSent && i0 + e < n) omask |= 1ull << (s * W + e);
+      }
+      if (i0 + W <= n) {
+        if constexpr (W == 4) {
+          *reinterpret_cast<int4 *>(codes + i0) = make_int4(c[0], c[1], c[2], c[3]);
+        } else {
+          *reinterpret_cast<int2 *>(codes + i0) = make_int2(c[0], c[1]);
+        }
+      } else {
+#pragma unroll
+        for (int e = 0; e < W; e++)
+          if (i0 + e < n) codes[i0 + e] = c[e];
+      }
+    }
+  }
+
+  // ---- in-tile ranks: wave totals per slot, then a scan over slots
+  const bool any = __syncthreads_or(omask != 0);
+  if (any) {
+#pragma unroll
+    for (int s = 0; s < NSLOT; s++) {
+      unsigned tot = 0;
+#pragma unroll
+      for (int e = 0; e < W; e++) tot += __popcll(__ballot((omask >> (s * W + e)) & 1u));
+      if (lane == 0) s_wtot[s][wave] = tot;
+    }
+    __syncthreads();
+  }
+
+  // ---- tile offset: wave 0 scans the slot totals, publishes, looks back
+  if (wave == 0) {
+    uint64_t tile_total = 0;
+    if (any) tile_total = wave_scan_slots(s_wtot, NSLOT, s_spre, lane);
+    if (tile == 0) {
+      if (lane == 0) {
+        store_state(f.state, kFlagIncl | tile_total);
+        s_prefix = 0;
+      }
+    } else {
+      if (lane == 0) store_state(f.state + tile, kFlagAgg | tile_total);
+      const uint64_t excl = look_back<T, Q>(f.state, tile, S::TILE, lane, spin_limit, f.in, n, f.p);
+      if (lane == 0) {
+        store_state(f.state + tile, kFlagIncl | (excl + tile_total));
+        s_prefix = excl;
+      }
+    }
+    if (tile == f.ntiles - 1 && lane == 0) {
+      // header, padding and size (the last tile owns the end of the stream)
+      const uint64_t k = s_prefix + tile_total;
+      const uint64_t ct = chunk_table_offset(n);
+      const uint64_t ce = ct + 8 * n_chunks(n);
+      const uint64_t oo = outlier_offset(n);
+      for (uint64_t b = 64 + 4 * n; b < ct; b++) f.stream[b] = 0;
+      for (uint64_t b = ce; b < oo; b++) f.stream[b] = 0;
+      uint64_t *hd = reinterpret_cast<uint64_t *>(f.stream);
+#pragma unroll
+      for (int i = 0; i < 8; i++) hd[i] = (i == 2) ? k : f.hdr[i];
+      *f.stream_bytes = oo + k * sizeof(T);
+    }
+  }
+  __syncthreads();
+  const uint64_t prefix = s_prefix;
+
+  // ---- chunk table: outliers before each chunk of the tile
+  uint64_t *chunk_tab = reinterpret_cast<uint64_t *>(f.stream + chunk_table_offset(n));
+  if (tid < S::CHUNKS) {
+    const uint64_t cidx = tile * S::CHUNKS + tid;
+    if (cidx * kChunk < n) chunk_tab[cidx] = prefix + (any ? s_spre[tid * S::SLOTS_PER_CHUNK] : 0u);
+  }
+
+  // ---- outliers: raw bits (re-read from the input), input order
+  if (any) {
+    U *outl = reinterpret_cast<U *>(f.stream + outlier_offset(n));
+    const U *inb = reinterpret_cast<const U *>(f.in);
+    const uint64_t lt = __lanemask_lt();
+#pragma unroll
+    for (int s = 0; s < NSLOT; s++) {
+      if (s_spre[s + 1] == s_spre[s]) continue;  // no outlier in this slot (uniform)
+      unsigned pre = 0;
+#pragma unroll
+      for (int e = 0; e < W; e++) pre += __popcll(__ballot((omask >> (s * W + e)) & 1u) & lt);
+      const unsigned m = (unsigned)(omask >> (s * W)) & ((1u << W) - 1);
+      if (m) {
+        uint64_t off = prefix + s_spre[s] + pre;
+        for (int w = 0; w < wave; w++) off += s_wtot[s][w];
+        const uint64_t i0 = base + ((uint64_t)s * kBlock + tid) * W;
+#pragma unroll
+        for (int e = 0; e < W; e++)
+          if ((m >> e) & 1u) outl[off++] = inb[i0 + e];
+      }
+    }
+  }
+}
+
+// Everything a workgroup needs to decode one tile of one stream.
+template <typename T> struct DField {
+  const uint8_t *stream;
+  uint64_t n;
+  uint64_t k;       // outlier count from the header
+  T step;
+  bool rel;
+  T *out;
+  unsigned long long *status;
+  unsigned long long tag;  // (epoch << 16)
+};
+
+template <int SLOTS, int ROUNDS> struct DeqShape {
+  static constexpr int NSLOT = SLOTS * ROUNDS;
+  static constexpr uint64_t TILE = (uint64_t)kBlock * 4 * NSLOT;  // codes
+  static constexpr int CHUNKS = NSLOT;  // one slot of 1024 codes = one chunk
+  static_assert((uint64_t)kBlock * 4 == kChunk, "a dequantize slot is one chunk");
+  static_assert(NSLOT * 4 <= 64, "outlier flags of a thread fit 64 bits");
+};
+
+// Decode one tile: 128-bit code loads, reconstruction, 128-bit stores; the
+// outliers' ranks come from the chunk table plus in-tile ballots and their
+// bits are gathered from the stream.  Every chunk-table entry the tile
+// covers (and the next one) is checked against the counted sentinels.
+template <typename T, int SLOTS, int ROUNDS>
+__device__ void dequant_tile(const DField<T> &f, uint64_t tile) {
+  using U = typename FT<T>::U;
+  using S = DeqShape<SLOTS, ROUNDS>;
+  constexpr int NSLOT = S::NSLOT;
+  __shared__ unsigned s_wtot[NSLOT][kWaves];
+  __shared__ unsigned s_spre[NSLOT + 1];
+
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const uint64_t n = f.n;
+  const uint64_t base = tile * S::TILE;
+  const int32_t *codes = reinterpret_cast<const int32_t *>(f.stream + 64);
+  const uint64_t *chunk_tab = reinterpret_cast<const uint64_t *>(f.stream + chunk_table_offset(n));
+  const U *outl = reinterpret_cast<const U *>(f.stream + outlier_offset(n));
+
+  uint64_t omask = 0;
+#pragma unroll
+  for (int r = 0; r < ROUNDS; r++) {
+    int4 c[SLOTS];
+#pragma unroll
+    for (int j = 0; j < SLOTS; j++) {
+      const uint64_t i0 = base + ((uint64_t)(r * SLOTS + j) * kBlock + tid) * 4;
+      if (i0 + 4 <= n) {
+        c[j] = *reinterpret_cast<const int4 *>(codes + i0);
+      } else {
+        int t[4];
+#pragma unroll
+        for (int e = 0; e < 4; e++) t[e] = (i0 + e < n) ? codes[i0 + e] : 0;
+        c[j] = make_int4(t[0], t[1], t[2], t[3]);
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < SLOTS; j++) {
+      const int s = r * SLOTS + j;
+      const uint64_t i0 = base + ((uint64_t)s * kBlock + tid) * 4;
+      const int32_t cc[4] = {c[j].x, c[j].y, c[j].z, c[j].w};
+      T y[4];
+#pragma unroll
+      for (int e = 0; e < 4; e++) {
+        // outliers get their bits after the ranks are known; 0 until then
+        const bool sent = cc[e] == kSent;
+        y[e] = sent ? (T)0 : decode<T>(cc[e], f.step, f.rel);
+        if (sent && i0 + e < n) omask |= 1ull << (s * 4 + e);
+      }
+      if (i0 + 4 <= n) {
+        if constexpr (sizeof(T) == 4) {
+          float4 o;
+          __builtin_memcpy(&o, y, 16);
+          *reinterpret_cast<float4 *>(f.out + i0) = o;
+        } else {
+          double2 o0, o1;
+          __builtin_memcpy(&o0, y, 16);
+          __builtin_memcpy(&o1, y + 2, 16);
+          *reinterpret_cast<double2 *>(f.out + i0) = o0;
+          *reinterpret_cast<double2 *>(f.out + i0 + 2) = o1;
+        }
+      } else {
+#pragma unroll
+        for (int e = 0; e < 4; e++)
+          if (i0 + e < n) f.out[i0 + e] = y[e];
+      }
+    }
+  }
+
+  const bool any = __syncthreads_or(omask != 0);
+  if (any) {
+#pragma unroll
+    for (int s = 0; s < NSLOT; s++) {
+      unsigned tot = 0;
+#pragma unroll
+      for (int e = 0; e < 4; e++) tot += __popcll(__ballot((omask >> (s * 4 + e)) & 1u));
+      if (lane == 0) s_wtot[s][wave] = tot;
+    }
+    __syncthreads();
+    if (wave == 0) wave_scan_slots(s_wtot, NSLOT, s_spre, lane);
+    __syncthreads();
+  }
+
+  // chunk-table consistency: entries of this tile and the one after it
+  const uint64_t first = chunk_tab[tile * S::CHUNKS];
+  if (tid <= S::CHUNKS) {
+    const uint64_t cidx = tile * S::CHUNKS + tid;
+    const uint64_t before = first + (any ? s_spre[tid] : 0u);
+    bool bad = false;
+    if (cidx * kChunk < n) bad = chunk_tab[cidx] != before;
+    else if ((cidx - 1) * kChunk < n) bad = before != f.k;  // the count closes at the end
+    if (bad) atomicMax(f.status, f.tag | (unsigned long long)LCQ_ERR_STREAM);
+  }
+  if (tid == 0 && first > f.k) atomicMax(f.status, f.tag | (unsigned long long)LCQ_ERR_STREAM);
+
+  if (any) {
+    const uint64_t lt = __lanemask_lt();
+#pragma unroll
+    for (int s = 0; s < NSLOT; s++) {
+      if (s_spre[s + 1] == s_spre[s]) continue;
+      unsigned pre = 0;
+#pragma unroll
+      for (int e = 0; e < 4; e++) pre += __popcll(__ballot((omask >> (s * 4 + e)) & 1u) & lt);
+      const unsigned m = (unsigned)(omask >> (s * 4)) & 0xFu;
+      if (m) {
+        uint64_t off = first + s_spre[s] + pre;
+        for (int w = 0; w < wave; w++) off += s_wtot[s][w];
+        const uint64_t i0 = base + ((uint64_t)s * kBlock + tid) * 4;
+#pragma unroll
+        for (int e = 0; e < 4; e++) {
+          if ((m >> e) & 1u) {
+            // rank checked against the outlier count: never read past it
+            f.out[i0 + e] = (off < f.k) ? from_bits(outl[off]) : (T)0;
+            off++;
+          }
+        }
+      }
+    }
+  }
+}
+
+// Finite min / max of in[begin, end) by one workgroup (-0 counts as +0);
+// the result is valid in thread 0.
+template <typename T>
+__device__ void block_minmax(const T *in, uint64_t begin, uint64_t end, T &lo, T &hi) {
+  using F = FT<T>;
+  using V = typename Vec<T>::type;
+  constexpr int W = vec_elems<T>();
+  __shared__ T s_lo[kWaves], s_hi[kWaves];
+  lo = (T)INFINITY;
+  hi = (T)-INFINITY;
+  auto take = [&](T x) {
+    const bool fin = ((to_bits(x) >> F::kMant) & F::kExpMask) != F::kExpMask;
+    const T y = (x == (T)0) ? (T)0 : x;
+    lo = fin ? fmin(lo, y) : lo;
+    hi = fin ? fmax(hi, y) : hi;
+  };
+  // begin is a multiple of W (slices are whole vectors); the tail is scalar
+  const uint64_t vb = begin / W, ve = end / W;
+  const V *vin = reinterpret_cast<const V *>(in);
+  for (uint64_t i = vb + threadIdx.x; i < ve; i += kBlock) {
+    V v = vin[i];
+    T x[W];
+    __builtin_memcpy(x, &v, sizeof(V));
+#pragma unroll
+    for (int e = 0; e < W; e++) take(x[e]);
+  }
+  for (uint64_t i = ve * W + threadIdx.x; i < end; i += kBlock) take(in[i]);
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    lo = fmin(lo, __shfl_xor(lo, o, 64));
+    hi = fmax(hi, __shfl_xor(hi, o, 64));
+  }
+  const int wave = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) {
+    s_lo[wave] = lo;
+    s_hi[wave] = hi;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0)
+    for (int w = 1; w < kWaves; w++) {
+      lo = fmin(lo, s_lo[w]);
+      hi = fmax(hi, s_hi[w]);
+    }
+  __syncthreads();
+}
+
+// NOA parameters from the finite range (section 2.1.3): R = hi - lo
+// (overflow clamped to the largest finite value), then ebR = RD(eb) * R with
+// each rounded step followed by one step toward zero, so ebR <= eb * R
+// exactly; no usable range -> every value lossless.
+template <typename T> __device__ DevParams noa_params(T lo, T hi, T eb_down) {
+  using U = typename FT<T>::U;
+  const T tmax = from_bits((U)(((U)FT<T>::kExpMask << FT<T>::kMant) - 1));
+  T r = hi - lo;
+  if (r == (T)INFINITY) r = tmax;
+  if (r > (T)0) r = step_down(r);
+  const T b = eb_down * r;
+  T ebr = b;
+  if (b > (T)0) ebr = step_down(b);
+  DevParams d;
+  d.lo = to_bits(lo);
+  d.hi = to_bits(hi);
+  d.ready = 0;
+  if (ebr > (T)0) {
+    const T step = ebr + ebr;
+    d.bound = to_bits(ebr);
+    d.step = to_bits(step);
+    d.inv = to_bits((T)1 / step);
+    d.lossless_all = 0;
+  } else {
+    d.bound = 0;
+    d.step = 0;
+    d.inv = 0;
+    d.lossless_all = 1;
+  }
+  return d;
+}
+
+// Header word 0: magic, version 1, dtype, quantizer, log2(chunk).
+__host__ __device__ inline uint64_t header_word0(int dtype, int q) {
+  return (uint64_t)kMagic | (1ull << 32) | ((uint64_t)dtype << 40) | ((uint64_t)q << 48) |
+         ((uint64_t)kLog2Chunk << 56);
+}
+
+}  // namespace lcq

@@ -189,3 +189,22 @@ def test_lookback_fallback_same_bytes():
                 _parity(q, x, eb, "spin0")
     finally:
         lcq.set_lookback_spin(4096)
+
+
+def test_every_launch_variant_same_bytes():
+    """All launch-shape variants (tile sizes, loads in flight) produce the
+    oracle's bytes, including ragged tails and multi-tile look-backs."""
+    import torch
+    import paper_2407_15037_amd as lcq
+    try:
+        for v in range(lcq.tune_variants()):
+            for dt, tdt in ((np.float32, torch.float32), (np.float64, torch.float64)):
+                lcq.tune_set("quantize", tdt, v)
+                lcq.tune_set("dequantize", tdt, v)
+                for q, eb in (("abs", 1e-3), ("noa", 1e-4), ("rel", 1e-3)):
+                    x = _field(dt, 11 * 4096 + 2345, 101 + v, eb, q)
+                    _parity(q, x, eb, f"variant {v}")
+    finally:
+        for tdt in (torch.float32, torch.float64):
+            lcq.tune_set("quantize", tdt, 0)
+            lcq.tune_set("dequantize", tdt, 0)
