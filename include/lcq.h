@@ -110,6 +110,53 @@ const char *lcq_status_string(lcq_status s);
  * kernel (the per-value pass), on the call's stream.  Pass nulls to clear. */
 void lcq_profile_events(hipEvent_t before, hipEvent_t after);
 
+/* ---------------------------------------------------------------- batch --
+ * Many fields of uneven size, mixed dtype, quantizer and bound, quantized or
+ * dequantized by one graph launch.  Each field's stream and decode are
+ * byte-identical to what lcq_quantize / lcq_dequantize give for it alone.
+ */
+typedef struct {
+  lcq_quantizer q;
+  lcq_dtype t;
+  double eb;                 /* as for lcq_quantize                          */
+  const void *d_in;          /* quantize input, n values (16-byte aligned)    */
+  uint64_t n;
+  void *d_stream;            /* quantize output / dequantize input            */
+  uint64_t stream_cap;       /* >= lcq_max_stream_bytes(t, n)                 */
+  uint64_t *d_stream_bytes;  /* receives the stream size (device u64)         */
+  void *d_out;               /* dequantize output, n values (may be null if   */
+                             /* the plan is only used to quantize)            */
+} lcq_field;
+
+typedef struct lcq_batch_plan lcq_batch_plan;
+
+/* Number of batch tile shapes the tuner may choose with "batch=<k>". */
+int32_t lcq_batch_variants(void);
+
+/* Device workspace a plan over these fields needs (0 for bad arguments).
+ * `tune` is null or a string containing "batch=<k>" (k < lcq_batch_variants). */
+uint64_t lcq_batch_workspace_bytes(const lcq_field *f, uint32_t nf, const char *tune);
+
+/* Validates every field like lcq_quantize does, derives the per-field
+ * parameters, uploads field descriptors and work-item tables into d_ws (the
+ * plan's workspace; it must stay alive and unused by others until the plan
+ * is destroyed), and captures the quantize and dequantize launches into HIP
+ * graphs.  Synchronises `stream`.  The caller keeps every field buffer alive
+ * while the plan is used.  On success *out receives the plan. */
+lcq_status lcq_batch_plan_create(const lcq_field *f, uint32_t nf, const char *tune,
+                                 void *d_ws, uint64_t ws_bytes, hipStream_t stream,
+                                 lcq_batch_plan **out);
+
+/* Quantize / dequantize every field of the plan: one hipGraphLaunch on s. */
+lcq_status lcq_batch_quantize(lcq_batch_plan *p, hipStream_t s);
+lcq_status lcq_batch_dequantize(lcq_batch_plan *p, hipStream_t s);
+
+/* Synchronises s; *h_first_bad receives the index of the first field whose
+ * last batch dequantize found its stream inconsistent, or -1. */
+lcq_status lcq_batch_status(lcq_batch_plan *p, hipStream_t s, int64_t *h_first_bad);
+
+void lcq_batch_plan_destroy(lcq_batch_plan *p);
+
 /* Launch-shape tuning.  Each per-value kernel comes in lcq_tune_variants()
  * shapes (loads in flight per thread x rounds per tile); all produce the
  * same bytes.  op 0 = quantize, 1 = dequantize.  Process-wide; the tuner

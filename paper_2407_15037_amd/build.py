@@ -10,7 +10,7 @@ import subprocess
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 SO = os.path.join(HERE, "liblcq.so")
-SRC = os.path.join(HERE, "csrc", "lcq.hip")
+SRCS = [os.path.join(HERE, "csrc", f) for f in ("lcq.hip", "lcq_batch.hip")]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [
@@ -23,7 +23,7 @@ FLAGS = [
 
 def build(out=SO, extra=(), quiet=True):
     cmd = [HIPCC, *FLAGS, *extra, "-I", os.path.join(ROOT, "include"),
-           "-I", os.path.join(HERE, "csrc"), SRC, "-o", out + ".tmp"]
+           "-I", os.path.join(HERE, "csrc"), *SRCS, "-o", out + ".tmp"]
     res = subprocess.run(cmd, capture_output=True, text=True)
     if res.returncode != 0:
         raise RuntimeError("hipcc failed:\n" + " ".join(cmd) + "\n" + res.stderr)
@@ -33,11 +33,11 @@ def build(out=SO, extra=(), quiet=True):
     return out
 
 
-def asm(out_path, extra=()):
-    """Device assembly of the library (for instruction checks)."""
+def asm(out_path, extra=(), src=None):
+    """Device assembly of one source of the library (for instruction checks)."""
     cmd = [HIPCC, *[f for f in FLAGS if f not in ("-shared", "-fPIC")], *extra,
            "--cuda-device-only", "-S", "-I", os.path.join(ROOT, "include"),
-           "-I", os.path.join(HERE, "csrc"), SRC, "-o", out_path]
+           "-I", os.path.join(HERE, "csrc"), src or SRCS[0], "-o", out_path]
     subprocess.run(cmd, check=True, capture_output=True, text=True)
     return out_path
 

@@ -1,0 +1,564 @@
+// lcq_batch.hip -- batched quantize / dequantize of many fields of uneven
+// size, mixed dtype, quantizer and bound in one graph launch.
+//
+// Quantize: one persistent kernel (grid = resident workgroups) pulls work
+// items from a device-side queue with an atomic head.  The queue holds, in
+// order: the NOA range slices of every NOA field (phase A), then every
+// quantize tile of every field (phase B), each field's tiles in increasing
+// order.  A phase-A item reduces its slice's finite min / max; the field's
+// last slice to finish derives the field's parameters on the device and
+// raises the field's ready flag.  A phase-B item of a NOA field waits for
+// that flag (all phase-A items were taken from the queue earlier and never
+// wait, so the wait ends), then runs the same quant_tile as the plain path;
+// the outlier-offset look-back runs inside each field.  Each workgroup takes
+// its next item from the queue before it starts the current one, so the
+// atomic's latency overlaps the work.
+//
+// Dequantize: one kernel with a workgroup per dequantize tile of every field
+// (independent tiles), mapped through an item table.
+//
+// Both are captured once into HIP graphs at plan creation; running the batch
+// is one hipGraphLaunch.  Every field's stream and decode are byte-identical
+// to what the plain entry points produce for that field alone.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+#include <cstdlib>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "lcq.h"
+#include "lcq_host.hpp"
+#include "lcq_math.hpp"
+#include "lcq_tile.hpp"
+
+#pragma clang fp contract(off)
+
+using namespace lcq;
+
+namespace {
+
+// Batch tile shapes (slots, rounds) per dtype; the tuner picks one.
+struct BatchShape {
+  Shape f32, f64;
+};
+constexpr int kNumBatchVariants = 3;
+constexpr BatchShape kBatchVariants[kNumBatchVariants] = {
+    {{4, 4}, {4, 8}},  // 16384-value tiles
+    {{4, 2}, {4, 4}},  // 8192
+    {{4, 1}, {4, 2}},  // 4096
+};
+constexpr uint64_t kSlice = 1ull << 18;  // values per NOA range item
+constexpr int kDeqSlots = 4, kDeqRounds = 1;
+constexpr uint64_t kDeqTile = (uint64_t)kBlock * 4 * kDeqSlots * kDeqRounds;
+
+// Device descriptor of one field.
+struct BField {
+  const void *in;
+  uint64_t n;
+  uint8_t *stream;
+  uint64_t stream_cap;
+  uint64_t *stream_bytes;
+  void *out;
+  uint64_t state_off;    // first look-back word of this field
+  uint64_t ntiles;       // quantize tiles
+  uint64_t step, inv, bound, low;  // host-derived parameters (ABS / REL)
+  uint64_t hdr[8];
+  uint64_t eb_down;      // NOA: RD_T(eb)
+  uint64_t partial_off;  // NOA: first (min, max) pair of this field
+  uint32_t nslices;      // NOA: range items of this field
+  uint32_t noa_idx;      // NOA: index of the field's DevParams / counters
+  int32_t dtype, q;
+};
+
+// Workspace layout of a plan (byte offsets).
+struct Layout {
+  uint64_t head, fields, items_q, items_d, params, done, state, partials, dstatus, total;
+  uint64_t clear_begin, clear_words;  // u64 words zeroed before each quantize
+};
+
+struct BatchQArgs {
+  const BField *fields;
+  const uint64_t *items;  // (field << 32) | (local index); phase A first
+  uint64_t n_a, n_items;
+  unsigned *head;
+  DevParams *params;
+  unsigned *done;
+  uint64_t *state;
+  uint8_t *partials;
+  unsigned spin_limit;
+};
+
+template <typename T>
+__device__ void range_item(const BatchQArgs &a, const BField &f, uint64_t slice) {
+  const uint64_t b = slice * kSlice;
+  const uint64_t e = min(b + kSlice, f.n);
+  T lo, hi;
+  block_minmax<T>(static_cast<const T *>(f.in), b, e, lo, hi);
+  __shared__ int s_last;
+  T *parts = reinterpret_cast<T *>(a.partials + f.partial_off);
+  if (threadIdx.x == 0) {
+    parts[2 * slice] = lo;
+    parts[2 * slice + 1] = hi;
+    // release our pair; the field's last slice (acquire) sees every pair
+    const unsigned prev = __hip_atomic_fetch_add(a.done + f.noa_idx, 1u, __ATOMIC_ACQ_REL,
+                                                 __HIP_MEMORY_SCOPE_AGENT);
+    s_last = prev == f.nslices - 1;
+  }
+  __syncthreads();
+  if (!s_last) return;
+  // the field's range from every slice, then its parameters
+  T l2 = (T)INFINITY, h2 = (T)-INFINITY;
+  for (uint32_t i = threadIdx.x; i < f.nslices; i += kBlock) {
+    l2 = fmin(l2, __hip_atomic_load(parts + 2 * i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+    h2 = fmax(h2, __hip_atomic_load(parts + 2 * i + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    l2 = fmin(l2, __shfl_xor(l2, o, 64));
+    h2 = fmax(h2, __shfl_xor(h2, o, 64));
+  }
+  __shared__ T s_lo[kWaves], s_hi[kWaves];
+  if ((threadIdx.x & 63) == 0) {
+    s_lo[threadIdx.x >> 6] = l2;
+    s_hi[threadIdx.x >> 6] = h2;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int w = 1; w < kWaves; w++) {
+      l2 = fmin(l2, s_lo[w]);
+      h2 = fmax(h2, s_hi[w]);
+    }
+    DevParams d = noa_params<T>(l2, h2, from_bits((typename FT<T>::U)f.eb_down));
+    DevParams *dst = a.params + f.noa_idx;
+    dst->step = d.step;
+    dst->inv = d.inv;
+    dst->bound = d.bound;
+    dst->lo = d.lo;
+    dst->hi = d.hi;
+    dst->lossless_all = d.lossless_all;
+    __hip_atomic_store(&dst->ready, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+  }
+}
+
+template <typename T, int Q, int SL, int RD>
+__device__ void tile_item(const BatchQArgs &a, const BField &bf, uint64_t tile) {
+  using U = typename FT<T>::U;
+  QField<T> f;
+  f.in = static_cast<const T *>(bf.in);
+  f.n = bf.n;
+  f.stream = bf.stream;
+  f.stream_bytes = bf.stream_bytes;
+  f.state = a.state + bf.state_off;
+  f.ntiles = bf.ntiles;
+#pragma unroll
+  for (int i = 0; i < 8; i++) f.hdr[i] = bf.hdr[i];
+  if constexpr (Q == kNOA) {
+    DevParams *dp = a.params + bf.noa_idx;
+    __shared__ int s_ready;
+    if (threadIdx.x == 0) {
+      while (__hip_atomic_load(&dp->ready, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == 0)
+        __builtin_amdgcn_s_sleep(2);
+      s_ready = 1;
+    }
+    __syncthreads();
+    (void)s_ready;
+    DevParams d;
+    d.step = __hip_atomic_load(&dp->step, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    d.inv = __hip_atomic_load(&dp->inv, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    d.bound = __hip_atomic_load(&dp->bound, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    d.lo = __hip_atomic_load(&dp->lo, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    d.hi = __hip_atomic_load(&dp->hi, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    d.lossless_all = __hip_atomic_load(&dp->lossless_all, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    f.p = params_from<T>(d);
+    f.hdr[4] = d.step;
+    f.hdr[5] = d.bound;
+    f.hdr[6] = d.lo;
+    f.hdr[7] = d.hi;
+  } else {
+    f.p.step = from_bits((U)bf.step);
+    f.p.inv = from_bits((U)bf.inv);
+    f.p.bound = from_bits((U)bf.bound);
+    f.p.low = from_bits((U)bf.low);
+    f.p.lossless_all = 0;
+  }
+  quant_tile<T, Q, SL, RD>(f, tile, a.spin_limit);
+}
+
+template <int SL32, int RD32, int SL64, int RD64>
+__global__ __launch_bounds__(kBlock) void k_batch_quantize(BatchQArgs a) {
+  __shared__ unsigned s_cur;
+  unsigned next = 0;
+  if (threadIdx.x == 0) next = atomicAdd(a.head, 1u);
+  while (true) {
+    __syncthreads();  // everyone is done with the previous item
+    if (threadIdx.x == 0) {
+      s_cur = next;
+      if (next < a.n_items) next = atomicAdd(a.head, 1u);  // prefetch the next item
+    }
+    __syncthreads();
+    const unsigned cur = s_cur;
+    if (cur >= a.n_items) break;
+    const uint64_t it = a.items[cur];
+    const BField &f = a.fields[it >> 32];
+    const uint64_t local = it & 0xFFFFFFFFull;
+    if (cur < a.n_a) {
+      if (f.dtype == LCQ_F32) range_item<float>(a, f, local);
+      else range_item<double>(a, f, local);
+      continue;
+    }
+    if (f.dtype == LCQ_F32) {
+      if (f.q == kABS) tile_item<float, kABS, SL32, RD32>(a, f, local);
+      else if (f.q == kREL) tile_item<float, kREL, SL32, RD32>(a, f, local);
+      else tile_item<float, kNOA, SL32, RD32>(a, f, local);
+    } else {
+      if (f.q == kABS) tile_item<double, kABS, SL64, RD64>(a, f, local);
+      else if (f.q == kREL) tile_item<double, kREL, SL64, RD64>(a, f, local);
+      else tile_item<double, kNOA, SL64, RD64>(a, f, local);
+    }
+  }
+}
+
+struct BatchDArgs {
+  const BField *fields;
+  const uint64_t *items;
+  uint64_t n_items;
+  unsigned long long *status;  // one word per field
+};
+
+template <typename T>
+__device__ void deq_item(const BatchDArgs &a, const BField &bf, uint32_t fi, uint64_t tile) {
+  using U = typename FT<T>::U;
+  const uint64_t n = bf.n;
+  const uint64_t *hd = reinterpret_cast<const uint64_t *>(bf.stream);
+  const uint64_t h0 = hd[0];
+  const uint64_t k = hd[2];
+  const int q = (int)((h0 >> 48) & 0xFF);
+  const bool bad = (h0 & ~(0xFFull << 48)) != header_word0(bf.dtype, 0) || q > 2 ||
+                   hd[1] != n || k > n || outlier_offset(n) + k * sizeof(T) > bf.stream_cap;
+  if (bad) {
+    if (threadIdx.x == 0) atomicMax(a.status + fi, (unsigned long long)LCQ_ERR_STREAM);
+    return;
+  }
+  DField<T> f;
+  f.stream = bf.stream;
+  f.n = n;
+  f.k = k;
+  f.step = from_bits((U)hd[4]);
+  f.rel = (q == kREL);
+  f.out = static_cast<T *>(bf.out);
+  f.status = a.status + fi;
+  f.tag = 0;
+  dequant_tile<T, kDeqSlots, kDeqRounds>(f, tile);
+}
+
+__global__ __launch_bounds__(kBlock) void k_batch_dequantize(BatchDArgs a) {
+  const uint64_t it = a.items[blockIdx.x];
+  const uint32_t fi = (uint32_t)(it >> 32);
+  const BField &f = a.fields[fi];
+  const uint64_t tile = it & 0xFFFFFFFFull;
+  if (f.dtype == LCQ_F32) deq_item<float>(a, f, fi, tile);
+  else deq_item<double>(a, f, fi, tile);
+}
+
+__global__ void k_batch_clear(uint64_t *p, uint64_t count) {
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count;
+       i += (uint64_t)gridDim.x * blockDim.x)
+    p[i] = 0;
+}
+
+uint64_t up256(uint64_t v) { return (v + 255) & ~255ull; }
+
+struct Counts {
+  uint64_t n_a = 0, n_b = 0, n_d = 0, states = 0, partial_bytes = 0;
+  uint32_t n_noa = 0;
+};
+
+uint64_t qtile_len(int dtype, int bv) {
+  const Shape s = dtype == LCQ_F64 ? kBatchVariants[bv].f64 : kBatchVariants[bv].f32;
+  return (uint64_t)kBlock * (dtype == LCQ_F64 ? 2 : 4) * s.slots * s.rounds;
+}
+
+Counts count(const lcq_field *f, uint32_t nf, int bv) {
+  Counts c;
+  for (uint32_t i = 0; i < nf; i++) {
+    const uint64_t tl = qtile_len(f[i].t, bv);
+    const uint64_t nt = f[i].n ? (f[i].n + tl - 1) / tl : 1;  // n = 0: one header-only tile
+    c.n_b += nt;
+    c.states += nt;
+    c.n_d += (f[i].n + kDeqTile - 1) / kDeqTile;
+    if (f[i].q == LCQ_NOA) {
+      const uint64_t ns = std::max<uint64_t>(1, (f[i].n + kSlice - 1) / kSlice);
+      c.n_a += ns;
+      c.partial_bytes += up256(ns * 2 * (f[i].t == LCQ_F64 ? 8 : 4));
+      c.n_noa++;
+    }
+  }
+  return c;
+}
+
+Layout layout_for(const Counts &c, uint32_t nf) {
+  Layout L{};
+  uint64_t o = 0;
+  L.head = o;          o += 256;
+  L.params = o;        o += up256(sizeof(DevParams) * std::max<uint32_t>(c.n_noa, 1));
+  L.done = o;          o += up256(4ull * std::max<uint32_t>(c.n_noa, 1));
+  L.dstatus = o;       o += up256(8ull * std::max<uint32_t>(nf, 1));
+  L.state = o;         o += up256(8 * std::max<uint64_t>(c.states, 1));
+  L.clear_begin = 0;
+  L.clear_words = o / 8;  // head, params (ready flags), done, status, state
+  L.fields = o;        o += up256(sizeof(BField) * std::max<uint32_t>(nf, 1));
+  L.items_q = o;       o += up256(8 * std::max<uint64_t>(c.n_a + c.n_b, 1));
+  L.items_d = o;       o += up256(8 * std::max<uint64_t>(c.n_d, 1));
+  L.partials = o;      o += std::max<uint64_t>(c.partial_bytes, 256);
+  L.total = o;
+  return L;
+}
+
+int parse_variant(const char *tune) {
+  if (!tune) return 0;
+  const char *p = std::strstr(tune, "batch=");
+  if (!p) return 0;
+  const int v = std::atoi(p + 6);
+  return (v >= 0 && v < kNumBatchVariants) ? v : -1;
+}
+
+lcq_status launch_batch_quantize(int bv, const BatchQArgs &a, unsigned grid, hipStream_t s) {
+  const dim3 g(grid), b(kBlock);
+  switch (bv) {
+    case 1: hipLaunchKernelGGL((k_batch_quantize<4, 2, 4, 4>), g, b, 0, s, a); break;
+    case 2: hipLaunchKernelGGL((k_batch_quantize<4, 1, 4, 2>), g, b, 0, s, a); break;
+    default: hipLaunchKernelGGL((k_batch_quantize<4, 4, 4, 8>), g, b, 0, s, a); break;
+  }
+  return hipGetLastError() == hipSuccess ? LCQ_OK : LCQ_ERR_HIP;
+}
+
+const void *batch_kernel_ptr(int bv) {
+  switch (bv) {
+    case 1: return (const void *)k_batch_quantize<4, 2, 4, 4>;
+    case 2: return (const void *)k_batch_quantize<4, 1, 4, 2>;
+    default: return (const void *)k_batch_quantize<4, 4, 4, 8>;
+  }
+}
+
+}  // namespace
+
+struct lcq_batch_plan {
+  int variant;
+  uint32_t nf;
+  uint8_t *ws;
+  Layout L;
+  Counts c;
+  unsigned grid;
+  hipGraph_t gq = nullptr, gd = nullptr;
+  hipGraphExec_t eq = nullptr, ed = nullptr;
+};
+
+extern "C" {
+
+int32_t lcq_batch_variants(void) { return kNumBatchVariants; }
+
+uint64_t lcq_batch_workspace_bytes(const lcq_field *f, uint32_t nf, const char *tune) {
+  const int bv = parse_variant(tune);
+  if (bv < 0 || (nf && !f)) return 0;
+  return layout_for(count(f, nf, bv), nf).total;
+}
+
+lcq_status lcq_batch_plan_create(const lcq_field *f, uint32_t nf, const char *tune, void *d_ws,
+                                 uint64_t ws_bytes, hipStream_t stream, lcq_batch_plan **out) {
+  if (!out || (nf && !f) || !d_ws || !aligned16(d_ws)) return LCQ_ERR_ARG;
+  *out = nullptr;
+  const int bv = parse_variant(tune);
+  if (bv < 0) return LCQ_ERR_ARG;
+  for (uint32_t i = 0; i < nf; i++) {
+    const lcq_field &x = f[i];
+    if (x.q != LCQ_ABS && x.q != LCQ_REL && x.q != LCQ_NOA) return LCQ_ERR_ARG;
+    if (x.t != LCQ_F32 && x.t != LCQ_F64) return LCQ_ERR_ARG;
+    if (!(x.eb > 0.0) || !std::isfinite(x.eb) || (x.q == LCQ_REL && !(x.eb < 1.0))) return LCQ_ERR_ARG;
+    if (x.n > LCQ_MAX_N || x.n >= (1ull << 32) * 1024) return LCQ_ERR_ARG;
+    if (x.n && (!x.d_in || !aligned16(x.d_in))) return LCQ_ERR_ARG;
+    if (!x.d_stream || !aligned16(x.d_stream) || !x.d_stream_bytes ||
+        ((uintptr_t)x.d_stream_bytes & 7u))
+      return LCQ_ERR_ARG;
+    if (x.d_out && !aligned16(x.d_out)) return LCQ_ERR_ARG;
+    if (x.stream_cap < lcq_max_stream_bytes(x.t, x.n)) return LCQ_ERR_CAPACITY;
+  }
+  const Counts c = count(f, nf, bv);
+  const Layout L = layout_for(c, nf);
+  if (ws_bytes < L.total) return LCQ_ERR_CAPACITY;
+  if (c.n_a + c.n_b >= (1ull << 32)) return LCQ_ERR_ARG;
+
+  // descriptors and item tables
+  std::vector<BField> bf(nf);
+  std::vector<uint64_t> items_a, items_b, items_d;
+  items_a.reserve(c.n_a);
+  items_b.reserve(c.n_b);
+  items_d.reserve(c.n_d);
+  uint64_t state_off = 0, part_off = 0;
+  uint32_t noa_idx = 0;
+  for (uint32_t i = 0; i < nf; i++) {
+    const lcq_field &x = f[i];
+    BField &d = bf[i];
+    std::memset(&d, 0, sizeof d);
+    d.in = x.d_in;
+    d.n = x.n;
+    d.stream = static_cast<uint8_t *>(x.d_stream);
+    d.stream_cap = x.stream_cap;
+    d.stream_bytes = x.d_stream_bytes;
+    d.out = x.d_out;
+    d.dtype = x.t;
+    d.q = x.q;
+    const HostParams hp = x.t == LCQ_F64 ? host_params<double>(x.q, x.eb) : host_params<float>(x.q, x.eb);
+    d.step = hp.step;
+    d.inv = hp.inv;
+    d.bound = hp.bound;
+    d.low = hp.low;
+    d.eb_down = hp.eb_down;
+    d.hdr[0] = header_word0(x.t, x.q);
+    d.hdr[1] = x.n;
+    d.hdr[2] = 0;
+    d.hdr[3] = __builtin_bit_cast(uint64_t, x.eb);
+    d.hdr[4] = hp.step;
+    d.hdr[5] = hp.bound;
+    d.hdr[6] = hp.aux0;
+    d.hdr[7] = hp.aux1;
+    const uint64_t tl = qtile_len(x.t, bv);
+    d.ntiles = x.n ? (x.n + tl - 1) / tl : 1;  // n = 0: one tile that writes the header
+    d.state_off = state_off;
+    state_off += d.ntiles;
+    if (x.q == LCQ_NOA) {
+      d.noa_idx = noa_idx++;
+      d.nslices = (uint32_t)std::max<uint64_t>(1, (x.n + kSlice - 1) / kSlice);
+      d.partial_off = part_off;
+      part_off += up256((uint64_t)d.nslices * 2 * (x.t == LCQ_F64 ? 8 : 4));
+      for (uint32_t s = 0; s < d.nslices; s++) items_a.push_back(((uint64_t)i << 32) | s);
+    }
+    const uint64_t ndt = (x.n + kDeqTile - 1) / kDeqTile;
+    for (uint64_t t = 0; t < ndt; t++) items_d.push_back(((uint64_t)i << 32) | t);
+  }
+  // phase B: larger fields first (their tiles are the long tail), each
+  // field's tiles in increasing order
+  std::vector<uint32_t> order(nf);
+  for (uint32_t i = 0; i < nf; i++) order[i] = i;
+  std::stable_sort(order.begin(), order.end(),
+                   [&](uint32_t a, uint32_t b) { return f[a].n * (f[a].t == LCQ_F64 ? 8 : 4) >
+                                                        f[b].n * (f[b].t == LCQ_F64 ? 8 : 4); });
+  for (uint32_t i : order) {
+    for (uint64_t t = 0; t < bf[i].ntiles; t++) items_b.push_back(((uint64_t)i << 32) | t);
+  }
+  std::vector<uint64_t> items_q(items_a);
+  items_q.insert(items_q.end(), items_b.begin(), items_b.end());
+
+  uint8_t *ws = static_cast<uint8_t *>(d_ws);
+  if (nf && hipMemcpyAsync(ws + L.fields, bf.data(), sizeof(BField) * nf, hipMemcpyHostToDevice, stream) != hipSuccess) return LCQ_ERR_HIP;
+  if (!items_q.empty() && hipMemcpyAsync(ws + L.items_q, items_q.data(), 8 * items_q.size(), hipMemcpyHostToDevice, stream) != hipSuccess) return LCQ_ERR_HIP;
+  if (!items_d.empty() && hipMemcpyAsync(ws + L.items_d, items_d.data(), 8 * items_d.size(), hipMemcpyHostToDevice, stream) != hipSuccess) return LCQ_ERR_HIP;
+  if (hipStreamSynchronize(stream) != hipSuccess) return LCQ_ERR_HIP;
+
+  lcq_batch_plan *p = new (std::nothrow) lcq_batch_plan();
+  if (!p) return LCQ_ERR_ARG;
+  p->variant = bv;
+  p->nf = nf;
+  p->ws = ws;
+  p->L = L;
+  p->c = c;
+  // persistent grid: every workgroup resident at once
+  int dev = 0, cus = 0, per_cu = 0;
+  (void)hipGetDevice(&dev);
+  (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, batch_kernel_ptr(bv), kBlock, 0);
+  if (cus <= 0) cus = 256;
+  if (per_cu <= 0) per_cu = 1;
+  uint64_t g = (uint64_t)cus * per_cu;
+  g = std::min<uint64_t>(g, std::max<uint64_t>(c.n_a + c.n_b, 1));
+  p->grid = (unsigned)g;
+
+  BatchQArgs qa{};
+  qa.fields = reinterpret_cast<const BField *>(ws + L.fields);
+  qa.items = reinterpret_cast<const uint64_t *>(ws + L.items_q);
+  qa.n_a = c.n_a;
+  qa.n_items = c.n_a + c.n_b;
+  qa.head = reinterpret_cast<unsigned *>(ws + L.head);
+  qa.params = reinterpret_cast<DevParams *>(ws + L.params);
+  qa.done = reinterpret_cast<unsigned *>(ws + L.done);
+  qa.state = reinterpret_cast<uint64_t *>(ws + L.state);
+  qa.partials = ws + L.partials;
+  qa.spin_limit = g_spin_limit.load();
+  BatchDArgs da{};
+  da.fields = qa.fields;
+  da.items = reinterpret_cast<const uint64_t *>(ws + L.items_d);
+  da.n_items = c.n_d;
+  da.status = reinterpret_cast<unsigned long long *>(ws + L.dstatus);
+
+  // capture: clear + persistent quantize; clear + dequantize
+  hipStream_t cs;
+  if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess) { delete p; return LCQ_ERR_HIP; }
+  lcq_status st = LCQ_OK;
+  const unsigned cgrid = (unsigned)std::min<uint64_t>((L.clear_words + kBlock - 1) / kBlock, 1024);
+  if (hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) != hipSuccess) st = LCQ_ERR_HIP;
+  if (st == LCQ_OK) {
+    hipLaunchKernelGGL(k_batch_clear, dim3(cgrid), dim3(kBlock), 0, cs,
+                       reinterpret_cast<uint64_t *>(ws), L.clear_words);
+    if (qa.n_items) st = launch_batch_quantize(bv, qa, p->grid, cs);
+    if (hipStreamEndCapture(cs, &p->gq) != hipSuccess) st = LCQ_ERR_HIP;
+  }
+  if (st == LCQ_OK && hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) != hipSuccess) st = LCQ_ERR_HIP;
+  if (st == LCQ_OK) {
+    const uint64_t sw = up256(8ull * std::max<uint32_t>(nf, 1)) / 8;
+    hipLaunchKernelGGL(k_batch_clear, dim3(1), dim3(kBlock), 0, cs,
+                       reinterpret_cast<uint64_t *>(ws + L.dstatus), sw);
+    if (c.n_d) hipLaunchKernelGGL(k_batch_dequantize, dim3((unsigned)c.n_d), dim3(kBlock), 0, cs, da);
+    if (hipGetLastError() != hipSuccess) st = LCQ_ERR_HIP;
+    if (hipStreamEndCapture(cs, &p->gd) != hipSuccess) st = LCQ_ERR_HIP;
+  }
+  if (st == LCQ_OK && hipGraphInstantiate(&p->eq, p->gq, nullptr, nullptr, 0) != hipSuccess) st = LCQ_ERR_HIP;
+  if (st == LCQ_OK && hipGraphInstantiate(&p->ed, p->gd, nullptr, nullptr, 0) != hipSuccess) st = LCQ_ERR_HIP;
+  (void)hipStreamDestroy(cs);
+  if (st != LCQ_OK) {
+    lcq_batch_plan_destroy(p);
+    return st;
+  }
+  *out = p;
+  return LCQ_OK;
+}
+
+lcq_status lcq_batch_quantize(lcq_batch_plan *p, hipStream_t s) {
+  if (!p) return LCQ_ERR_ARG;
+  return hipGraphLaunch(p->eq, s) == hipSuccess ? LCQ_OK : LCQ_ERR_HIP;
+}
+
+lcq_status lcq_batch_dequantize(lcq_batch_plan *p, hipStream_t s) {
+  if (!p) return LCQ_ERR_ARG;
+  return hipGraphLaunch(p->ed, s) == hipSuccess ? LCQ_OK : LCQ_ERR_HIP;
+}
+
+lcq_status lcq_batch_status(lcq_batch_plan *p, hipStream_t s, int64_t *h_first_bad) {
+  if (!p || !h_first_bad) return LCQ_ERR_ARG;
+  std::vector<uint64_t> st(std::max<uint32_t>(p->nf, 1));
+  if (p->nf && hipMemcpyAsync(st.data(), p->ws + p->L.dstatus, 8ull * p->nf,
+                              hipMemcpyDeviceToHost, s) != hipSuccess)
+    return LCQ_ERR_HIP;
+  if (hipStreamSynchronize(s) != hipSuccess) return LCQ_ERR_HIP;
+  *h_first_bad = -1;
+  for (uint32_t i = 0; i < p->nf; i++)
+    if (st[i] & 0xFFFF) {
+      *h_first_bad = i;
+      break;
+    }
+  return LCQ_OK;
+}
+
+void lcq_batch_plan_destroy(lcq_batch_plan *p) {
+  if (!p) return;
+  if (p->eq) (void)hipGraphExecDestroy(p->eq);
+  if (p->ed) (void)hipGraphExecDestroy(p->ed);
+  if (p->gq) (void)hipGraphDestroy(p->gq);
+  if (p->gd) (void)hipGraphDestroy(p->gd);
+  delete p;
+}
+
+}  // extern "C"
