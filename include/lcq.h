@@ -157,6 +157,47 @@ lcq_status lcq_batch_status(lcq_batch_plan *p, hipStream_t s, int64_t *h_first_b
 
 void lcq_batch_plan_destroy(lcq_batch_plan *p);
 
+/* -------------------------------------------------------------- serving --
+ * Continuous batching: lcq_serve runs an open-loop schedule of requests.  A
+ * request is admitted (first come, first served) as soon as one of
+ * n_streams HIP streams is free and its output and workspace fit in the
+ * device arena; admitted requests run concurrently; completions free their
+ * slot and memory at once.  Every output is compared on the device with the
+ * caller's expected bytes.  Blocking; host-side single loop.
+ */
+typedef struct {
+  int32_t op;             /* 0 = quantize, 1 = dequantize                      */
+  lcq_quantizer q;        /* quantize only                                     */
+  lcq_dtype t;
+  double eb;              /* quantize only                                     */
+  const void *d_in;       /* quantize: n values; dequantize: the stream        */
+  uint64_t n;             /* values                                            */
+  uint64_t in_bytes;      /* dequantize: valid stream bytes at d_in            */
+  const void *d_expect;   /* expected output (stream / n values) or null       */
+  uint64_t expect_bytes;  /* quantize: expected stream size (<= the capacity)  */
+  int64_t arrival_ns;     /* arrival, ns after the start; non-decreasing       */
+} lcq_request;
+
+typedef struct {
+  int64_t admit_ns;       /* launch time, ns after the start                  */
+  int64_t done_ns;        /* completion seen by the loop, ns after the start  */
+  uint64_t mismatched;    /* differing 16-byte words vs expected; +2^40 if    */
+                          /* the stream size differs                          */
+  int32_t status;         /* lcq_status of the request                        */
+  int32_t stream;         /* slot it ran on                                   */
+} lcq_request_result;
+
+typedef struct {
+  uint32_t n_streams;     /* concurrent slots (1..64)                          */
+  void *d_arena;          /* device memory outputs / workspaces come from      */
+  uint64_t arena_bytes;   /* the admission budget                              */
+  void *d_scratch;        /* >= 8 bytes per request (mismatch counters)        */
+  uint64_t scratch_bytes;
+} lcq_server_config;
+
+lcq_status lcq_serve(const lcq_server_config *cfg, const lcq_request *req, uint32_t nreq,
+                     lcq_request_result *res);
+
 /* Launch-shape tuning.  Each per-value kernel comes in lcq_tune_variants()
  * shapes (loads in flight per thread x rounds per tile); all produce the
  * same bytes.  op 0 = quantize, 1 = dequantize.  Process-wide; the tuner

@@ -202,3 +202,55 @@ def adversarial_rel(m, eb, seed, dtype):
     v = np.where(j > 0, np.nextafter(v, dtype.type(np.inf)), v)
     v = np.where(rng.integers(0, 2, m) == 1, -v, v)
     return v.astype(dtype)
+
+
+def log_uniform_sizes(rng, m, lo_bytes, hi_bytes):
+    """m sizes in bytes, log-uniform on [lo_bytes, hi_bytes]."""
+    return np.exp(rng.uniform(np.log(lo_bytes), np.log(hi_bytes), m))
+
+
+def field_specs(m, seed, lo_bytes, hi_bytes, p_f32=0.7, eb_lo=1e-5, eb_hi=1e-1):
+    """Per-field (or per-payload) choices of the batched / serving workloads:
+    byte size log-uniform on [lo_bytes, hi_bytes], float32 with probability
+    p_f32 else float64, quantizer uniform over ABS / REL / NOA, bound
+    log-uniform on [eb_lo, eb_hi].  Returns a list of dicts."""
+    rng = _rng(seed)
+    sizes = log_uniform_sizes(rng, m, lo_bytes, hi_bytes)
+    out = []
+    for b in sizes:
+        f32 = rng.random() < p_f32
+        s = 4 if f32 else 8
+        out.append(dict(dtype=np.float32 if f32 else np.float64, n=max(1, int(b) // s),
+                        q=["abs", "rel", "noa"][int(rng.integers(0, 3))],
+                        eb=float(np.exp(rng.uniform(np.log(eb_lo), np.log(eb_hi)))),
+                        offset_u=float(rng.random())))
+    return out
+
+
+def field_data(spec, master, rel_master, seed, special_frac=1e-4):
+    """A field's values: a contiguous (wrapping) slice of the master field
+    (its lognormal variant for REL), cast to the field's dtype, with
+    special_frac of the positions replaced by special values."""
+    src = rel_master if spec["q"] == "rel" else master
+    n = spec["n"]
+    off = int(spec["offset_u"] * src.size)
+    if off + n <= src.size:
+        x = src[off: off + n].astype(spec["dtype"])
+    else:
+        x = np.take(src, np.arange(off, off + n) % src.size).astype(spec["dtype"])
+    k = int(round(n * special_frac))
+    if k:
+        x, _, _ = inject_specials(x, k, seed, spec["eb"])
+    return x
+
+
+def poisson_arrivals(rate_per_s, seconds, seed):
+    """Arrival times (ns) of a Poisson process of the given rate."""
+    rng = _rng(seed)
+    t, out = 0.0, []
+    while True:
+        t += rng.exponential(1.0 / rate_per_s)
+        if t >= seconds:
+            break
+        out.append(int(t * 1e9))
+    return np.array(out, dtype=np.int64)
