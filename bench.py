@@ -1,19 +1,26 @@
-"""Benchmark: plain single-field quantize + dequantize on one MI355X.
+"""Benchmark of the guaranteed-error-bound quantizers on one MI355X.
 
-Workload (one "step"): a 512^3 float32 Gaussian-random-field grid (power
-spectrum k^-3, unit variance, seed 1, 0.01 % special values) quantized and
-dequantized under ABS and NOA at eb = 1e-3, and its lognormal-magnitude
-variant (log10|x| ~ U(-30, 30), random signs, 1 % zeros, seed 11) under REL at
-eb = 1e-3.  Inputs are resident in HBM before timing starts; every stream and
-decode is produced by the library's HIP kernels through the C ABI.
+Headline (the `value` field): plain single-field quantize + dequantize.  One
+step = a 512^3 float32 Gaussian-random-field grid (power spectrum k^-3, unit
+variance, seed 1, 0.01 % special values) quantized and dequantized under ABS
+and NOA at eb = 1e-3, and its lognormal-magnitude variant (log10|x| ~
+U(-30, 30), random signs, 1 % zeros, seed 11) quantized and dequantized under
+REL at eb = 1e-3.  value = input bytes of the three fields / step time, GB/s.
+Inputs are resident in HBM before timing starts; every stream and decode is
+produced by the library's HIP kernels through the C ABI.
 
-value = input bytes of the three fields / step time (each field quantized
-once and dequantized once per step), GB/s.
-
-Also reported: per-operation GB/s, the dominant kernel's roofline (HIP events
-around each main-kernel launch inside the timed steps), the oracle's
-throughput on this host, and a byte-exact comparison of the GPU streams with
-the oracle's.
+Also reported on the same JSON line:
+  ops          per-kernel time and GB/s (HIP events around each main kernel)
+  roofline     the dominant kernel against the 8 TB/s HBM peak
+  batched      2,000 fields, log-uniform 4 KiB - 64 MiB, 70 % float32, random
+               quantizer and eb in [1e-5, 1e-1]: one graph launch vs a
+               per-field launch loop, byte-equal outputs checked
+  serving      Poisson requests (50/50 quantize / dequantize, 64 KiB - 256 MiB,
+               mixed dtype / quantizer / eb), 64 GB admission budget: GB/s,
+               p50 / p99 latency, every output checked against the same
+               request run alone
+  cpu_baseline the CPU oracle on this host (single thread), which also checks
+               the GPU streams of the plain step and of sampled batch fields
 """
 import argparse
 import json
@@ -32,7 +39,22 @@ def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
 
 
-def make_inputs(N, eb, seed=1, rel_seed=11, frac=1e-4):
+def alg_bytes_quant(n, s, k):
+    # read n values, write n int32 codes, one u64 per 1024-value chunk, k outliers
+    return n * s + 4 * n + 8 * ((n + 1023) // 1024) + k * s
+
+
+def alg_bytes_dequant(n, s, k):
+    return 4 * n + 8 * ((n + 1023) // 1024) + k * s + n * s
+
+
+def header_k(buf):
+    import numpy as np
+    return int(buf[:64].cpu().numpy()[16:24].view(np.uint64)[0])
+
+
+# ------------------------------------------------------------------- plain --
+def make_plain_inputs(N, eb, seed=1, rel_seed=11, frac=1e-4):
     import numpy as np
     import synth
     t0 = time.time()
@@ -43,17 +65,278 @@ def make_inputs(N, eb, seed=1, rel_seed=11, frac=1e-4):
     xr = synth.rel_variant(g, rel_seed, dtype=np.float32)
     del g
     xr, _, _ = synth.inject_specials(xr, nsp, rel_seed + 1000, eb)
-    log(f"inputs {N}^3 generated in {time.time() - t0:.1f}s")
+    log(f"plain inputs {N}^3 generated in {time.time() - t0:.1f}s")
     return x, xr
 
 
-def alg_bytes_quant(n, s, k):
-    # read n values, write n int32 codes, one u64 per 1024-value chunk, k outliers
-    return n * s + 4 * n + 8 * ((n + 1023) // 1024) + k * s
+def run_plain(args, x, xr):
+    import torch
+    import paper_2407_15037_amd as lcq
+    dev = torch.device("cuda:0")
+    eb = args.eb
+    n, s = x.size, 4
+    order_q = ["abs", "noa", "rel"]
+    dx = {"abs": torch.from_numpy(x).to(dev)}
+    dx["noa"] = dx["abs"]
+    dx["rel"] = torch.from_numpy(xr).to(dev)
+    cap = lcq.max_stream_bytes(torch.float32, n)
+    bufs = {q: torch.empty(cap, dtype=torch.uint8, device=dev) for q in order_q}
+    nbs = {q: torch.zeros(1, dtype=torch.int64, device=dev) for q in order_q}
+    ws = {q: torch.empty(lcq.workspace_bytes(q, torch.float32, n), dtype=torch.uint8, device=dev)
+          for q in order_q}
+    outs = {q: torch.empty(n, dtype=torch.float32, device=dev) for q in order_q}
+    torch.cuda.synchronize()
+    ev = {}
+
+    def step(record):
+        for kind in ("q", "d"):
+            for q in order_q:
+                if record:
+                    e0 = torch.cuda.Event(enable_timing=True)
+                    e1 = torch.cuda.Event(enable_timing=True)
+                    e0.record(); e1.record()  # create the events before handing them over
+                    lcq.profile_events(e0, e1)
+                    ev.setdefault((kind, q), []).append((e0, e1))
+                if kind == "q":
+                    lcq.quantize(dx[q], q, eb, out=bufs[q], nbytes=nbs[q], ws=ws[q])
+                else:
+                    lcq.dequantize(bufs[q], torch.float32, n, out=outs[q], ws=ws[q])
+        lcq.profile_events(None, None)
+
+    for _ in range(args.warmup):
+        step(False)
+    torch.cuda.synchronize()
+    t_start = torch.cuda.Event(enable_timing=True)
+    t_end = torch.cuda.Event(enable_timing=True)
+    t_start.record()
+    for _ in range(args.steps):
+        step(True)
+    t_end.record()
+    torch.cuda.synchronize()
+    ms_per_step = t_start.elapsed_time(t_end) / args.steps
+    ks = {q: header_k(bufs[q]) for q in order_q}
+    kern = {}
+    for (kind, q), pairs in ev.items():
+        ms = [a.elapsed_time(b) for a, b in pairs]
+        avg = sum(ms) / len(ms)
+        nbytes = (alg_bytes_quant if kind == "q" else alg_bytes_dequant)(n, s, ks[q])
+        kern[f"{'quantize' if kind == 'q' else 'dequantize'}_{q}"] = {
+            "avg_us": avg * 1e3, "alg_bytes": nbytes, "gbs_hbm": nbytes / (avg * 1e-3) / 1e9,
+            "gbs_input": n * s / (avg * 1e-3) / 1e9}
+    value = n * s * len(order_q) / (ms_per_step * 1e-3) / 1e9
+    sizes = {q: int(nbs[q].item()) for q in order_q}
+    gpu_streams = {q: bufs[q][: sizes[q]].cpu().numpy() for q in order_q}
+    gpu_decodes = {q: outs[q].cpu().numpy() for q in order_q}
+    del dx, bufs, ws, outs
+    torch.cuda.empty_cache()
+    return dict(ms_per_step=ms_per_step, value=value, kern=kern, ks=ks, sizes=sizes, n=n,
+                gpu_streams=gpu_streams, gpu_decodes=gpu_decodes)
 
 
-def alg_bytes_dequant(n, s, k):
-    return 4 * n + 8 * ((n + 1023) // 1024) + k * s + n * s
+# ----------------------------------------------------------------- batched --
+def make_batch_specs(nf, seed=3):
+    import synth
+    return synth.field_specs(nf, seed, 4 << 10, 64 << 20)
+
+
+def make_masters(seed, N=256):
+    import numpy as np
+    import synth
+    master = synth.grf_3d(N, seed, dtype=np.float64)
+    return master, synth.rel_variant(master, seed + 10, dtype=np.float64)
+
+
+def run_batched(args):
+    import numpy as np
+    import torch
+    import paper_2407_15037_amd as lcq
+    import synth
+    from paper_2407_15037_amd.batch import BatchPlan, variants
+    t0 = time.time()
+    specs = make_batch_specs(args.fields)
+    master, relm = make_masters(3)
+    fields, total_bytes = [], 0
+    for i, sp in enumerate(specs):
+        x = synth.field_data(sp, master, relm, 30000 + i)
+        xt = torch.from_numpy(x).cuda()
+        fields.append(dict(x=xt, q=sp["q"], eb=sp["eb"]))
+        total_bytes += x.nbytes
+    torch.cuda.synchronize()
+    log(f"batched: {len(fields)} fields, {total_bytes / 1e9:.2f} GB generated in "
+        f"{time.time() - t0:.1f}s")
+
+    def timed(fn, reps):
+        ts = []
+        for r in range(reps + 1):
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record()
+            fn()
+            e1.record()
+            torch.cuda.synchronize()
+            if r:
+                ts.append(e0.elapsed_time(e1))
+        ts.sort()
+        return ts[len(ts) // 2]
+
+    # tuner: each batch tile shape, quantize graph time
+    best_v, tune_ms = 0, []
+    for v in range(variants()):
+        p = BatchPlan(fields, variant=v)
+        tune_ms.append(round(timed(p.quantize, 2), 3))
+        p.close()
+        del p
+        torch.cuda.empty_cache()
+    best_v = min(range(len(tune_ms)), key=lambda i: tune_ms[i])
+    log(f"batched tuner (quantize ms per variant): {tune_ms} -> {best_v}")
+    plan = BatchPlan(fields, variant=best_v)
+    bq = timed(plan.quantize, args.batch_reps)
+    bd = timed(plan.dequantize, args.batch_reps)
+    bad = plan.first_bad_field()
+
+    # per-field launch loop on the same fields (plain entry points)
+    loop_bufs = []
+    for f, d in zip(fields, plan.fields):
+        n = d["x"].numel()
+        loop_bufs.append(dict(
+            buf=torch.empty(lcq.max_stream_bytes(d["x"].dtype, n), dtype=torch.uint8, device="cuda"),
+            nb=torch.zeros(1, dtype=torch.int64, device="cuda"),
+            ws=torch.empty(lcq.workspace_bytes(f["q"], d["x"].dtype, n), dtype=torch.uint8, device="cuda"),
+            out=torch.empty(n, dtype=d["x"].dtype, device="cuda")))
+
+    def loop_q():
+        for f, lb in zip(fields, loop_bufs):
+            lcq.quantize(f["x"], f["q"], f["eb"], out=lb["buf"], nbytes=lb["nb"], ws=lb["ws"])
+
+    def loop_d():
+        for f, lb in zip(fields, loop_bufs):
+            lcq.dequantize(lb["buf"], f["x"].dtype, f["x"].numel(), out=lb["out"], ws=lb["ws"])
+
+    lq = timed(loop_q, args.batch_reps)
+    ld = timed(loop_d, args.batch_reps)
+    # batch output == per-field output, every field, compared on the device
+    same_streams = same_decodes = 0
+    for d, lb in zip(plan.fields, loop_bufs):
+        s1, s2 = int(d["nbytes"].item()), int(lb["nb"].item())
+        same_streams += int(s1 == s2 and torch.equal(d["stream"][:s1], lb["buf"][:s2]))
+        same_decodes += int(torch.equal(d["out"].view(torch.uint8), lb["out"].view(torch.uint8)))
+    res = {
+        "workload": f"{len(fields)} fields, log-uniform 4 KiB-64 MiB, 70% float32, "
+                    "random ABS/REL/NOA, eb log-uniform [1e-5, 1e-1], 0.01% specials",
+        "total_input_GB": round(total_bytes / 1e9, 3),
+        "variant": best_v, "tuner_quantize_ms": tune_ms,
+        "batch_quantize_ms": round(bq, 3), "batch_dequantize_ms": round(bd, 3),
+        "loop_quantize_ms": round(lq, 3), "loop_dequantize_ms": round(ld, 3),
+        "batch_GBs": round(total_bytes / ((bq + bd) * 1e-3) / 1e9, 1),
+        "loop_GBs": round(total_bytes / ((lq + ld) * 1e-3) / 1e9, 1),
+        "speedup_vs_loop": round((lq + ld) / (bq + bd), 3),
+        "fields_equal_to_plain": f"{same_streams}/{len(fields)} streams, "
+                                 f"{same_decodes}/{len(fields)} decodes",
+        "stream_check_first_bad": bad,
+    }
+    sample = [i for i in range(len(fields)) if fields[i]["x"].numel() <= (1 << 20)][:12]
+    sample_data = [(specs[i], fields[i]["x"].cpu().numpy(),
+                    plan.fields[i]["stream"][: int(plan.fields[i]["nbytes"].item())].cpu().numpy())
+                   for i in sample]
+    plan.close()
+    del plan, fields, loop_bufs
+    torch.cuda.empty_cache()
+    return res, sample_data
+
+
+# ----------------------------------------------------------------- serving --
+def run_serving(args):
+    import numpy as np
+    import torch
+    import paper_2407_15037_amd as lcq
+    import synth
+    from paper_2407_15037_amd import serve
+    t0 = time.time()
+    specs = synth.field_specs(args.pool, 4, 64 << 10, 256 << 20)
+    master, relm = make_masters(4, N=256)
+    pool = []
+    for i, sp in enumerate(specs):
+        x = synth.field_data(sp, master, relm, 40000 + i)
+        xt = torch.from_numpy(x).cuda()
+        tdt = xt.dtype
+        # the payload processed alone once: expected bytes for the mix
+        buf, nb = lcq.quantize(xt, sp["q"], sp["eb"])
+        torch.cuda.synchronize()
+        size = int(nb.item())
+        st = buf[:size].clone()
+        del buf
+        dec = lcq.dequantize(st, tdt, x.size, stream_bytes=size)
+        pool.append(dict(spec=sp, tdt=tdt, x=xt, stream=st, size=size,
+                         dec=dec.view(torch.uint8)))
+    torch.cuda.synchronize()
+    log(f"serving pool of {len(pool)} payloads ready in {time.time() - t0:.1f}s")
+    arr = synth.poisson_arrivals(args.rate, args.serve_seconds, 5)
+    rng = np.random.default_rng(6)
+    reqs, in_bytes = [], 0
+    for t in arr:
+        p = pool[int(rng.integers(0, len(pool)))]
+        sp = p["spec"]
+        es = 8 if p["tdt"] == torch.float64 else 4
+        if rng.random() < 0.5:
+            reqs.append(dict(op="quantize", x=p["x"], n=sp["n"], dtype=p["tdt"], q=sp["q"],
+                             eb=sp["eb"], expect=p["stream"], expect_bytes=p["size"],
+                             arrival_ns=int(t)))
+            in_bytes += sp["n"] * es
+        else:
+            reqs.append(dict(op="dequantize", x=p["stream"], n=sp["n"], dtype=p["tdt"],
+                             in_bytes=p["size"], expect=p["dec"], arrival_ns=int(t)))
+            in_bytes += p["size"]
+    arena = torch.empty(int(args.budget_gb * (1 << 30)), dtype=torch.uint8, device="cuda")
+    log(f"serving {len(reqs)} requests over {args.serve_seconds}s")
+    r = serve.run(reqs, n_streams=args.streams, arena=arena)
+    lat = (r["done_ns"] - r["arrival_ns"]) / 1e6
+    qwait = (r["admit_ns"] - r["arrival_ns"]) / 1e6
+    makespan = (r["done_ns"].max() - r["arrival_ns"].min()) / 1e9
+    ok = int(np.sum((r["status"] == 0) & (r["mismatched"] == 0)))
+    res = {
+        "workload": f"Poisson {args.rate}/s for {args.serve_seconds}s, 50/50 quantize/"
+                    "dequantize, 64 KiB-256 MiB log-uniform, 70% float32, random "
+                    f"ABS/REL/NOA, eb [1e-5,1e-1]; pool of {len(pool)} resident payloads; "
+                    f"{args.budget_gb} GB admission budget, {args.streams} streams",
+        "requests": len(reqs), "GBs": round(in_bytes / makespan / 1e9, 2),
+        "offered_GBs": round(in_bytes / args.serve_seconds / 1e9, 2),
+        "p50_ms": round(float(np.percentile(lat, 50)), 4),
+        "p99_ms": round(float(np.percentile(lat, 99)), 4),
+        "max_ms": round(float(lat.max()), 4),
+        "queue_p99_ms": round(float(np.percentile(qwait, 99)), 4),
+        "outputs_equal_alone": f"{ok}/{len(reqs)}",
+    }
+    del arena, pool, reqs
+    torch.cuda.empty_cache()
+    return res
+
+
+# ------------------------------------------------------------ CPU baseline --
+def cpu_baseline_leg(x, xr, eb, plain, batch_sample):
+    """The CPU oracle, single thread, timed on the plain step's three fields
+    (quantize + dequantize each); its streams also check the GPU's."""
+    import numpy as np
+    import oracle
+    n = x.size
+    tsum, parity = 0.0, {}
+    for q, arr in (("abs", x), ("noa", x), ("rel", xr)):
+        t0 = time.perf_counter()
+        st = oracle.quantize(q, arr, eb)
+        t1 = time.perf_counter()
+        dec = oracle.dequantize(st, np.float32, n)
+        t2 = time.perf_counter()
+        tsum += t2 - t0
+        g = plain["gpu_streams"][q]
+        parity[q] = bool(g.size == st.size and np.array_equal(g, st) and
+                         np.array_equal(plain["gpu_decodes"][q].view(np.uint32), dec.view(np.uint32)))
+        del st, dec
+    bparity = 0
+    for sp, xv, gs in batch_sample:
+        bparity += int(np.array_equal(oracle.quantize(sp["q"], xv, sp["eb"]), gs))
+    base = {"value": round(3 * n * 4 / tsum / 1e9, 4), "unit": "GB/s", "cores": 1, "kind": "oracle",
+            "sample": f"the plain step's three fields ({n} float32 values each): one "
+                      "single-threaded oracle quantize + dequantize per field"}
+    return base, parity, f"{bparity}/{len(batch_sample)}"
 
 
 def main():
@@ -64,139 +347,62 @@ def main():
     ap.add_argument("--grid", type=int, default=512)
     ap.add_argument("--eb", type=float, default=1e-3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-verify", action="store_true")
     ap.add_argument("--no-tune", action="store_true",
                     help="skip the launch-shape autotuner (use variant 0)")
+    ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--fields", type=int, default=2000)
+    ap.add_argument("--batch-reps", type=int, default=5)
+    ap.add_argument("--pool", type=int, default=256)
+    ap.add_argument("--rate", type=float, default=2000.0)
+    ap.add_argument("--serve-seconds", type=float, default=60.0)
+    ap.add_argument("--budget-gb", type=float, default=64.0)
+    ap.add_argument("--streams", type=int, default=8)
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build measures one GPU; the quantizer path has no "
-                          "multi-GPU form here (see DESIGN.md for how it would shard)",
+                          "multi-GPU form here (DESIGN.md describes how it would shard)",
                           "n_gpus": args.gpus}))
         sys.exit(2)
 
-    import numpy as np
     import torch
-    import paper_2407_15037_amd as lcq
-
-    dev = torch.device("cuda:0")
-    eb = args.eb
     tuned = None
     if not args.no_tune:
         from paper_2407_15037_amd import autotune
         tuned = autotune.tune(log=log)
-    x, xr = make_inputs(args.grid, eb)
-    n = x.size
-    s = 4
-    fields = [("abs", x), ("noa", x), ("rel", xr)]
-    dx = {"abs": torch.from_numpy(x).to(dev)}
-    dx["noa"] = dx["abs"]
-    dx["rel"] = torch.from_numpy(xr).to(dev)
-    cap = lcq.max_stream_bytes(torch.float32, n)
-    bufs = {q: torch.empty(cap, dtype=torch.uint8, device=dev) for q, _ in fields}
-    nbs = {q: torch.zeros(1, dtype=torch.int64, device=dev) for q, _ in fields}
-    ws = {q: torch.empty(lcq.workspace_bytes(q, torch.float32, n), dtype=torch.uint8, device=dev)
-          for q, _ in fields}
-    outs = {q: torch.empty(n, dtype=torch.float32, device=dev) for q, _ in fields}
-    torch.cuda.synchronize()
-
-    order_q = ["abs", "noa", "rel"]
-    ev = {}
-
-    def step(record):
-        for q in order_q:
-            if record:
-                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-                e0.record(); e1.record()  # create the events before handing them over
-                lcq.profile_events(e0, e1)
-                ev.setdefault(("q", q), []).append((e0, e1))
-            lcq.quantize(dx[q], q, eb, out=bufs[q], nbytes=nbs[q], ws=ws[q])
-        for q in order_q:
-            if record:
-                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-                e0.record(); e1.record()
-                lcq.profile_events(e0, e1)
-                ev.setdefault(("d", q), []).append((e0, e1))
-            lcq.dequantize(bufs[q], torch.float32, n, out=outs[q], ws=ws[q])
-        lcq.profile_events(None, None)
-
-    for _ in range(args.warmup):
-        step(False)
-    torch.cuda.synchronize()
-    t_start = torch.cuda.Event(enable_timing=True)
-    t_end = torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    t_start.record()
-    for _ in range(args.steps):
-        step(True)
-    t_end.record()
-    torch.cuda.synchronize()
-    total_ms = t_start.elapsed_time(t_end)
-    ms_per_step = total_ms / args.steps
-
-    sizes = {q: int(nbs[q].item()) for q, _ in fields}
-    ks = {}
-    for q, _ in fields:
-        hdr = bufs[q][:64].cpu().numpy()
-        ks[q] = int(hdr[16:24].view(np.uint64)[0])
-
-    kern = {}
-    for (kind, q), pairs in ev.items():
-        ms = [a.elapsed_time(b) for a, b in pairs]
-        avg = sum(ms) / len(ms)
-        nbytes = (alg_bytes_quant if kind == "q" else alg_bytes_dequant)(n, s, ks[q])
-        kern[f"{'quantize' if kind == 'q' else 'dequantize'}_{q}"] = {
-            "avg_us": avg * 1e3, "alg_bytes": nbytes, "gbs_hbm": nbytes / (avg * 1e-3) / 1e9,
-            "gbs_input": n * s / (avg * 1e-3) / 1e9}
+    x, xr = make_plain_inputs(args.grid, args.eb)
+    plain = run_plain(args, x, xr)
+    kern = plain["kern"]
     dom_name = max(kern, key=lambda k: kern[k]["avg_us"])
     dom = kern[dom_name]
-    total_input = n * s * len(fields)
-    value = total_input / (ms_per_step * 1e-3) / 1e9
-
     result = {
-        "metric": METRIC, "value": round(value, 2), "unit": "GB/s", "n_gpus": 1,
-        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4),
+        "metric": METRIC, "value": round(plain["value"], 2), "unit": "GB/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(plain["ms_per_step"], 4),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": f"grf{args.grid}^3 float32, 0.01% specials; ABS+NOA eb={eb}, "
-                               f"REL eb={eb} on lognormal variant; quantize+dequantize each",
-                   "n": n, "eb": eb, "quantizers": order_q},
+        "config": {"workload": f"grf{args.grid}^3 float32, 0.01% specials; ABS+NOA eb={args.eb}, "
+                               f"REL eb={args.eb} on lognormal variant; quantize+dequantize each",
+                   "n": plain["n"], "eb": args.eb, "quantizers": ["abs", "noa", "rel"]},
         "ops": {k: {"us": round(v["avg_us"], 2), "input_GBs": round(v["gbs_input"], 1),
                     "alg_GBs": round(v["gbs_hbm"], 1)} for k, v in sorted(kern.items())},
-        "outlier_fraction": {q: ks[q] / n for q in order_q},
-        "stream_bytes": sizes,
+        "outlier_fraction": {q: plain["ks"][q] / plain["n"] for q in plain["ks"]},
+        "stream_bytes": plain["sizes"],
         "autotune": tuned,
         "roofline": {"kernel": dom_name, "bound": "hbm", "achieved": round(dom["gbs_hbm"], 1),
                      "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(dom["gbs_hbm"] / HBM_PEAK_GBS, 4), "traffic": None,
-                     "alg_bytes_per_launch": dom["alg_bytes"], "avg_launch_us": round(dom["avg_us"], 2)},
+                     "alg_bytes_per_launch": dom["alg_bytes"],
+                     "avg_launch_us": round(dom["avg_us"], 2)},
     }
-
-    if not args.no_verify or not args.no_cpu_baseline:
-        import oracle
-        cpu = {}
-        parity = {}
-        for q, arr in fields:
-            t0 = time.perf_counter()
-            st = oracle.quantize(q, arr, eb)
-            t1 = time.perf_counter()
-            dec = oracle.dequantize(st, np.float32, n)
-            t2 = time.perf_counter()
-            cpu[q] = (t1 - t0, t2 - t1)
-            if not args.no_verify:
-                g = bufs[q][: sizes[q]].cpu().numpy()
-                gd = outs[q].cpu().numpy()
-                parity[q] = bool(g.size == st.size and np.array_equal(g, st)
-                                 and np.array_equal(gd.view(np.uint32), dec.view(np.uint32)))
-            del st, dec
-        if not args.no_cpu_baseline:
-            tsum = sum(a + b for a, b in cpu.values())
-            result["cpu_baseline"] = {
-                "value": round(total_input / tsum / 1e9, 4), "unit": "GB/s", "cores": 1,
-                "kind": "oracle",
-                "sample": f"the full step's three fields ({n} float32 values each), one "
-                          "single-threaded oracle quantize + dequantize per field"}
-        if not args.no_verify:
-            result["parity_vs_oracle"] = parity
+    sample = []
+    if not args.no_batched:
+        result["batched"], sample = run_batched(args)
+    if not args.no_serving:
+        result["serving"] = run_serving(args)
+    if not args.no_cpu_baseline:
+        base, parity, bpar = cpu_baseline_leg(x, xr, args.eb, plain, sample)
+        result["cpu_baseline"] = base
+        result["parity_vs_oracle"] = {"plain": parity, "batched_sample": bpar}
     print(json.dumps(result), flush=True)
 
 
