@@ -1,0 +1,99 @@
+"""Exhaustive float32 sweep (the paper tests its quantizers on all 2^32 float32
+values at several bounds, section 6): every bit pattern goes through the GPU
+quantize + dequantize of ABS, REL and NOA at eb in {1e-1, 1e-3, 1e-5, 1e-7};
+every decoded value must satisfy its bound (special values bit-exact), and
+the GPU stream of every 2^28-value chunk must equal the CPU oracle's (compared
+by digest, oracle chunks run in a process pool).
+
+Opt-in: runs only with LCQ_EXHAUSTIVE=1 (about 10 minutes on one MI355X machine
+with 16 host cores); the default GPU suite skips it.
+"""
+import hashlib
+import os
+from concurrent.futures import ProcessPoolExecutor
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+CHUNK = 1 << 28
+EBS = [1e-1, 1e-3, 1e-5, 1e-7]
+
+
+def _host_chunk(c):
+    return (np.arange(c * CHUNK, (c + 1) * CHUNK, dtype=np.uint64) & 0xFFFFFFFF).astype(
+        np.uint32).view(np.float32)
+
+
+def _oracle_digest(args):
+    q, eb, c = args
+    import oracle as O
+    st = O.quantize(q, _host_chunk(c), eb)
+    return hashlib.blake2b(st.tobytes(), digest_size=16).hexdigest()
+
+
+def _gpu_check(q, eb, c, lcq, torch):
+    """Quantize + dequantize chunk c on the GPU; returns (digest, violations,
+    outliers)."""
+    base = torch.arange(c * CHUNK, (c + 1) * CHUNK, dtype=torch.int64, device="cuda")
+    xb = (base & 0xFFFFFFFF).to(torch.int32)
+    del base
+    x = xb.view(torch.float32)
+    buf, nb = lcq.quantize(x, q, eb)
+    torch.cuda.synchronize()
+    size = int(nb.item())
+    dec = lcq.dequantize(buf, torch.float32, CHUNK, stream_bytes=size)
+    u = xb.view(torch.int32).to(torch.int64) & 0xFFFFFFFF
+    e = (u >> 23) & 0xFF
+    frac = u & 0x7FFFFF
+    special = (e == 255) | ((e == 0) & (frac != 0))
+    if q == "rel":
+        special = special | (e == 0)
+    db = dec.view(torch.int32)
+    bad = int(((db != xb) & special).sum().item())
+    fin = ~special
+    x64 = x.double()
+    d64 = dec.double()
+    if q == "abs":
+        # |x - x'| is exact in float64 for float32 operands this close
+        viol = fin & ((x64 - d64).abs() > eb)
+    elif q == "noa":
+        f = x[torch.isfinite(x)].double()
+        R = float(f.max().item()) - float(f.min().item()) if f.numel() else 0.0
+        bound = eb * R
+        viol = fin & ((x64 - d64).abs() > bound)
+    else:
+        a = x64.abs()
+        ad = d64.abs()
+        same_sign = torch.signbit(x) == torch.signbit(dec)
+        viol = fin & (~same_sign | (ad > a * (1 + eb) * (1 + 2 ** -50)) |
+                      (ad * (1 + eb) < a * (1 - 2 ** -50)) | (dec == 0))
+    nviol = int(viol.sum().item()) + bad
+    k = int(buf[16:24].cpu().numpy().view(np.uint64)[0])
+    host = buf[:size].cpu().numpy()
+    return hashlib.blake2b(host.tobytes(), digest_size=16).hexdigest(), nviol, k
+
+
+@pytest.mark.skipif(os.environ.get("LCQ_EXHAUSTIVE") != "1",
+                    reason="opt-in exhaustive float32 sweep (set LCQ_EXHAUSTIVE=1)")
+@pytest.mark.timeout(3000)
+@pytest.mark.parametrize("q", ["abs", "rel", "noa"])
+def test_all_float32_values(q):
+    import torch
+    import paper_2407_15037_amd as lcq
+    nchunks = (1 << 32) // CHUNK
+    jobs = [(q, eb, c) for eb in EBS for c in range(nchunks)]
+    workers = min(16, os.cpu_count() or 1)
+    with ProcessPoolExecutor(workers) as ex:
+        futs = {j: ex.submit(_oracle_digest, j) for j in jobs}
+        total_k = 0
+        for j in jobs:
+            _, eb, c = j
+            print(f"[exhaustive] {q} eb={eb} chunk {c}/{nchunks}", flush=True)
+            dg, nviol, k = _gpu_check(q, eb, c, lcq, torch)
+            total_k += k
+            assert nviol == 0, (q, eb, c, nviol)
+            assert dg == futs[j].result(), (q, eb, c, "GPU stream differs from the oracle's")
+    print(f"[exhaustive] {q}: all 2^32 values x {len(EBS)} bounds, 0 violations, "
+          f"GPU == oracle, {total_k} lossless values", flush=True)
