@@ -471,7 +471,22 @@ __device__ void block_minmax(const T *in, uint64_t begin, uint64_t end, T &lo, T
   // begin is a multiple of W (slices are whole vectors); the tail is scalar
   const uint64_t vb = begin / W, ve = end / W;
   const V *vin = reinterpret_cast<const V *>(in);
-  for (uint64_t i = vb + threadIdx.x; i < ve; i += kBlock) {
+  // eight 128-bit loads in flight per thread, then the remainder one by one
+  constexpr int U = 8;
+  uint64_t i = vb + threadIdx.x;
+  for (; i + (U - 1) * kBlock < ve; i += U * kBlock) {
+    V v[U];
+#pragma unroll
+    for (int u = 0; u < U; u++) v[u] = vin[i + u * kBlock];
+#pragma unroll
+    for (int u = 0; u < U; u++) {
+      T x[W];
+      __builtin_memcpy(x, &v[u], sizeof(V));
+#pragma unroll
+      for (int e = 0; e < W; e++) take(x[e]);
+    }
+  }
+  for (; i < ve; i += kBlock) {
     V v = vin[i];
     T x[W];
     __builtin_memcpy(x, &v, sizeof(V));
