@@ -90,7 +90,8 @@ struct BatchQArgs {
   unsigned *done;
   uint64_t *state;
   uint8_t *partials;
-  unsigned spin_limit;
+  unsigned spin_limit;   // look-back polls before a predecessor is counted directly
+  unsigned ready_polls;  // NOA parameter-flag polls before deriving them directly
 };
 
 template <typename T>
@@ -158,22 +159,40 @@ __device__ void tile_item(const BatchQArgs &a, const BField &bf, uint64_t tile) 
 #pragma unroll
   for (int i = 0; i < 8; i++) f.hdr[i] = bf.hdr[i];
   if constexpr (Q == kNOA) {
+    // Wait for the field's parameters.  Every range item of the field left
+    // the queue before this tile and never waits, so the flag comes; the
+    // wait is bounded all the same: past the bound this workgroup derives
+    // the same parameters from the whole field itself (min / max do not
+    // depend on order).
     DevParams *dp = a.params + bf.noa_idx;
     __shared__ int s_ready;
+    __shared__ DevParams s_dp;
     if (threadIdx.x == 0) {
-      while (__hip_atomic_load(&dp->ready, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == 0)
+      int r = __hip_atomic_load(&dp->ready, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+      for (unsigned polls = 0; r == 0 && polls < a.ready_polls; polls++) {
         __builtin_amdgcn_s_sleep(2);
-      s_ready = 1;
+        r = __hip_atomic_load(&dp->ready, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+      }
+      s_ready = r;
     }
     __syncthreads();
-    (void)s_ready;
     DevParams d;
-    d.step = __hip_atomic_load(&dp->step, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    d.inv = __hip_atomic_load(&dp->inv, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    d.bound = __hip_atomic_load(&dp->bound, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    d.lo = __hip_atomic_load(&dp->lo, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    d.hi = __hip_atomic_load(&dp->hi, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    d.lossless_all = __hip_atomic_load(&dp->lossless_all, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (s_ready) {
+      d.step = __hip_atomic_load(&dp->step, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      d.inv = __hip_atomic_load(&dp->inv, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      d.bound = __hip_atomic_load(&dp->bound, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      d.lo = __hip_atomic_load(&dp->lo, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      d.hi = __hip_atomic_load(&dp->hi, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      d.lossless_all =
+          __hip_atomic_load(&dp->lossless_all, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    } else {
+      T lo, hi;
+      block_minmax<T>(static_cast<const T *>(bf.in), 0, bf.n, lo, hi);
+      if (threadIdx.x == 0)
+        s_dp = noa_params<T>(lo, hi, from_bits((typename FT<T>::U)bf.eb_down));
+      __syncthreads();
+      d = s_dp;
+    }
     f.p = params_from<T>(d);
     f.hdr[4] = d.step;
     f.hdr[5] = d.bound;
@@ -488,6 +507,7 @@ lcq_status lcq_batch_plan_create(const lcq_field *f, uint32_t nf, const char *tu
   qa.state = reinterpret_cast<uint64_t *>(ws + L.state);
   qa.partials = ws + L.partials;
   qa.spin_limit = g_spin_limit.load();
+  qa.ready_polls = g_spin_limit.load() ? (1u << 15) : 0u;
   BatchDArgs da{};
   da.fields = qa.fields;
   da.items = reinterpret_cast<const uint64_t *>(ws + L.items_d);

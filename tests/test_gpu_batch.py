@@ -86,3 +86,28 @@ def test_batch_dequant_reports_bad_field():
     plan.dequantize()
     assert plan.first_bad_field() == 2
     plan.close()
+
+
+def test_batch_fallback_paths_same_bytes():
+    """With the look-back and NOA-parameter waits forced to fall back at once
+    (every wait recomputes what it waits for from the input), the batch still
+    produces the oracle's bytes."""
+    import torch
+    import paper_2407_15037_amd as lcq
+    from paper_2407_15037_amd.batch import BatchPlan
+    fl = _fields(300, 24, 100000)
+    dev_fields = [dict(x=torch.from_numpy(f["x_np"]).cuda(), q=f["q"], eb=f["eb"]) for f in fl]
+    try:
+        lcq.set_lookback_spin(0)
+        announce("batch fallback plan")
+        plan = BatchPlan(dev_fields, variant=2)
+    finally:
+        lcq.set_lookback_spin(4096)
+    plan.quantize()
+    torch.cuda.synchronize()
+    for i, (f, d) in enumerate(zip(fl, plan.fields)):
+        size = int(d["nbytes"].item())
+        got = d["stream"][:size].cpu().numpy()
+        want = O.quantize(f["q"], f["x_np"], f["eb"])
+        assert first_diff(got, want) is None, f"field {i}"
+    plan.close()
