@@ -358,6 +358,9 @@ def main():
     ap.add_argument("--serve-seconds", type=float, default=60.0)
     ap.add_argument("--budget-gb", type=float, default=64.0)
     ap.add_argument("--streams", type=int, default=8)
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="first run three 512 MiB device-to-device copies (a plain copy "
+                         "kernel of known size, to scale hardware byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build measures one GPU; the quantizer path has no "
@@ -366,6 +369,14 @@ def main():
         sys.exit(2)
 
     import torch
+    if args.calib_copy:
+        src = torch.ones(128 << 20, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+        log("calibration copies: 3 x 512 MiB read + 512 MiB written")
     tuned = None
     if not args.no_tune:
         from paper_2407_15037_amd import autotune
