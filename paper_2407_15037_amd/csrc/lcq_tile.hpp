@@ -193,7 +193,7 @@ __device__ void quant_tile(const QField<T> &f, uint64_t tile, unsigned spin_limi
   int32_t *codes = reinterpret_cast<int32_t *>(f.stream + 64);
 
   uint64_t omask = 0;
-#pragma unroll
+#pragma unroll 1
   for (int r = 0; r < ROUNDS; r++) {
     V v[SLOTS];
 #pragma unroll
@@ -352,7 +352,7 @@ __device__ void dequant_tile(const DField<T> &f, uint64_t tile) {
   const U *outl = reinterpret_cast<const U *>(f.stream + outlier_offset(n));
 
   uint64_t omask = 0;
-#pragma unroll
+#pragma unroll 1
   for (int r = 0; r < ROUNDS; r++) {
     int4 c[SLOTS];
 #pragma unroll
