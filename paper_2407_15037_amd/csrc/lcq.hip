@@ -28,7 +28,7 @@
 #pragma clang fp contract(off)
 
 namespace lcq {
-std::atomic<int> g_variant[2][2] = {{{0}, {0}}, {{0}, {0}}};
+std::atomic<int> g_variant[2][2] = {{{1}, {1}}, {{0}, {0}}};  // [op][dtype]
 std::atomic<unsigned> g_spin_limit{4096};
 }  // namespace lcq
 
@@ -44,7 +44,7 @@ namespace {
 constexpr uint64_t kWsParams = 64;
 constexpr uint64_t kWsState = 256;
 constexpr int kMinmaxBlocks = 2048;
-constexpr uint64_t kMinTileF32 = 4096, kMinTileF64 = 2048;  // smallest tile of any variant
+constexpr uint64_t kMinTileF32 = 4096, kMinTileF64 = 2048;  // smallest quantize tile of any variant
 
 thread_local hipEvent_t g_ev_before = nullptr, g_ev_after = nullptr;
 std::atomic<uint64_t> g_epoch{0};
@@ -91,10 +91,10 @@ __device__ __forceinline__ QField<T> plain_field(const PlainQ &a) {
   return f;
 }
 
-template <typename T, int Q, int SL, int RD>
+template <typename T, int Q, int SL, int RD, int DP, bool UR>
 __global__ __launch_bounds__(kBlock) void k_quantize(PlainQ a) {
   const QField<T> f = plain_field<T, Q>(a);
-  quant_tile<T, Q, SL, RD>(f, blockIdx.x, a.spin_limit);
+  quant_tile<T, Q, SL, RD, DP, UR>(f, blockIdx.x, a.spin_limit);
 }
 
 // Header-only stream (n = 0).
@@ -211,29 +211,41 @@ uint64_t ws_need(lcq_quantizer q, lcq_dtype t, uint64_t n) {
 
 lcq_status check_launch() { return hipGetLastError() == hipSuccess ? LCQ_OK : LCQ_ERR_HIP; }
 
-template <typename T, int Q, int SL, int RD>
+template <typename T, int Q, int V>
 void launch_quantize(const PlainQ &a, hipStream_t s) {
-  hipLaunchKernelGGL((k_quantize<T, Q, SL, RD>), dim3((unsigned)a.ntiles), dim3(kBlock), 0, s, a);
+  constexpr QShape sh = kQVariants[V];
+  hipLaunchKernelGGL((k_quantize<T, Q, sh.slots, sh.rounds, sh.depth, sh.unroll>),
+                     dim3((unsigned)a.ntiles), dim3(kBlock), 0, s, a);
 }
 
 template <typename T, int Q>
 void launch_quantize_variant(int v, const PlainQ &a, hipStream_t s) {
   switch (v) {
-    case 1: return launch_quantize<T, Q, kVariants[1].slots, kVariants[1].rounds>(a, s);
-    case 2: return launch_quantize<T, Q, kVariants[2].slots, kVariants[2].rounds>(a, s);
-    case 3: return launch_quantize<T, Q, kVariants[3].slots, kVariants[3].rounds>(a, s);
-    default: return launch_quantize<T, Q, kVariants[0].slots, kVariants[0].rounds>(a, s);
+    case 1: return launch_quantize<T, Q, 1>(a, s);
+    case 2: return launch_quantize<T, Q, 2>(a, s);
+    case 3: return launch_quantize<T, Q, 3>(a, s);
+    case 4: return launch_quantize<T, Q, 4>(a, s);
+    case 5: return launch_quantize<T, Q, 5>(a, s);
+    default: return launch_quantize<T, Q, 0>(a, s);
   }
+}
+
+template <typename T, int V>
+void launch_dequantize(uint64_t ntiles, const PlainD &a, hipStream_t s) {
+  constexpr Shape sh = kDVariants[V];
+  hipLaunchKernelGGL((k_dequantize<T, sh.slots, sh.rounds>), dim3((unsigned)ntiles), dim3(kBlock),
+                     0, s, a);
 }
 
 template <typename T>
 void launch_dequantize_variant(int v, uint64_t ntiles, const PlainD &a, hipStream_t s) {
-  const dim3 g((unsigned)ntiles), b(kBlock);
   switch (v) {
-    case 1: hipLaunchKernelGGL((k_dequantize<T, kVariants[1].slots, kVariants[1].rounds>), g, b, 0, s, a); break;
-    case 2: hipLaunchKernelGGL((k_dequantize<T, kVariants[2].slots, kVariants[2].rounds>), g, b, 0, s, a); break;
-    case 3: hipLaunchKernelGGL((k_dequantize<T, kVariants[3].slots, kVariants[3].rounds>), g, b, 0, s, a); break;
-    default: hipLaunchKernelGGL((k_dequantize<T, kVariants[0].slots, kVariants[0].rounds>), g, b, 0, s, a); break;
+    case 1: return launch_dequantize<T, 1>(ntiles, a, s);
+    case 2: return launch_dequantize<T, 2>(ntiles, a, s);
+    case 3: return launch_dequantize<T, 3>(ntiles, a, s);
+    case 4: return launch_dequantize<T, 4>(ntiles, a, s);
+    case 5: return launch_dequantize<T, 5>(ntiles, a, s);
+    default: return launch_dequantize<T, 0>(ntiles, a, s);
   }
 }
 

@@ -1,18 +1,16 @@
 // lcq_batch.hip -- batched quantize / dequantize of many fields of uneven
 // size, mixed dtype, quantizer and bound in one graph launch.
 //
-// Quantize: one persistent kernel (grid = resident workgroups) pulls work
-// items from a device-side queue with an atomic head.  The queue holds, in
-// order: the NOA range slices of every NOA field (phase A), then every
-// quantize tile of every field (phase B), each field's tiles in increasing
-// order.  A phase-A item reduces its slice's finite min / max; the field's
-// last slice to finish derives the field's parameters on the device and
-// raises the field's ready flag.  A phase-B item of a NOA field waits for
-// that flag (all phase-A items were taken from the queue earlier and never
-// wait, so the wait ends), then runs the same quant_tile as the plain path;
-// the outlier-offset look-back runs inside each field.  Each workgroup takes
-// its next item from the queue before it starts the current one, so the
-// atomic's latency overlaps the work.
+// Quantize: one kernel over a device-side table of work items, one
+// workgroup per item in table order.  The table holds, in order: the NOA
+// range slices of every NOA field (phase A), then every quantize tile of
+// every field (phase B), each field's tiles in increasing order (largest
+// fields first).  A phase-A item reduces its slice's finite min / max; the
+// field's last slice to finish derives the field's parameters on the device
+// and raises the field's ready flag.  A phase-B item of a NOA field waits for
+// that flag, then runs the same quant_tile as the plain path; the outlier-
+// offset look-back runs inside each field.  Both waits are bounded, with a
+// fallback that computes the awaited value from the input.
 //
 // Dequantize: one kernel with a workgroup per dequantize tile of every field
 // (independent tiles), mapped through an item table.
@@ -77,7 +75,7 @@ struct BField {
 
 // Workspace layout of a plan (byte offsets).
 struct Layout {
-  uint64_t head, fields, items_q, items_d, params, done, state, partials, dstatus, total;
+  uint64_t head, fields, items_q, items_d, params, done, state, partials, dstatus, args, total;
   uint64_t clear_begin, clear_words;  // u64 words zeroed before each quantize
 };
 
@@ -94,8 +92,31 @@ struct BatchQArgs {
   unsigned ready_polls;  // NOA parameter-flag polls before deriving them directly
 };
 
+// Values the caller knows are the same on every lane, moved to scalar
+// registers (so the loads they address become scalar loads).
+template <typename P> __device__ __forceinline__ P *uni_ptr(P *p) {
+  const uint64_t v = reinterpret_cast<uint64_t>(p);
+  const uint64_t lo = __builtin_amdgcn_readfirstlane((unsigned)v);
+  const uint64_t hi = __builtin_amdgcn_readfirstlane((unsigned)(v >> 32));
+  return reinterpret_cast<P *>(lo | (hi << 32));
+}
+// Copy of a descriptor every lane reads at the same address, word by word
+// into scalar registers.  (The kernel writes global memory, so the compiler
+// cannot prove these loads unclobbered and would otherwise keep every field
+// of the descriptor, and everything computed from it, in vector registers.)
+template <typename S> __device__ __forceinline__ S uload(const S *p) {
+  static_assert(sizeof(S) % 4 == 0, "descriptor of whole words");
+  S out;
+  unsigned w[sizeof(S) / 4];
+  __builtin_memcpy(w, p, sizeof(S));
+#pragma unroll
+  for (unsigned k = 0; k < sizeof(S) / 4; k++) w[k] = __builtin_amdgcn_readfirstlane(w[k]);
+  __builtin_memcpy(&out, w, sizeof(S));
+  return out;
+}
+
 template <typename T>
-__device__ void range_item(const BatchQArgs &a, const BField &f, uint64_t slice) {
+__device__ __forceinline__ void range_item(const BatchQArgs &a, const BField &f, uint64_t slice) {
   const uint64_t b = slice * kSlice;
   const uint64_t e = min(b + kSlice, f.n);
   T lo, hi;
@@ -111,7 +132,7 @@ __device__ void range_item(const BatchQArgs &a, const BField &f, uint64_t slice)
     s_last = prev == f.nslices - 1;
   }
   __syncthreads();
-  if (!s_last) return;
+  if (!__builtin_amdgcn_readfirstlane(s_last)) return;
   // the field's range from every slice, then its parameters
   T l2 = (T)INFINITY, h2 = (T)-INFINITY;
   for (uint32_t i = threadIdx.x; i < f.nslices; i += kBlock) {
@@ -147,7 +168,7 @@ __device__ void range_item(const BatchQArgs &a, const BField &f, uint64_t slice)
 }
 
 template <typename T, int Q, int SL, int RD>
-__device__ void tile_item(const BatchQArgs &a, const BField &bf, uint64_t tile) {
+__device__ __forceinline__ void tile_item(const BatchQArgs &a, const BField &bf, uint64_t tile) {
   using U = typename FT<T>::U;
   QField<T> f;
   f.in = static_cast<const T *>(bf.in);
@@ -177,7 +198,7 @@ __device__ void tile_item(const BatchQArgs &a, const BField &bf, uint64_t tile) 
     }
     __syncthreads();
     DevParams d;
-    if (s_ready) {
+    if (__builtin_amdgcn_readfirstlane(s_ready)) {
       d.step = __hip_atomic_load(&dp->step, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       d.inv = __hip_atomic_load(&dp->inv, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       d.bound = __hip_atomic_load(&dp->bound, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -208,37 +229,32 @@ __device__ void tile_item(const BatchQArgs &a, const BField &bf, uint64_t tile) 
   quant_tile<T, Q, SL, RD>(f, tile, a.spin_limit);
 }
 
+// One workgroup per work item, in queue order: the hardware dispatcher hands
+// the item table to the workgroups front to back (range items first, then
+// each field's tiles in increasing order).  No atomic head is needed; every
+// wait inside an item (a NOA field's parameters, a predecessor tile's
+// outlier count) is bounded with a fallback that computes the awaited value
+// from the input, so no dispatch order can stall the grid.
 template <int SL32, int RD32, int SL64, int RD64>
-__global__ __launch_bounds__(kBlock) void k_batch_quantize(BatchQArgs a) {
-  __shared__ unsigned s_cur;
-  unsigned next = 0;
-  if (threadIdx.x == 0) next = atomicAdd(a.head, 1u);
-  while (true) {
-    __syncthreads();  // everyone is done with the previous item
-    if (threadIdx.x == 0) {
-      s_cur = next;
-      if (next < a.n_items) next = atomicAdd(a.head, 1u);  // prefetch the next item
-    }
-    __syncthreads();
-    const unsigned cur = s_cur;
-    if (cur >= a.n_items) break;
-    const uint64_t it = a.items[cur];
-    const BField &f = a.fields[it >> 32];
-    const uint64_t local = it & 0xFFFFFFFFull;
-    if (cur < a.n_a) {
-      if (f.dtype == LCQ_F32) range_item<float>(a, f, local);
-      else range_item<double>(a, f, local);
-      continue;
-    }
-    if (f.dtype == LCQ_F32) {
-      if (f.q == kABS) tile_item<float, kABS, SL32, RD32>(a, f, local);
-      else if (f.q == kREL) tile_item<float, kREL, SL32, RD32>(a, f, local);
-      else tile_item<float, kNOA, SL32, RD32>(a, f, local);
-    } else {
-      if (f.q == kABS) tile_item<double, kABS, SL64, RD64>(a, f, local);
-      else if (f.q == kREL) tile_item<double, kREL, SL64, RD64>(a, f, local);
-      else tile_item<double, kNOA, SL64, RD64>(a, f, local);
-    }
+__global__ __launch_bounds__(kBlock) void k_batch_quantize(const BatchQArgs *ap) {
+  const BatchQArgs a = uload(ap);
+  const unsigned cur = blockIdx.x;
+  const uint64_t it = uload(a.items + cur);
+  const BField f = uload(a.fields + (it >> 32));
+  const uint64_t local = it & 0xFFFFFFFFull;
+  if (cur < a.n_a) {
+    if (f.dtype == LCQ_F32) range_item<float>(a, f, local);
+    else range_item<double>(a, f, local);
+    return;
+  }
+  if (f.dtype == LCQ_F32) {
+    if (f.q == kABS) tile_item<float, kABS, SL32, RD32>(a, f, local);
+    else if (f.q == kREL) tile_item<float, kREL, SL32, RD32>(a, f, local);
+    else tile_item<float, kNOA, SL32, RD32>(a, f, local);
+  } else {
+    if (f.q == kABS) tile_item<double, kABS, SL64, RD64>(a, f, local);
+    else if (f.q == kREL) tile_item<double, kREL, SL64, RD64>(a, f, local);
+    else tile_item<double, kNOA, SL64, RD64>(a, f, local);
   }
 }
 
@@ -330,6 +346,7 @@ Layout layout_for(const Counts &c, uint32_t nf) {
   L.state = o;         o += up256(8 * std::max<uint64_t>(c.states, 1));
   L.clear_begin = 0;
   L.clear_words = o / 8;  // head, params (ready flags), done, status, state
+  L.args = o;          o += up256(sizeof(BatchQArgs));
   L.fields = o;        o += up256(sizeof(BField) * std::max<uint32_t>(nf, 1));
   L.items_q = o;       o += up256(8 * std::max<uint64_t>(c.n_a + c.n_b, 1));
   L.items_d = o;       o += up256(8 * std::max<uint64_t>(c.n_d, 1));
@@ -346,7 +363,7 @@ int parse_variant(const char *tune) {
   return (v >= 0 && v < kNumBatchVariants) ? v : -1;
 }
 
-lcq_status launch_batch_quantize(int bv, const BatchQArgs &a, unsigned grid, hipStream_t s) {
+lcq_status launch_batch_quantize(int bv, const BatchQArgs *a, unsigned grid, hipStream_t s) {
   const dim3 g(grid), b(kBlock);
   switch (bv) {
     case 1: hipLaunchKernelGGL((k_batch_quantize<4, 2, 4, 4>), g, b, 0, s, a); break;
@@ -354,14 +371,6 @@ lcq_status launch_batch_quantize(int bv, const BatchQArgs &a, unsigned grid, hip
     default: hipLaunchKernelGGL((k_batch_quantize<4, 4, 4, 8>), g, b, 0, s, a); break;
   }
   return hipGetLastError() == hipSuccess ? LCQ_OK : LCQ_ERR_HIP;
-}
-
-const void *batch_kernel_ptr(int bv) {
-  switch (bv) {
-    case 1: return (const void *)k_batch_quantize<4, 2, 4, 4>;
-    case 2: return (const void *)k_batch_quantize<4, 1, 4, 2>;
-    default: return (const void *)k_batch_quantize<4, 4, 4, 8>;
-  }
 }
 
 }  // namespace
@@ -485,16 +494,8 @@ lcq_status lcq_batch_plan_create(const lcq_field *f, uint32_t nf, const char *tu
   p->ws = ws;
   p->L = L;
   p->c = c;
-  // persistent grid: every workgroup resident at once
-  int dev = 0, cus = 0, per_cu = 0;
-  (void)hipGetDevice(&dev);
-  (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-  (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, batch_kernel_ptr(bv), kBlock, 0);
-  if (cus <= 0) cus = 256;
-  if (per_cu <= 0) per_cu = 1;
-  uint64_t g = (uint64_t)cus * per_cu;
-  g = std::min<uint64_t>(g, std::max<uint64_t>(c.n_a + c.n_b, 1));
-  p->grid = (unsigned)g;
+  // one workgroup per work item
+  p->grid = (unsigned)(c.n_a + c.n_b);
 
   BatchQArgs qa{};
   qa.fields = reinterpret_cast<const BField *>(ws + L.fields);
@@ -514,7 +515,14 @@ lcq_status lcq_batch_plan_create(const lcq_field *f, uint32_t nf, const char *tu
   da.n_items = c.n_d;
   da.status = reinterpret_cast<unsigned long long *>(ws + L.dstatus);
 
-  // capture: clear + persistent quantize; clear + dequantize
+  if (hipMemcpyAsync(ws + L.args, &qa, sizeof qa, hipMemcpyHostToDevice, stream) != hipSuccess ||
+      hipStreamSynchronize(stream) != hipSuccess) {
+    delete p;
+    return LCQ_ERR_HIP;
+  }
+  const BatchQArgs *qa_dev = reinterpret_cast<const BatchQArgs *>(ws + L.args);
+
+  // capture: clear + quantize; clear + dequantize
   hipStream_t cs;
   if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess) { delete p; return LCQ_ERR_HIP; }
   lcq_status st = LCQ_OK;
@@ -523,7 +531,7 @@ lcq_status lcq_batch_plan_create(const lcq_field *f, uint32_t nf, const char *tu
   if (st == LCQ_OK) {
     hipLaunchKernelGGL(k_batch_clear, dim3(cgrid), dim3(kBlock), 0, cs,
                        reinterpret_cast<uint64_t *>(ws), L.clear_words);
-    if (qa.n_items) st = launch_batch_quantize(bv, qa, p->grid, cs);
+    if (qa.n_items) st = launch_batch_quantize(bv, qa_dev, p->grid, cs);
     if (hipStreamEndCapture(cs, &p->gq) != hipSuccess) st = LCQ_ERR_HIP;
   }
   if (st == LCQ_OK && hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) != hipSuccess) st = LCQ_ERR_HIP;

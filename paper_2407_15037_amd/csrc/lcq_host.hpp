@@ -103,21 +103,30 @@ template <typename T> inline FieldParams<T> field_params(const HostParams &h) {
   return p;
 }
 
-// Launch-shape variants: (slots per round, rounds per tile).  A slot is one
-// 128-bit load per thread of a 256-thread workgroup.
+// Launch-shape variants.  A slot is one 128-bit load per thread of a
+// 256-thread workgroup; a tile is slots x rounds of them.  Quantize variants
+// also choose the look-back depth (loads per lane per round trip) and
+// whether the rounds are unrolled.
 struct Shape {
   int slots, rounds;
 };
-constexpr int kNumVariants = 4;
-constexpr Shape kVariants[kNumVariants] = {{4, 1}, {2, 2}, {4, 2}, {4, 4}};
+struct QShape {
+  int slots, rounds, depth;
+  bool unroll;
+};
+constexpr int kNumVariants = 6;
+constexpr QShape kQVariants[kNumVariants] = {
+    {4, 1, 1, true}, {4, 4, 1, true}, {4, 4, 4, true},
+    {4, 4, 1, false}, {4, 2, 2, true}, {4, 1, 4, true}};
+constexpr Shape kDVariants[kNumVariants] = {{4, 1}, {2, 2}, {4, 2}, {4, 4}, {2, 1}, {8, 1}};
 
 // Values per quantize tile / codes per dequantize tile of a variant.
 inline uint64_t quant_tile_len(lcq_dtype t, int v) {
   const uint64_t w = t == LCQ_F64 ? 2 : 4;
-  return (uint64_t)kBlock * w * kVariants[v].slots * kVariants[v].rounds;
+  return (uint64_t)kBlock * w * kQVariants[v].slots * kQVariants[v].rounds;
 }
 inline uint64_t deq_tile_len(int v) {
-  return (uint64_t)kBlock * 4 * kVariants[v].slots * kVariants[v].rounds;
+  return (uint64_t)kBlock * 4 * kDVariants[v].slots * kDVariants[v].rounds;
 }
 
 // Process-wide tuning: variant per (operation, dtype); 0 = quantize.

@@ -100,30 +100,28 @@ __device__ uint64_t wave_count_tile(const T *in, uint64_t n, uint64_t u, uint64_
 }
 
 // Exclusive outlier prefix of `tile` (> 0) by one wavefront: decoupled
-// look-back.  Each round issues kLookDepth loads per lane, so one memory
-// round trip inspects the kLookDepth * 64 nearest unvisited predecessors
+// look-back.  Each round issues DEPTH loads per lane, so one memory
+// round trip inspects the DEPTH * 64 nearest unvisited predecessors
 // (batch j, lane l: tile pos - 64 j - l); the batches are then taken nearest
 // first, and the look-back ends at the nearest tile that has published its
 // inclusive prefix.  A tile that has published nothing after `spin_limit`
 // polls has its count computed here from its input instead, so the wait
 // ends whatever the dispatch order.
-constexpr int kLookDepth = 8;
-
-template <typename T, int Q>
+template <typename T, int Q, int DEPTH>
 __device__ uint64_t look_back(uint64_t *state, uint64_t tile, uint64_t tile_len, int lane,
                               unsigned spin_limit, const T *in, uint64_t n,
                               const FieldParams<T> &p) {
   uint64_t excl = 0;
   int64_t pos = (int64_t)tile - 1;
   while (true) {
-    uint64_t s[kLookDepth];
+    uint64_t s[DEPTH];
 #pragma unroll
-    for (int j = 0; j < kLookDepth; j++) {
+    for (int j = 0; j < DEPTH; j++) {
       const int64_t idx = pos - 64 * j - lane;
       s[j] = idx >= 0 ? load_state(state + idx) : kFlagIncl;  // before tile 0: prefix 0
     }
 #pragma unroll
-    for (int j = 0; j < kLookDepth; j++) {
+    for (int j = 0; j < DEPTH; j++) {
       const int64_t idx = pos - 64 * j - lane;
       uint64_t sj = s[j];
       for (unsigned polls = 0; (sj >> 62) == 0 && polls < spin_limit; polls++) {
@@ -147,7 +145,7 @@ __device__ uint64_t look_back(uint64_t *state, uint64_t tile, uint64_t tile_len,
       }
       excl += wave_sum(v);
     }
-    pos -= 64 * kLookDepth;
+    pos -= 64 * DEPTH;
   }
 }
 
@@ -174,7 +172,9 @@ __device__ __forceinline__ unsigned wave_scan_slots(const unsigned (*wtot)[kWave
 // verify (sections 2.2, 3.1-3.3), code stores, in-tile outlier ranks, the
 // tile's outlier offset by look-back, chunk-table entries and the outliers'
 // raw bits.  The field's last tile also writes the header and the size.
-template <typename T, int Q, int SLOTS, int ROUNDS>
+// DEPTH: look-back loads per lane per round trip; UNROLL: unroll the rounds
+// (more loads in flight, more registers).
+template <typename T, int Q, int SLOTS, int ROUNDS, int DEPTH = 1, bool UNROLL = true>
 __device__ void quant_tile(const QField<T> &f, uint64_t tile, unsigned spin_limit) {
   using F = FT<T>;
   using U = typename F::U;
@@ -193,8 +193,7 @@ __device__ void quant_tile(const QField<T> &f, uint64_t tile, unsigned spin_limi
   int32_t *codes = reinterpret_cast<int32_t *>(f.stream + 64);
 
   uint64_t omask = 0;
-#pragma unroll 1
-  for (int r = 0; r < ROUNDS; r++) {
+  auto one_round = [&](int r) {
     V v[SLOTS];
 #pragma unroll
     for (int j = 0; j < SLOTS; j++) {
@@ -232,6 +231,13 @@ __device__ void quant_tile(const QField<T> &f, uint64_t tile, unsigned spin_limi
           if (i0 + e < n) codes[i0 + e] = c[e];
       }
     }
+  };
+  if constexpr (UNROLL) {
+#pragma unroll
+    for (int r = 0; r < ROUNDS; r++) one_round(r);
+  } else {
+#pragma unroll 1
+    for (int r = 0; r < ROUNDS; r++) one_round(r);
   }
 
   // ---- in-tile ranks: wave totals per slot, then a scan over slots
@@ -258,7 +264,8 @@ __device__ void quant_tile(const QField<T> &f, uint64_t tile, unsigned spin_limi
       }
     } else {
       if (lane == 0) store_state(f.state + tile, kFlagAgg | tile_total);
-      const uint64_t excl = look_back<T, Q>(f.state, tile, S::TILE, lane, spin_limit, f.in, n, f.p);
+      const uint64_t excl =
+          look_back<T, Q, DEPTH>(f.state, tile, S::TILE, lane, spin_limit, f.in, n, f.p);
       if (lane == 0) {
         store_state(f.state + tile, kFlagIncl | (excl + tile_total));
         s_prefix = excl;
@@ -352,7 +359,7 @@ __device__ void dequant_tile(const DField<T> &f, uint64_t tile) {
   const U *outl = reinterpret_cast<const U *>(f.stream + outlier_offset(n));
 
   uint64_t omask = 0;
-#pragma unroll 1
+#pragma unroll
   for (int r = 0; r < ROUNDS; r++) {
     int4 c[SLOTS];
 #pragma unroll
