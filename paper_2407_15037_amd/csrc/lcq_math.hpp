@@ -71,9 +71,11 @@ template <typename T> LCQ_HD T log2approx(T a) {
 template <typename T> LCQ_HD T pow2approx(T y) {
   using F = FT<T>;
   using U = typename F::U;
+  // clamp to [0, max exponent field]; a (quiet) NaN t becomes 0 because
+  // fmax returns the non-NaN operand -- t is an arithmetic result, never a
+  // signalling NaN
   T t = y + (T)F::kBias;
-  t = (t >= (T)0) ? t : (T)0;
-  t = (t > (T)F::kExpMask) ? (T)F::kExpMask : t;
+  t = fmin(fmax(t, (T)0), (T)F::kExpMask);
   const int k = (int)t;
   const T g = t - (T)(k - 1);
   return from_bits((U)(((U)k << F::kMant) | (to_bits(g) & F::kFracMask)));
@@ -111,8 +113,10 @@ template <typename T, int Q> LCQ_HD int32_t encode(T x, const FieldParams<T> &p)
     const int32_t b = (int32_t)(ok ? q : (T)0);
     const T rec = pow2approx((T)b * p.step);
     // section 3.1 double-check against both sides of the section 2.1.2 range
+    // |rec - a| equals (a - rec) when rec < a: round-to-nearest is
+    // symmetric under negation, so one subtraction serves both sides
     const bool up = rec >= a;
-    const T diff = up ? (rec - a) : (a - rec);
+    const T diff = abs_t(rec - a);
     const T lim = (up ? p.bound : p.low) * a;
     ok = ok && (diff < lim);
     const uint32_t code = ((uint32_t)b << 1) | (uint32_t)(u >> (sizeof(T) * 8 - 1));
