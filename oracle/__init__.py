@@ -57,6 +57,12 @@ def _bind(L):
     L.orc_quantize.restype = i32
     L.orc_dequantize.argtypes = [i32, vp, u64, vp, u64]
     L.orc_dequantize.restype = i32
+    L.orc_inline_stream_bytes.argtypes = [i32, u64]
+    L.orc_inline_stream_bytes.restype = u64
+    L.orc_quantize_inline.argtypes = [i32, i32, ctypes.c_double, vp, u64, vp, u64, ctypes.POINTER(u64)]
+    L.orc_quantize_inline.restype = i32
+    L.orc_dequantize_inline.argtypes = [i32, vp, u64, vp, u64]
+    L.orc_dequantize_inline.restype = i32
     for name in ("orc_log2approx_f32", "orc_pow2approx_f32",
                  "orc_log2approx_f64", "orc_pow2approx_f64"):
         getattr(L, name).argtypes = [vp, vp, u64]
@@ -105,6 +111,31 @@ def dequantize(stream, dtype, n, L=None):
     st = L.orc_dequantize(dt, stream.ctypes.data, stream.size, out.ctypes.data, n)
     if st != OK:
         raise OracleError(st, "orc_dequantize")
+    return out
+
+
+def quantize_inline(q, x, eb, L=None):
+    """In-line layout (one word per value + raw-value bitmap)."""
+    L = L or lib()
+    x = np.ascontiguousarray(x)
+    dt = _dt(x)
+    cap = int(L.orc_inline_stream_bytes(dt, x.size))
+    buf = np.zeros(cap, dtype=np.uint8)
+    nbytes = ctypes.c_uint64(0)
+    st = L.orc_quantize_inline(_q(q), dt, float(eb), x.ctypes.data, x.size, buf.ctypes.data, cap,
+                               ctypes.byref(nbytes))
+    if st != OK:
+        raise OracleError(st, "orc_quantize_inline")
+    return buf[: nbytes.value].copy()
+
+
+def dequantize_inline(stream, dtype, n, L=None):
+    L = L or lib()
+    stream = np.ascontiguousarray(stream, dtype=np.uint8)
+    out = np.empty(n, dtype=dtype)
+    st = L.orc_dequantize_inline(_dt(out), stream.ctypes.data, stream.size, out.ctypes.data, n)
+    if st != OK:
+        raise OracleError(st, "orc_dequantize_inline")
     return out
 
 

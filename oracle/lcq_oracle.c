@@ -534,3 +534,117 @@ int orc_dequantize(int dtype, const void *stream, uint64_t bytes, void *out_v,
   if (cursor != k) return ORC_ERR_STREAM;
   return ORC_OK;
 }
+
+/* ------------------------------------------------- in-line outlier format --
+ * The paper's own layout (section 3.1): outliers are stored in-line with the
+ * bin numbers, one word of the field type's width per value, so no scan is
+ * needed.  Here a word holds either the value's code (the same int32 code as
+ * above, sign-extended to the word) or, for a value stored losslessly, its
+ * raw bits; a bitmap with one bit per value tells which.
+ *
+ *   [0,64)              header: u32 magic "LCQI", u8 version 1, u8 dtype,
+ *                       u8 quantizer, u8 0, u64 n, u64 0, f64 eb as passed,
+ *                       then step, bound, aux0, aux1 as in the format above
+ *   [64, 64 + n*s)      one word per value
+ *   fl = align16(64+n*s) ceil(n/8) bytes: bit (i % 8) of byte i/8 set when
+ *                       value i is stored raw
+ *   total size = fl + ceil(n/8); every padding or unused bit is zero
+ */
+#define MAGIC_INLINE 0x4951434Cu /* bytes 'L','C','Q','I' */
+
+uint64_t orc_inline_stream_bytes(int dtype, uint64_t n) {
+  uint64_t s = dtype == ORC_F64 ? 8 : 4;
+  return align16(64 + s * n) + (n + 7) / 8;
+}
+
+int orc_quantize_inline(int q, int dtype, double eb, const void *in, uint64_t n,
+                        void *stream, uint64_t cap, uint64_t *stream_bytes) {
+  if (!fpenv_ok()) return ORC_ERR_FPENV;
+  int st = check_args(q, dtype, eb);
+  if (st) return st;
+  if (!stream || !stream_bytes || (n > 0 && !in)) return ORC_ERR_ARG;
+  if (n > (1ull << 38)) return ORC_ERR_ARG;
+  const uint64_t total = orc_inline_stream_bytes(dtype, n);
+  if (cap < total) return ORC_ERR_CAPACITY;
+  const uint64_t s = dtype == ORC_F64 ? 8 : 4;
+  uint8_t *S = (uint8_t *)stream;
+  const uint64_t fl = align16(64 + s * n);
+  memset(S, 0, total);
+
+  params_t p;
+  if (dtype == ORC_F32) derive_f32(q, eb, (const float *)in, n, &p);
+  else derive_f64(q, eb, (const double *)in, n, &p);
+
+  for (uint64_t i = 0; i < n; i++) {
+    int32_t code = 0;
+    int raw;
+    if (dtype == ORC_F32) {
+      float x;
+      memcpy(&x, (const uint8_t *)in + 4 * i, 4);
+      raw = encode_f32(&p, x, &code);
+    } else {
+      double x;
+      memcpy(&x, (const uint8_t *)in + 8 * i, 8);
+      raw = encode_f64(&p, x, &code);
+    }
+    if (raw) {
+      memcpy(S + 64 + s * i, (const uint8_t *)in + s * i, s);
+      S[fl + i / 8] |= (uint8_t)(1u << (i % 8));
+    } else if (s == 4) {
+      memcpy(S + 64 + 4 * i, &code, 4);
+    } else {
+      int64_t w = code;
+      memcpy(S + 64 + 8 * i, &w, 8);
+    }
+  }
+
+  orc_params o;
+  export_params(dtype, &p, &o);
+  put_u32(S + 0, MAGIC_INLINE);
+  S[4] = 1;
+  S[5] = (uint8_t)dtype;
+  S[6] = (uint8_t)q;
+  S[7] = 0;
+  put_u64(S + 8, n);
+  put_u64(S + 16, 0);
+  memcpy(S + 24, &eb, 8);
+  put_u64(S + 32, o.step);
+  put_u64(S + 40, o.bound);
+  put_u64(S + 48, o.aux0);
+  put_u64(S + 56, o.aux1);
+  *stream_bytes = total;
+  return ORC_OK;
+}
+
+int orc_dequantize_inline(int dtype, const void *stream, uint64_t bytes, void *out_v,
+                          uint64_t n) {
+  if (!fpenv_ok()) return ORC_ERR_FPENV;
+  if (dtype != ORC_F32 && dtype != ORC_F64) return ORC_ERR_ARG;
+  if (!stream || (n > 0 && !out_v)) return ORC_ERR_ARG;
+  if (bytes < 64) return ORC_ERR_STREAM;
+  const uint8_t *S = (const uint8_t *)stream;
+  const uint64_t s = dtype == ORC_F64 ? 8 : 4;
+  if (get_u32(S) != MAGIC_INLINE || S[4] != 1 || S[5] != dtype || S[6] > 2 || S[7] != 0)
+    return ORC_ERR_STREAM;
+  if (get_u64(S + 8) != n || bytes < orc_inline_stream_bytes(dtype, n)) return ORC_ERR_STREAM;
+  const int q = S[6];
+  const uint64_t fl = align16(64 + s * n);
+  const uint64_t stepbits = get_u64(S + 32);
+  for (uint64_t i = 0; i < n; i++) {
+    uint8_t *dst = (uint8_t *)out_v + s * i;
+    if (S[fl + i / 8] & (1u << (i % 8))) {
+      memcpy(dst, S + 64 + s * i, s);
+      continue;
+    }
+    int32_t c;
+    memcpy(&c, S + 64 + s * i, 4); /* low word (little-endian) */
+    if (dtype == ORC_F32) {
+      float v = decode_f32(q, from32((uint32_t)stepbits), c);
+      memcpy(dst, &v, 4);
+    } else {
+      double v = decode_f64(q, from64(stepbits), c);
+      memcpy(dst, &v, 8);
+    }
+  }
+  return ORC_OK;
+}

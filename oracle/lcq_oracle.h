@@ -69,6 +69,16 @@ void orc_pow2approx_f32(const float *in, float *out, uint64_t n);
 void orc_log2approx_f64(const double *in, double *out, uint64_t n);
 void orc_pow2approx_f64(const double *in, double *out, uint64_t n);
 
+/* In-line outlier layout (the paper's own, section 3.1): one word of the
+ * field type's width per value -- the value's code, or its raw bits when it
+ * is stored losslessly -- plus one flag bit per value.  Fixed size
+ * orc_inline_stream_bytes(dtype, n). */
+uint64_t orc_inline_stream_bytes(int dtype, uint64_t n);
+int orc_quantize_inline(int q, int dtype, double eb, const void *in, uint64_t n,
+                        void *stream, uint64_t cap, uint64_t *stream_bytes);
+int orc_dequantize_inline(int dtype, const void *stream, uint64_t bytes, void *out,
+                          uint64_t n);
+
 #ifdef __cplusplus
 }
 #endif

@@ -417,8 +417,37 @@ def pin_noa_degenerate(L):
         assert P["hdr"]["step"] == 0 and P["hdr"]["bound"] == 0
 
 
+def pin_inline_format(L):
+    """The in-line layout (section 3.1, the paper's own) carries the same
+    decisions as the pinned separate-list layout: a word is the value's code
+    (sign-extended) where that code is not the sentinel, else the value's raw
+    bits with its flag set; unused bits and padding are zero; it decodes to
+    the same values."""
+    for dt, q, eb, x in _cases():
+        st = O.quantize(q, x, eb, L=L)
+        P = parse(st, dt)
+        il = O.quantize_inline(q, x, eb, L=L)
+        s = np.dtype(dt).itemsize
+        n = x.size
+        hdr = np.frombuffer(il[:64].tobytes(), dtype=np.uint8)
+        assert bytes(hdr[:4]) == b"LCQI" and hdr[4] == 1 and hdr[7] == 0
+        assert np.array_equal(hdr[32:64], np.frombuffer(st[32:64].tobytes(), np.uint8))
+        words = np.frombuffer(il.tobytes(), dtype=np.int32 if s == 4 else np.int64, count=n, offset=64)
+        fl = (64 + s * n + 15) // 16 * 16
+        flags = np.unpackbits(np.frombuffer(il.tobytes(), np.uint8, count=(n + 7) // 8, offset=fl),
+                              bitorder="little")
+        raw = P["codes"] == SENT
+        assert np.array_equal(flags[:n].astype(bool), raw)
+        assert not flags[n:].any()
+        assert np.array_equal(words[~raw], P["codes"][~raw].astype(words.dtype))
+        assert np.array_equal(words[raw].view(bits(x).dtype), bits(x)[raw])
+        assert il.size == fl + (n + 7) // 8 and not il[64 + s * n: fl].any()
+        dec = O.dequantize_inline(il, dt, n, L=L)
+        assert np.array_equal(bits(dec), bits(O.dequantize(st, dt, n, L=L)))
+
+
 PINS = [pin_mitchell_golden, pin_mitchell_powers_of_two, pin_mitchell_log2_error,
         pin_mitchell_log2_monotone, pin_mitchell_pow2_error, pin_params_abs,
         pin_params_rel, pin_params_noa, pin_arg_errors, pin_structure, pin_bounds,
         pin_specials, pin_abs_nearest_bin, pin_rel_nearest_bin, pin_bin_range,
-        pin_roundtrip_sizes, pin_stream_errors, pin_noa_degenerate]
+        pin_roundtrip_sizes, pin_stream_errors, pin_noa_degenerate, pin_inline_format]
