@@ -55,16 +55,9 @@ def header_k(buf):
 
 # ------------------------------------------------------------------- plain --
 def make_plain_inputs(N, eb, seed=1, rel_seed=11, frac=1e-4):
-    import numpy as np
     import synth
     t0 = time.time()
-    g = synth.grf_3d(N, seed, dtype=np.float64)
-    x = g.astype(np.float32)
-    nsp = synth.n_specials(x.size, frac)
-    x, _, _ = synth.inject_specials(x, nsp, seed + 1000, eb)
-    xr = synth.rel_variant(g, rel_seed, dtype=np.float32)
-    del g
-    xr, _, _ = synth.inject_specials(xr, nsp, rel_seed + 1000, eb)
+    x, xr = synth.plain_step_inputs(N, eb, seed, rel_seed, frac)
     log(f"plain inputs {N}^3 generated in {time.time() - t0:.1f}s")
     return x, xr
 

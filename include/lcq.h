@@ -110,6 +110,34 @@ const char *lcq_status_string(lcq_status s);
  * kernel (the per-value pass), on the call's stream.  Pass nulls to clear. */
 void lcq_profile_events(hipEvent_t before, hipEvent_t after);
 
+/* ---------------------------------------------- in-line outlier layout --
+ * The paper's own layout (section 3.1): outliers stored in-line with the
+ * bins.  One word of the field type's width per value -- its code (the same
+ * int32 code as above, sign-extended) or, for a value stored losslessly, its
+ * raw bits -- and one flag bit per value saying which.  Same decisions and
+ * decoded values as the separate-list layout; fixed size, no scan.
+ *   [0,64)   header as above but magic "LCQI" and byte 7 = 0, word 2 = 0
+ *   [64, 64 + n*s)            one word per value
+ *   fl = align16(64 + n*s)    ceil(n/8) bytes; bit i%8 of byte i/8 set when
+ *                             value i is stored raw; unused bits zero
+ *   size = fl + ceil(n/8)
+ */
+uint64_t lcq_inline_stream_bytes(lcq_dtype t, uint64_t n);  /* 0: bad dtype / n */
+uint64_t lcq_inline_workspace_bytes(lcq_quantizer q);      /* 0: bad quantizer */
+
+/* As lcq_quantize, into the in-line layout; stream_cap >=
+ * lcq_inline_stream_bytes(t, n), ws_bytes >= lcq_inline_workspace_bytes(q). */
+lcq_status lcq_quantize_inline(lcq_quantizer q, lcq_dtype t, double eb,
+                               const void *d_in, uint64_t n,
+                               void *d_stream, uint64_t stream_cap,
+                               void *d_ws, uint64_t ws_bytes, hipStream_t stream);
+
+/* As lcq_dequantize, from the in-line layout (header validated on the
+ * device, status in the first 8 bytes of d_ws, read with lcq_stream_status). */
+lcq_status lcq_dequantize_inline(lcq_dtype t, const void *d_stream, uint64_t stream_bytes,
+                                 void *d_out, uint64_t n,
+                                 void *d_ws, uint64_t ws_bytes, hipStream_t stream);
+
 /* ---------------------------------------------------------------- batch --
  * Many fields of uneven size, mixed dtype, quantizer and bound, quantized or
  * dequantized by one graph launch.  Each field's stream and decode are

@@ -11,7 +11,7 @@ import os
 __all__ = ["ABS", "REL", "NOA", "F32", "F64", "LCQError", "lib", "max_stream_bytes",
            "workspace_bytes", "quantize", "dequantize", "stream_status", "profile_events",
            "set_lookback_spin", "tune_variants", "tune_set", "tune_get",
-           "SO_PATH"]
+           "inline_stream_bytes", "quantize_inline", "dequantize_inline", "SO_PATH"]
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 SO_PATH = os.path.join(HERE, "liblcq.so")
@@ -37,6 +37,14 @@ _lib.lcq_quantize.argtypes = [_i32, _i32, _dbl, _vp, _u64, _vp, _u64, _vp, _vp, 
 _lib.lcq_quantize.restype = _i32
 _lib.lcq_dequantize.argtypes = [_i32, _vp, _u64, _vp, _u64, _vp, _u64, _vp]
 _lib.lcq_dequantize.restype = _i32
+_lib.lcq_inline_stream_bytes.argtypes = [_i32, _u64]
+_lib.lcq_inline_stream_bytes.restype = _u64
+_lib.lcq_inline_workspace_bytes.argtypes = [_i32]
+_lib.lcq_inline_workspace_bytes.restype = _u64
+_lib.lcq_quantize_inline.argtypes = [_i32, _i32, _dbl, _vp, _u64, _vp, _u64, _vp, _u64, _vp]
+_lib.lcq_quantize_inline.restype = _i32
+_lib.lcq_dequantize_inline.argtypes = [_i32, _vp, _u64, _vp, _u64, _vp, _u64, _vp]
+_lib.lcq_dequantize_inline.restype = _i32
 _lib.lcq_stream_status.argtypes = [_vp, _vp, ctypes.POINTER(ctypes.c_int32)]
 _lib.lcq_stream_status.restype = _i32
 _lib.lcq_status_string.argtypes = [_i32]
@@ -140,6 +148,47 @@ def dequantize(stream_buf, dtype, n, *, stream_bytes=None, out=None, ws=None, st
     st = _lib.lcq_dequantize(dt, _ptr(stream_buf), sb, _ptr(out) if n else None, n, _ptr(ws),
                              ws.numel(), _stream_handle(stream))
     _check(st, "lcq_dequantize")
+    return out
+
+
+def inline_stream_bytes(dtype, n):
+    return int(_lib.lcq_inline_stream_bytes(_dtype_code(dtype), n))
+
+
+def quantize_inline(x, q, eb, *, out=None, ws=None, stream=None):
+    """Quantize x into the in-line layout (one word per value plus a bitmap
+    of values stored raw).  Returns the stream, a uint8 device tensor of
+    exactly inline_stream_bytes(x.dtype, x.numel()) bytes."""
+    import torch
+    if not x.is_cuda or not x.is_contiguous():
+        raise ValueError("x must be a contiguous CUDA tensor")
+    dt = _dtype_code(x.dtype)
+    n = x.numel()
+    if out is None:
+        out = torch.empty(int(_lib.lcq_inline_stream_bytes(dt, n)), dtype=torch.uint8,
+                          device=x.device)
+    if ws is None:
+        ws = torch.empty(int(_lib.lcq_inline_workspace_bytes(_q(q))), dtype=torch.uint8,
+                         device=x.device)
+    st = _lib.lcq_quantize_inline(_q(q), dt, float(eb), _ptr(x) if n else None, n, _ptr(out),
+                                  out.numel(), _ptr(ws), ws.numel(), _stream_handle(stream))
+    _check(st, "lcq_quantize_inline")
+    return out
+
+
+def dequantize_inline(stream_buf, dtype, n, *, out=None, ws=None, stream=None):
+    """Decode an in-line layout stream into n values; the header check's
+    result lands in ws (read with stream_status)."""
+    import torch
+    dt = _dtype_code(dtype)
+    if out is None:
+        out = torch.empty(n, dtype=dtype, device=stream_buf.device)
+    if ws is None:
+        ws = torch.empty(64, dtype=torch.uint8, device=stream_buf.device)
+    st = _lib.lcq_dequantize_inline(dt, _ptr(stream_buf), stream_buf.numel(),
+                                    _ptr(out) if n else None, n, _ptr(ws), ws.numel(),
+                                    _stream_handle(stream))
+    _check(st, "lcq_dequantize_inline")
     return out
 
 

@@ -161,6 +161,15 @@ __global__ __launch_bounds__(kBlock) void k_noa_params(const T *partials, int np
   *out = noa_params<T>(lo, hi, eb_down);
 }
 
+// In-line layout (the paper's own, section 3.1): a pure map per tile.
+constexpr int kInlineSlots = 4;
+
+template <typename T, int Q>
+__global__ __launch_bounds__(kBlock) void k_quantize_inline(PlainQ a) {
+  const QField<T> f = plain_field<T, Q>(a);
+  quant_tile_inline<T, Q, kInlineSlots>(f, blockIdx.x);
+}
+
 // ------------------------------------------------------------ dequantize ---
 struct PlainD {
   const uint8_t *stream;
@@ -198,6 +207,24 @@ __global__ __launch_bounds__(kBlock) void k_dequantize(PlainD a) {
   f.status = a.status;
   f.tag = tag;
   dequant_tile<T, SL, RD>(f, blockIdx.x);
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_dequantize_inline(PlainD a) {
+  using U = typename FT<T>::U;
+  const uint64_t n = a.n;
+  const uint64_t *hd = reinterpret_cast<const uint64_t *>(a.stream);
+  const uint64_t h0 = hd[0];
+  const int q = (int)((h0 >> 48) & 0xFF);
+  const uint64_t want0 = (uint64_t)kMagicInline | (1ull << 32) | ((uint64_t)a.dtype << 40);
+  const bool bad = (h0 & ~(0xFFull << 48)) != want0 || q > 2 || hd[1] != n ||
+                   inline_stream_bytes(n, sizeof(T)) > a.stream_bytes;
+  const unsigned long long tag = (unsigned long long)(a.epoch << 16);
+  if (blockIdx.x == 0 && threadIdx.x == 0)
+    atomicMax(a.status, tag | (unsigned long long)(bad ? LCQ_ERR_STREAM : LCQ_OK));
+  if (bad || n == 0) return;
+  dequant_tile_inline<T, kInlineSlots>(a.stream, n, from_bits((U)hd[4]), q == kREL,
+                                      static_cast<T *>(a.out), blockIdx.x);
 }
 
 // ----------------------------------------------------------- host side ---
@@ -308,6 +335,56 @@ lcq_status run_quantize(double eb, const void *d_in, uint64_t n, void *d_stream,
   return check_launch();
 }
 
+template <typename T, int Q>
+lcq_status run_quantize_inline(double eb, const void *d_in, uint64_t n, void *d_stream,
+                               void *d_ws, hipStream_t s) {
+  const int dt = sizeof(T) == 8 ? LCQ_F64 : LCQ_F32;
+  const HostParams hp = host_params<T>(Q, eb);
+  uint8_t *ws = static_cast<uint8_t *>(d_ws);
+  PlainQ a{};
+  a.in = d_in;
+  a.n = n;
+  a.stream = static_cast<uint8_t *>(d_stream);
+  a.noa = reinterpret_cast<const DevParams *>(ws + kWsParams);
+  a.step = hp.step;
+  a.inv = hp.inv;
+  a.bound = hp.bound;
+  a.low = hp.low;
+  a.hdr[0] = (uint64_t)kMagicInline | (1ull << 32) | ((uint64_t)dt << 40) | ((uint64_t)Q << 48);
+  a.hdr[1] = n;
+  a.hdr[2] = 0;
+  a.hdr[3] = __builtin_bit_cast(uint64_t, eb);
+  a.hdr[4] = hp.step;
+  a.hdr[5] = hp.bound;
+  a.hdr[6] = hp.aux0;
+  a.hdr[7] = hp.aux1;
+  if (Q == kNOA) {
+    T *partials = reinterpret_cast<T *>(ws + kWsState);
+    const uint64_t W = 16 / sizeof(T);
+    const uint64_t per = (uint64_t)kBlock * W * 8;
+    uint64_t nb = (n + per - 1) / per;
+    nb = nb < 1 ? 1 : (nb > (uint64_t)kMinmaxBlocks ? kMinmaxBlocks : nb);
+    uint64_t share = (n + nb - 1) / nb;
+    share = (share + W - 1) / W * W;
+    hipLaunchKernelGGL(k_minmax<T>, dim3((unsigned)nb), dim3(kBlock), 0, s,
+                       static_cast<const T *>(d_in), n, share, partials, (uint64_t *)nullptr,
+                       (uint64_t)0);
+    hipLaunchKernelGGL(k_noa_params<T>, dim3(1), dim3(kBlock), 0, s, partials, (int)nb,
+                       from_bits((typename FT<T>::U)hp.eb_down),
+                       reinterpret_cast<DevParams *>(ws + kWsParams));
+  }
+  const uint64_t tile = (uint64_t)kBlock * (16 / sizeof(T)) * kInlineSlots;
+  const uint64_t ntiles = n ? (n + tile - 1) / tile : 1;
+  if (g_ev_before) (void)hipEventRecord(g_ev_before, s);
+  hipLaunchKernelGGL((k_quantize_inline<T, Q>), dim3((unsigned)ntiles), dim3(kBlock), 0, s, a);
+  if (g_ev_after) (void)hipEventRecord(g_ev_after, s);
+  return check_launch();
+}
+
+uint64_t ws_need_inline(lcq_quantizer q) {
+  return q == LCQ_NOA ? kWsState + 16ull * kMinmaxBlocks : 8;
+}
+
 }  // namespace
 
 // ------------------------------------------------------------------- ABI ---
@@ -374,6 +451,70 @@ lcq_status lcq_dequantize(lcq_dtype t, const void *d_stream, uint64_t stream_byt
   if (g_ev_before) (void)hipEventRecord(g_ev_before, stream);
   if (t == LCQ_F32) launch_dequantize_variant<float>(v, ntiles, a, stream);
   else launch_dequantize_variant<double>(v, ntiles, a, stream);
+  if (g_ev_after) (void)hipEventRecord(g_ev_after, stream);
+  return check_launch();
+}
+
+uint64_t lcq_inline_stream_bytes(lcq_dtype t, uint64_t n) {
+  if ((t != LCQ_F32 && t != LCQ_F64) || n > LCQ_MAX_N) return 0;
+  return inline_stream_bytes(n, t == LCQ_F64 ? 8 : 4);
+}
+
+uint64_t lcq_inline_workspace_bytes(lcq_quantizer q) {
+  if (q != LCQ_ABS && q != LCQ_REL && q != LCQ_NOA) return 0;
+  return ws_need_inline(q);
+}
+
+lcq_status lcq_quantize_inline(lcq_quantizer q, lcq_dtype t, double eb, const void *d_in,
+                               uint64_t n, void *d_stream, uint64_t stream_cap, void *d_ws,
+                               uint64_t ws_bytes, hipStream_t stream) {
+  if (q != LCQ_ABS && q != LCQ_REL && q != LCQ_NOA) return LCQ_ERR_ARG;
+  if (t != LCQ_F32 && t != LCQ_F64) return LCQ_ERR_ARG;
+  if (!(eb > 0.0) || !std::isfinite(eb) || (q == LCQ_REL && !(eb < 1.0))) return LCQ_ERR_ARG;
+  if (n > LCQ_MAX_N) return LCQ_ERR_ARG;
+  if ((n && !d_in) || !d_stream || !d_ws) return LCQ_ERR_ARG;
+  if ((n && !aligned16(d_in)) || !aligned16(d_stream) || !aligned16(d_ws)) return LCQ_ERR_ARG;
+  if (stream_cap < lcq_inline_stream_bytes(t, n)) return LCQ_ERR_CAPACITY;
+  if (ws_bytes < ws_need_inline(q)) return LCQ_ERR_CAPACITY;
+  if (t == LCQ_F32) {
+    switch (q) {
+      case LCQ_ABS: return run_quantize_inline<float, kABS>(eb, d_in, n, d_stream, d_ws, stream);
+      case LCQ_REL: return run_quantize_inline<float, kREL>(eb, d_in, n, d_stream, d_ws, stream);
+      default: return run_quantize_inline<float, kNOA>(eb, d_in, n, d_stream, d_ws, stream);
+    }
+  }
+  switch (q) {
+    case LCQ_ABS: return run_quantize_inline<double, kABS>(eb, d_in, n, d_stream, d_ws, stream);
+    case LCQ_REL: return run_quantize_inline<double, kREL>(eb, d_in, n, d_stream, d_ws, stream);
+    default: return run_quantize_inline<double, kNOA>(eb, d_in, n, d_stream, d_ws, stream);
+  }
+}
+
+lcq_status lcq_dequantize_inline(lcq_dtype t, const void *d_stream, uint64_t stream_bytes,
+                                 void *d_out, uint64_t n, void *d_ws, uint64_t ws_bytes,
+                                 hipStream_t stream) {
+  if (t != LCQ_F32 && t != LCQ_F64) return LCQ_ERR_ARG;
+  if (n > LCQ_MAX_N) return LCQ_ERR_ARG;
+  if (!d_stream || (n && !d_out) || !d_ws) return LCQ_ERR_ARG;
+  if (!aligned16(d_stream) || (n && !aligned16(d_out)) || !aligned16(d_ws)) return LCQ_ERR_ARG;
+  if (ws_bytes < 8) return LCQ_ERR_CAPACITY;
+  const uint64_t s = t == LCQ_F64 ? 8 : 4;
+  if (stream_bytes < inline_stream_bytes(n, s)) return LCQ_ERR_STREAM;
+  PlainD a{};
+  a.stream = static_cast<const uint8_t *>(d_stream);
+  a.stream_bytes = stream_bytes;
+  a.n = n;
+  a.out = d_out;
+  a.status = static_cast<unsigned long long *>(d_ws);
+  a.epoch = g_epoch.fetch_add(1) + 1;
+  a.dtype = (int)t;
+  const uint64_t tile = (uint64_t)kBlock * (16 / s) * kInlineSlots;
+  const uint64_t ntiles = n ? (n + tile - 1) / tile : 1;
+  if (g_ev_before) (void)hipEventRecord(g_ev_before, stream);
+  if (t == LCQ_F32)
+    hipLaunchKernelGGL(k_dequantize_inline<float>, dim3((unsigned)ntiles), dim3(kBlock), 0, stream, a);
+  else
+    hipLaunchKernelGGL(k_dequantize_inline<double>, dim3((unsigned)ntiles), dim3(kBlock), 0, stream, a);
   if (g_ev_after) (void)hipEventRecord(g_ev_after, stream);
   return check_launch();
 }

@@ -10,6 +10,8 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "lcq_math.hpp"
 
 #pragma clang fp contract(off)
@@ -556,6 +558,158 @@ template <typename T> __device__ DevParams noa_params(T lo, T hi, T eb_down) {
 __host__ __device__ inline uint64_t header_word0(int dtype, int q) {
   return (uint64_t)kMagic | (1ull << 32) | ((uint64_t)dtype << 40) | ((uint64_t)q << 48) |
          ((uint64_t)kLog2Chunk << 56);
+}
+
+}  // namespace lcq
+
+namespace lcq {
+
+// ------------------------------------------------- in-line outlier layout --
+// One word of the field type's width per value (its code sign-extended, or
+// its raw bits when stored losslessly) plus one flag bit per value.
+constexpr uint32_t kMagicInline = 0x4951434Cu;  // "LCQI"
+
+__host__ __device__ inline uint64_t inline_flags_offset(uint64_t n, uint64_t s) {
+  return align16(64 + s * n);
+}
+__host__ __device__ inline uint64_t inline_stream_bytes(uint64_t n, uint64_t s) {
+  return inline_flags_offset(n, s) + (n + 7) / 8;
+}
+
+// OR together the W-bit masks of `lanes` consecutive lanes into one 32-bit
+// word held by the first lane of each group (lane-major bit order, as the
+// values are laid out).
+template <int W> __device__ __forceinline__ unsigned gather_flag_word(unsigned m, int lane) {
+  constexpr int LANES = 32 / W;
+  unsigned v = m << (W * (lane & (LANES - 1)));
+#pragma unroll
+  for (int o = 1; o < LANES; o <<= 1) v |= __shfl_xor(v, o, 64);
+  return v;
+}
+
+// Store a flag word at byte offset `b` of the flag array of `nbytes` bytes;
+// the tail of the array is written byte by byte.
+__device__ __forceinline__ void store_flag_word(uint8_t *flags, uint64_t b, uint64_t nbytes,
+                                                unsigned v) {
+  if (b + 4 <= nbytes) {
+    *reinterpret_cast<unsigned *>(flags + b) = v;
+  } else {
+    for (uint64_t i = 0; i < 4 && b + i < nbytes; i++) flags[b + i] = (uint8_t)(v >> (8 * i));
+  }
+}
+
+// Quantize one tile in the in-line layout: a pure map, no scan.
+template <typename T, int Q, int SLOTS>
+__device__ void quant_tile_inline(const QField<T> &f, uint64_t tile) {
+  using U = typename FT<T>::U;
+  using V = typename Vec<T>::type;
+  constexpr int W = vec_elems<T>();
+  constexpr uint64_t TILE = (uint64_t)kBlock * W * SLOTS;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const uint64_t n = f.n;
+  const uint64_t base = tile * TILE;
+  U *words = reinterpret_cast<U *>(f.stream + 64);
+  const uint64_t fl = inline_flags_offset(n, sizeof(T));
+  const uint64_t nflag = (n + 7) / 8;
+  uint8_t *flags = f.stream + fl;
+
+  V v[SLOTS];
+#pragma unroll
+  for (int j = 0; j < SLOTS; j++) {
+    const uint64_t i0 = base + ((uint64_t)j * kBlock + tid) * W;
+    if (i0 + W <= n) {
+      v[j] = *reinterpret_cast<const V *>(f.in + i0);
+    } else {
+      T tmp[W];
+#pragma unroll
+      for (int e = 0; e < W; e++) tmp[e] = (i0 + e < n) ? f.in[i0 + e] : (T)0;
+      __builtin_memcpy(&v[j], tmp, sizeof(V));
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < SLOTS; j++) {
+    const uint64_t i0 = base + ((uint64_t)j * kBlock + tid) * W;
+    T x[W];
+    __builtin_memcpy(x, &v[j], sizeof(V));
+    U w[W];
+    unsigned m = 0;
+#pragma unroll
+    for (int e = 0; e < W; e++) {
+      const int32_t c = encode<T, Q>(x[e], f.p);
+      const bool raw = c == kSent;
+      // a code is stored sign-extended to the word; a raw value as its bits
+      w[e] = raw ? to_bits(x[e]) : (U)(typename std::make_signed<U>::type)c;
+      if (raw && i0 + e < n) m |= 1u << e;
+    }
+    if (i0 + W <= n) {
+      if constexpr (sizeof(T) == 4) {
+        *reinterpret_cast<uint4 *>(words + i0) = make_uint4(w[0], w[1], w[2], w[3]);
+      } else {
+        *reinterpret_cast<ulonglong2 *>(words + i0) = make_ulonglong2(w[0], w[1]);
+      }
+    } else {
+#pragma unroll
+      for (int e = 0; e < W; e++)
+        if (i0 + e < n) words[i0 + e] = w[e];
+    }
+    const unsigned fw = gather_flag_word<W>(m, lane);
+    constexpr int LANES = 32 / W;
+    if ((lane & (LANES - 1)) == 0 && i0 < n) store_flag_word(flags, i0 / 8, nflag, fw);
+  }
+  if (tile == 0 && tid == 0) {
+    uint64_t *hd = reinterpret_cast<uint64_t *>(f.stream);
+#pragma unroll
+    for (int i = 0; i < 8; i++) hd[i] = f.hdr[i];
+  }
+  if (tile == (n ? (n - 1) / TILE : 0) && tid == 0)
+    for (uint64_t b = 64 + sizeof(T) * n; b < fl; b++) f.stream[b] = 0;
+}
+
+// Decode one tile of the in-line layout.
+template <typename T, int SLOTS>
+__device__ void dequant_tile_inline(const uint8_t *stream, uint64_t n, T step, bool rel, T *out,
+                                    uint64_t tile) {
+  using U = typename FT<T>::U;
+  using V = typename Vec<T>::type;
+  constexpr int W = vec_elems<T>();
+  constexpr uint64_t TILE = (uint64_t)kBlock * W * SLOTS;
+  const int tid = threadIdx.x;
+  const uint64_t base = tile * TILE;
+  const U *words = reinterpret_cast<const U *>(stream + 64);
+  const uint8_t *flags = stream + inline_flags_offset(n, sizeof(T));
+#pragma unroll
+  for (int j = 0; j < SLOTS; j++) {
+    const uint64_t i0 = base + ((uint64_t)j * kBlock + tid) * W;
+    if (i0 >= n) continue;
+    U w[W];
+    if (i0 + W <= n) {
+      if constexpr (sizeof(T) == 4) {
+        const uint4 q4 = *reinterpret_cast<const uint4 *>(words + i0);
+        w[0] = q4.x; w[1] = q4.y; w[2] = q4.z; w[3] = q4.w;
+      } else {
+        const ulonglong2 q2 = *reinterpret_cast<const ulonglong2 *>(words + i0);
+        w[0] = q2.x; w[1] = q2.y;
+      }
+    } else {
+#pragma unroll
+      for (int e = 0; e < W; e++) w[e] = (i0 + e < n) ? words[i0 + e] : (U)0;
+    }
+    // the thread's W flag bits: W divides 8, so they sit in one byte
+    const unsigned m = (flags[i0 / 8] >> (i0 % 8)) & ((1u << W) - 1);
+    T y[W];
+#pragma unroll
+    for (int e = 0; e < W; e++)
+      y[e] = ((m >> e) & 1u) ? from_bits(w[e]) : decode<T>((int32_t)(uint32_t)w[e], step, rel);
+    if (i0 + W <= n) {
+      V o;
+      __builtin_memcpy(&o, y, sizeof(V));
+      *reinterpret_cast<V *>(out + i0) = o;
+    } else {
+#pragma unroll
+      for (int e = 0; e < W; e++)
+        if (i0 + e < n) out[i0 + e] = y[e];
+    }
+  }
 }
 
 }  // namespace lcq

@@ -87,6 +87,20 @@ def rel_variant(g, seed, dtype=None, zero_frac=0.01):
     return x.astype(dtype)
 
 
+def plain_step_inputs(N=512, eb=1e-3, seed=1, rel_seed=11, frac=1e-4):
+    """The single-field workload: an N^3 float32 Gaussian random field with a
+    fraction `frac` of special values, and its lognormal-magnitude variant
+    (for REL) with the same fraction of specials."""
+    g = grf_3d(N, seed, dtype=np.float64)
+    x = g.astype(np.float32)
+    nsp = n_specials(x.size, frac)
+    x, _, _ = inject_specials(x, nsp, seed + 1000, eb)
+    xr = rel_variant(g, rel_seed, dtype=np.float32)
+    del g
+    xr, _, _ = inject_specials(xr, nsp, rel_seed + 1000, eb)
+    return x, xr
+
+
 def n_specials(n, frac):
     return int(round(n * frac))
 

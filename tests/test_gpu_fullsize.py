@@ -1,0 +1,70 @@
+"""Parity at the single-field benchmark's full size: the 512^3 float32 GRF
+(and its lognormal variant for REL), eb = 1e-3.  The oracle finishes these
+in seconds, so whole streams and decodes are compared, under every
+quantize / dequantize launch variant the tuner can pick (the benchmark times
+whichever wins), and for the in-line layout."""
+import numpy as np
+import pytest
+
+import oracle as O
+import synth
+from gpu_util import announce, bits, first_diff
+
+pytestmark = pytest.mark.gpu
+
+EB = 1e-3
+
+
+@pytest.fixture(scope="module")
+def fields():
+    x, xr = synth.plain_step_inputs(512, EB)
+    return {"abs": x, "noa": x, "rel": xr}
+
+
+@pytest.mark.parametrize("q", ["abs", "noa", "rel"])
+def test_fullsize_every_variant(fields, q):
+    import torch
+    import paper_2407_15037_amd as lcq
+    x = fields[q]
+    n = x.size
+    st_o = O.quantize(q, x, EB)
+    dec_o = bits(O.dequantize(st_o, np.float32, n))
+    xt = torch.from_numpy(x).cuda()
+    out = torch.empty(lcq.max_stream_bytes(torch.float32, n), dtype=torch.uint8, device="cuda")
+    nb = torch.empty(1, dtype=torch.int64, device="cuda")
+    ws = torch.empty(lcq.workspace_bytes(q, torch.float32, n), dtype=torch.uint8, device="cuda")
+    dec = torch.empty(n, dtype=torch.float32, device="cuda")
+    saved = (lcq.tune_get("quantize", torch.float32), lcq.tune_get("dequantize", torch.float32))
+    try:
+        for v in range(lcq.tune_variants()):
+            lcq.tune_set("quantize", torch.float32, v)
+            lcq.tune_set("dequantize", torch.float32, v)
+            announce("fullsize", q, n, "variant", v)
+            lcq.quantize(xt, q, EB, out=out, nbytes=nb, ws=ws)
+            size = int(nb.item())
+            diff = first_diff(out[:size].cpu().numpy(), st_o)
+            assert diff is None, f"{q} variant {v}: stream {diff}"
+            lcq.dequantize(out, torch.float32, n, stream_bytes=size, out=dec, ws=ws)
+            assert lcq.stream_status(ws) == 0
+            diff = first_diff(bits(dec.cpu().numpy()), dec_o)
+            assert diff is None, f"{q} variant {v}: decode {diff}"
+    finally:
+        lcq.tune_set("quantize", torch.float32, saved[0])
+        lcq.tune_set("dequantize", torch.float32, saved[1])
+
+
+@pytest.mark.parametrize("q", ["abs", "noa", "rel"])
+def test_fullsize_inline(fields, q):
+    import torch
+    import paper_2407_15037_amd as lcq
+    x = fields[q]
+    announce("fullsize inline", q, x.size)
+    st_o = O.quantize_inline(q, x, EB)
+    xt = torch.from_numpy(x).cuda()
+    st = lcq.quantize_inline(xt, q, EB)
+    assert first_diff(st.cpu().numpy(), st_o) is None
+    ws = torch.zeros(64, dtype=torch.uint8, device="cuda")
+    dec = lcq.dequantize_inline(st, torch.float32, x.size, ws=ws)
+    assert lcq.stream_status(ws) == 0
+    ref = bits(O.dequantize_inline(st_o, np.float32, x.size))
+    assert first_diff(bits(dec.cpu().numpy()), ref) is None
