@@ -12,6 +12,8 @@ produced by the library's HIP kernels through the C ABI.
 Also reported on the same JSON line:
   ops          per-kernel time and GB/s (HIP events around each main kernel)
   roofline     the dominant kernel against the 8 TB/s HBM peak
+  inline_layout the same fields in the in-line outlier layout (section 3.1):
+               per-kernel time, decodes equal to the list layout's
   batched      2,000 fields, log-uniform 4 KiB - 64 MiB, 70 % float32, random
                quantizer and eb in [1e-5, 1e-1]: one graph launch vs a
                per-field launch loop, byte-equal outputs checked
@@ -124,6 +126,57 @@ def run_plain(args, x, xr):
     torch.cuda.empty_cache()
     return dict(ms_per_step=ms_per_step, value=value, kern=kern, ks=ks, sizes=sizes, n=n,
                 gpu_streams=gpu_streams, gpu_decodes=gpu_decodes)
+
+
+# ----------------------------------------------------------------- in-line --
+def run_inline(args, x, xr, plain):
+    """The same three fields in the in-line layout (one word per value plus a
+    raw-value bitmap): per-kernel time, and decodes equal to the list
+    layout's decodes of the timed plain step."""
+    import torch
+    import paper_2407_15037_amd as lcq
+    dev = torch.device("cuda:0")
+    eb = args.eb
+    n, s = x.size, 4
+    order_q = ["abs", "noa", "rel"]
+    dx = {"abs": torch.from_numpy(x).to(dev)}
+    dx["noa"] = dx["abs"]
+    dx["rel"] = torch.from_numpy(xr).to(dev)
+    nb = lcq.inline_stream_bytes(torch.float32, n)
+    bufs = {q: torch.empty(nb, dtype=torch.uint8, device=dev) for q in order_q}
+    ws = torch.empty(1 << 16, dtype=torch.uint8, device=dev)
+    outs = {q: torch.empty(n, dtype=torch.float32, device=dev) for q in order_q}
+    ev = {}
+    reps = max(3, args.steps // 2)
+    for r in range(reps + 1):
+        for kind in ("q", "d"):
+            for q in order_q:
+                if r:
+                    e0 = torch.cuda.Event(enable_timing=True)
+                    e1 = torch.cuda.Event(enable_timing=True)
+                    e0.record(); e1.record()
+                    lcq.profile_events(e0, e1)
+                    ev.setdefault((kind, q), []).append((e0, e1))
+                if kind == "q":
+                    lcq.quantize_inline(dx[q], q, eb, out=bufs[q], ws=ws)
+                else:
+                    lcq.dequantize_inline(bufs[q], torch.float32, n, out=outs[q], ws=ws)
+                lcq.profile_events(None, None)
+    torch.cuda.synchronize()
+    ops, same = {}, {}
+    for (kind, q), pairs in ev.items():
+        avg = sum(a.elapsed_time(b) for a, b in pairs) / len(pairs)
+        alg = n * s + n * s + (n + 7) // 8
+        name = f"{'quantize' if kind == 'q' else 'dequantize'}_inline_{q}"
+        ops[name] = {"us": round(avg * 1e3, 2), "alg_GBs": round(alg / (avg * 1e-3) / 1e9, 1),
+                     "input_GBs": round(n * s / (avg * 1e-3) / 1e9, 1)}
+    for q in order_q:
+        ref = torch.from_numpy(plain["gpu_decodes"][q]).to(dev)
+        same[q] = bool(torch.equal(outs[q].view(torch.int32), ref.view(torch.int32)))
+    del dx, bufs, outs, ws
+    torch.cuda.empty_cache()
+    return {"stream_bytes": nb, "ops": dict(sorted(ops.items())),
+            "decode_equals_list_layout": same}
 
 
 # ----------------------------------------------------------------- batched --
@@ -343,6 +396,7 @@ def main():
     ap.add_argument("--no-tune", action="store_true",
                     help="skip the launch-shape autotuner (use variant 0)")
     ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-inline", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--fields", type=int, default=2000)
     ap.add_argument("--batch-reps", type=int, default=5)
@@ -398,6 +452,8 @@ def main():
                      "alg_bytes_per_launch": dom["alg_bytes"],
                      "avg_launch_us": round(dom["avg_us"], 2)},
     }
+    if not args.no_inline:
+        result["inline_layout"] = run_inline(args, x, xr, plain)
     sample = []
     if not args.no_batched:
         result["batched"], sample = run_batched(args)
