@@ -67,7 +67,8 @@ uint64_t lcq_max_stream_bytes(lcq_dtype t, uint64_t n);
 
 /* Bytes of device workspace lcq_quantize / lcq_dequantize need for n values
  * of type t under quantizer q.  The workspace needs no initialisation; its
- * first 8 bytes hold the status word of the last lcq_dequantize. */
+ * first 8 bytes hold the status word of the last lcq_dequantize (each decode
+ * call tags the word with its own epoch and replaces whatever it held). */
 uint64_t lcq_workspace_bytes(lcq_quantizer q, lcq_dtype t, uint64_t n);
 
 /* Quantize d_in[0..n) of type t under bound eb (sections 2.1, 3.1-3.3).

@@ -17,6 +17,7 @@
 #include <hip/hip_runtime.h>
 
 #include <atomic>
+#include <chrono>
 #include <cmath>
 #include <cstring>
 
@@ -47,7 +48,12 @@ constexpr int kMinmaxBlocks = 2048;
 constexpr uint64_t kMinTileF32 = 4096, kMinTileF64 = 2048;  // smallest quantize tile of any variant
 
 thread_local hipEvent_t g_ev_before = nullptr, g_ev_after = nullptr;
-std::atomic<uint64_t> g_epoch{0};
+// Decode-call epochs tag the status word; starting from the clock keeps a
+// workspace left over from another process from matching a new call.
+uint64_t epoch_seed() {
+  return (uint64_t)std::chrono::steady_clock::now().time_since_epoch().count() & 0xFFFFFFFFFFFull;
+}
+std::atomic<uint64_t> g_epoch{epoch_seed()};
 
 struct PlainQ {
   const void *in;
@@ -195,7 +201,7 @@ __global__ __launch_bounds__(kBlock) void k_dequantize(PlainD a) {
                    hd[1] != n || k > n || oo + k * sizeof(T) > a.stream_bytes;
   const unsigned long long tag = (unsigned long long)(a.epoch << 16);
   if (blockIdx.x == 0 && threadIdx.x == 0)
-    atomicMax(a.status, tag | (unsigned long long)(bad ? LCQ_ERR_STREAM : LCQ_OK));
+    report_status(a.status, tag, bad ? LCQ_ERR_STREAM : LCQ_OK);
   if (bad || n == 0) return;
   DField<T> f;
   f.stream = a.stream;
@@ -221,7 +227,7 @@ __global__ __launch_bounds__(kBlock) void k_dequantize_inline(PlainD a) {
                    inline_stream_bytes(n, sizeof(T)) > a.stream_bytes;
   const unsigned long long tag = (unsigned long long)(a.epoch << 16);
   if (blockIdx.x == 0 && threadIdx.x == 0)
-    atomicMax(a.status, tag | (unsigned long long)(bad ? LCQ_ERR_STREAM : LCQ_OK));
+    report_status(a.status, tag, bad ? LCQ_ERR_STREAM : LCQ_OK);
   if (bad || n == 0) return;
   dequant_tile_inline<T, kInlineSlots>(a.stream, n, from_bits((U)hd[4]), q == kREL,
                                       static_cast<T *>(a.out), blockIdx.x);

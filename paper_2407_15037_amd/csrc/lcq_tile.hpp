@@ -322,6 +322,22 @@ __device__ void quant_tile(const QField<T> &f, uint64_t tile, unsigned spin_limi
 }
 
 // Everything a workgroup needs to decode one tile of one stream.
+// Record `code` in a decode status word (epoch << 16 | code) for the call
+// tagged `tag`.  A word carrying another epoch -- an earlier call, or whatever
+// the workspace held before -- is replaced; within one epoch the larger code
+// wins.  Every successful exchange ends one reporting thread, so the loop
+// ends once the other reporters of the moment have finished.
+__device__ inline void report_status(unsigned long long *w, unsigned long long tag,
+                                     unsigned long long code) {
+  unsigned long long old = __hip_atomic_load(w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  for (;;) {
+    if ((old >> 16) == (tag >> 16) && (old & 0xFFFFull) >= code) return;
+    const unsigned long long prev = atomicCAS(w, old, tag | code);
+    if (prev == old) return;
+    old = prev;
+  }
+}
+
 template <typename T> struct DField {
   const uint8_t *stream;
   uint64_t n;
@@ -431,9 +447,9 @@ __device__ void dequant_tile(const DField<T> &f, uint64_t tile) {
     bool bad = false;
     if (cidx * kChunk < n) bad = chunk_tab[cidx] != before;
     else if ((cidx - 1) * kChunk < n) bad = before != f.k;  // the count closes at the end
-    if (bad) atomicMax(f.status, f.tag | (unsigned long long)LCQ_ERR_STREAM);
+    if (bad) report_status(f.status, f.tag, LCQ_ERR_STREAM);
   }
-  if (tid == 0 && first > f.k) atomicMax(f.status, f.tag | (unsigned long long)LCQ_ERR_STREAM);
+  if (tid == 0 && first > f.k) report_status(f.status, f.tag, LCQ_ERR_STREAM);
 
   if (any) {
     const uint64_t lt = __lanemask_lt();

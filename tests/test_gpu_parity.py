@@ -208,3 +208,30 @@ def test_every_launch_variant_same_bytes():
         for tdt in (torch.float32, torch.float64):
             lcq.tune_set("quantize", tdt, 0)
             lcq.tune_set("dequantize", tdt, 0)
+
+
+def test_status_word_ignores_workspace_contents():
+    """The decode status word is tagged per call: a workspace whose first
+    bytes hold anything (here all ones, the largest possible word) still
+    reports OK for a good stream and ERR_STREAM for a broken one, in both
+    layouts."""
+    import torch
+    import paper_2407_15037_amd as lcq
+    x = _field(np.float32, 3 * 4096 + 5, 261, 1e-3, "abs")
+    st = O.quantize("abs", x, 1e-3)
+    sti = O.quantize_inline("abs", x, 1e-3)
+    for fill in (0xFF, 0x00, 0x7F):
+        for inline in (False, True):
+            s = sti if inline else st
+            for broken in (False, True):
+                b = s.copy()
+                if broken:
+                    b[0] ^= 0xFF
+                announce("status word", hex(fill), "inline" if inline else "list", broken)
+                buf = torch.from_numpy(b).cuda()
+                ws = torch.full((64,), fill, dtype=torch.uint8, device="cuda")
+                if inline:
+                    lcq.dequantize_inline(buf, torch.float32, x.size, ws=ws)
+                else:
+                    lcq.dequantize(buf, torch.float32, x.size, ws=ws)
+                assert lcq.stream_status(ws) == (3 if broken else 0)
