@@ -321,7 +321,6 @@ __device__ void quant_tile(const QField<T> &f, uint64_t tile, unsigned spin_limi
   }
 }
 
-// Everything a workgroup needs to decode one tile of one stream.
 // Record `code` in a decode status word (epoch << 16 | code) for the call
 // tagged `tag`.  A word carrying another epoch -- an earlier call, or whatever
 // the workspace held before -- is replaced; within one epoch the larger code
@@ -338,6 +337,7 @@ __device__ inline void report_status(unsigned long long *w, unsigned long long t
   }
 }
 
+// Everything a workgroup needs to decode one tile of one stream.
 template <typename T> struct DField {
   const uint8_t *stream;
   uint64_t n;
