@@ -394,7 +394,11 @@ def main():
     ap.add_argument("--eb", type=float, default=1e-3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-tune", action="store_true",
-                    help="skip the launch-shape autotuner (use variant 0)")
+                    help="skip the launch-shape autotuner (use the built-in defaults)")
+    ap.add_argument("--variants", default=None,
+                    help="Q,D: fixed float32 quantize / dequantize launch variants "
+                         "instead of the autotuner (for profiler runs that must time "
+                         "the same kernels)")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-inline", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
@@ -425,7 +429,13 @@ def main():
         del src, dst
         log("calibration copies: 3 x 512 MiB read + 512 MiB written")
     tuned = None
-    if not args.no_tune:
+    if args.variants:
+        import paper_2407_15037_amd as lcq
+        qv, dv = (int(v) for v in args.variants.split(","))
+        lcq.tune_set("quantize", torch.float32, qv)
+        lcq.tune_set("dequantize", torch.float32, dv)
+        tuned = {"float32": {"quantize": {"best": qv}, "dequantize": {"best": dv}}}
+    elif not args.no_tune:
         from paper_2407_15037_amd import autotune
         tuned = autotune.tune(log=log)
     x, xr = make_plain_inputs(args.grid, args.eb)
