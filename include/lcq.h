@@ -227,9 +227,15 @@ typedef struct {
 lcq_status lcq_serve(const lcq_server_config *cfg, const lcq_request *req, uint32_t nreq,
                      lcq_request_result *res);
 
-/* Launch-shape tuning.  Each per-value kernel comes in lcq_tune_variants()
- * shapes (loads in flight per thread x rounds per tile); all produce the
- * same bytes.  op 0 = quantize, 1 = dequantize.  Process-wide; the tuner
+/* Launch-shape tuning.  Each operation comes in lcq_tune_variants()
+ * kernel variants; all produce the same bytes.  Variants 0-5: one
+ * workgroup-wide tile per workgroup (loads in flight per thread x rounds;
+ * quantize finds its outlier offset by a decoupled look-back over earlier
+ * tiles).  Variants 6-8 (6 is the default): one wavefront per 1024-value
+ * chunk; quantize runs two kernels, a streaming pass that writes codes,
+ * per-chunk outlier counts and staged outliers, then a scan pass that
+ * writes the chunk table, the outliers and the header.  op 0 = quantize,
+ * 1 = dequantize.  Process-wide; the tuner
  * (paper_2407_15037_amd/autotune.py) measures them and sets the fastest.
  * lcq_tune_set returns LCQ_ERR_ARG for a bad op, dtype or variant;
  * lcq_tune_get returns -1 for a bad op or dtype. */

@@ -16,6 +16,7 @@
 //   k_dequantize   one tile per workgroup, independent tiles: dequant_tile
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <atomic>
 #include <chrono>
 #include <cmath>
@@ -25,11 +26,12 @@
 #include "lcq_host.hpp"
 #include "lcq_math.hpp"
 #include "lcq_tile.hpp"
+#include "lcq_chunk.hpp"
 
 #pragma clang fp contract(off)
 
 namespace lcq {
-std::atomic<int> g_variant[2][2] = {{{1}, {1}}, {{0}, {0}}};  // [op][dtype]
+std::atomic<int> g_variant[2][2] = {{{6}, {6}}, {{6}, {6}}};  // [op][dtype]
 std::atomic<unsigned> g_spin_limit{4096};
 }  // namespace lcq
 
@@ -167,6 +169,68 @@ __global__ __launch_bounds__(kBlock) void k_noa_params(const T *partials, int np
   *out = noa_params<T>(lo, hi, eb_down);
 }
 
+// Two-pass chunk-per-wavefront quantize (lcq_chunk.hpp).
+struct StageQ {
+  const void *in;
+  uint64_t n;
+  uint8_t *stream;
+  uint64_t *stream_bytes;
+  uint32_t *counts;
+  void *stage;
+  unsigned long long *group;
+  uint64_t tiles_per_group, chunks_per_group, ngroups;
+  const DevParams *noa;
+  uint64_t step, inv, bound, low;  // ABS / REL parameters (raw bits)
+  uint64_t hdr[8];
+};
+
+template <typename T, int Q>
+__device__ __forceinline__ FieldParams<T> stage_params(const StageQ &a) {
+  using U = typename FT<T>::U;
+  if constexpr (Q == kNOA) return params_from<T>(*a.noa);
+  FieldParams<T> p;
+  p.step = from_bits((U)a.step);
+  p.inv = from_bits((U)a.inv);
+  p.bound = from_bits((U)a.bound);
+  p.low = from_bits((U)a.low);
+  p.lossless_all = 0;
+  return p;
+}
+
+template <typename T, int Q, int CPW, int PF>
+__global__ __launch_bounds__(kBlock) void k_quant_stage(StageQ a) {
+  using U = typename FT<T>::U;
+  StageField<T> f;
+  f.in = static_cast<const T *>(a.in);
+  f.n = a.n;
+  f.codes = reinterpret_cast<int32_t *>(a.stream + 64);
+  f.counts = a.counts;
+  f.stage = static_cast<U *>(a.stage);
+  f.group = a.group;
+  f.tiles_per_group = a.tiles_per_group;
+  f.p = stage_params<T, Q>(a);
+  quant_chunks<T, Q, CPW, PF>(f, blockIdx.x);
+}
+
+template <typename T, int Q>
+__global__ __launch_bounds__(kBlock) void k_quant_finish(StageQ a) {
+  using U = typename FT<T>::U;
+  FinishField<T> f;
+  f.in = static_cast<const T *>(a.in);
+  f.n = a.n;
+  f.stream = a.stream;
+  f.stream_bytes = a.stream_bytes;
+  f.counts = a.counts;
+  f.stage = static_cast<const U *>(a.stage);
+  f.group = a.group;
+  f.chunks_per_group = a.chunks_per_group;
+  f.ngroups = a.ngroups;
+  f.noa = Q == kNOA ? a.noa : nullptr;
+#pragma unroll
+  for (int i = 0; i < 8; i++) f.hdr[i] = a.hdr[i];
+  quant_finish<T>(f, blockIdx.x);
+}
+
 // In-line layout (the paper's own, section 3.1): a pure map per tile.
 constexpr int kInlineSlots = 4;
 
@@ -187,8 +251,10 @@ struct PlainD {
   int dtype;
 };
 
-template <typename T, int SL, int RD>
-__global__ __launch_bounds__(kBlock) void k_dequantize(PlainD a) {
+// Header check shared by the dequantize kernels; fills f and returns false
+// (after recording the status) when the stream does not describe this call.
+template <typename T>
+__device__ __forceinline__ bool deq_setup(const PlainD &a, DField<T> &f) {
   using U = typename FT<T>::U;
   const uint64_t n = a.n;
   const uint64_t *hd = reinterpret_cast<const uint64_t *>(a.stream);
@@ -202,8 +268,7 @@ __global__ __launch_bounds__(kBlock) void k_dequantize(PlainD a) {
   const unsigned long long tag = (unsigned long long)(a.epoch << 16);
   if (blockIdx.x == 0 && threadIdx.x == 0)
     report_status(a.status, tag, bad ? LCQ_ERR_STREAM : LCQ_OK);
-  if (bad || n == 0) return;
-  DField<T> f;
+  if (bad || n == 0) return false;
   f.stream = a.stream;
   f.n = n;
   f.k = k;
@@ -212,7 +277,19 @@ __global__ __launch_bounds__(kBlock) void k_dequantize(PlainD a) {
   f.out = static_cast<T *>(a.out);
   f.status = a.status;
   f.tag = tag;
-  dequant_tile<T, SL, RD>(f, blockIdx.x);
+  return true;
+}
+
+template <typename T, int CPW, int PF>
+__global__ __launch_bounds__(kBlock) void k_dequantize_chunks(PlainD a) {
+  DField<T> f;
+  if (deq_setup<T>(a, f)) dequant_chunks<T, CPW, PF>(f, blockIdx.x);
+}
+
+template <typename T, int SL, int RD>
+__global__ __launch_bounds__(kBlock) void k_dequantize(PlainD a) {
+  DField<T> f;
+  if (deq_setup<T>(a, f)) dequant_tile<T, SL, RD>(f, blockIdx.x);
 }
 
 template <typename T>
@@ -234,40 +311,66 @@ __global__ __launch_bounds__(kBlock) void k_dequantize_inline(PlainD a) {
 }
 
 // ----------------------------------------------------------- host side ---
-uint64_t ws_need(lcq_quantizer q, lcq_dtype t, uint64_t n) {
+// Workspace layout beyond the status word and the NOA parameters:
+//   single-pass variants  one look-back word per tile at kWsState
+//   two-pass variants     group sums at kWsState, chunk counts, staged raw
+//                         bits (kStageCap per chunk)
+//   NOA                   per-workgroup (min, max) pairs after both
+uint64_t align256(uint64_t v) { return (v + 255) & ~255ull; }
+uint64_t ws_counts_off() { return align256(kWsState + 8 * kMaxGroups); }
+uint64_t ws_stage_off(uint64_t n) { return align256(ws_counts_off() + 4 * n_chunks(n)); }
+uint64_t ws_partials_off(lcq_dtype t, uint64_t n) {
+  const uint64_t s = t == LCQ_F64 ? 8 : 4;
   const uint64_t tile = t == LCQ_F64 ? kMinTileF64 : kMinTileF32;
-  const uint64_t ntiles = (n + tile - 1) / tile;
-  uint64_t b = kWsState + 8 * ntiles;
-  if (q == LCQ_NOA) b = ((b + 255) & ~255ull) + 16ull * kMinmaxBlocks;
-  return b;
+  const uint64_t lookback_end = kWsState + 8 * ((n + tile - 1) / tile);
+  const uint64_t staged_end = ws_stage_off(n) + (uint64_t)kStageCap * s * n_chunks(n);
+  return align256(std::max(lookback_end, staged_end));
+}
+uint64_t ws_need(lcq_quantizer q, lcq_dtype t, uint64_t n) {
+  return ws_partials_off(t, n) + (q == LCQ_NOA ? 16ull * kMinmaxBlocks : 0);
 }
 
 lcq_status check_launch() { return hipGetLastError() == hipSuccess ? LCQ_OK : LCQ_ERR_HIP; }
 
 template <typename T, int Q, int V>
-void launch_quantize(const PlainQ &a, hipStream_t s) {
+void launch_quantize(const PlainQ &a, const StageQ &sq, hipStream_t s) {
   constexpr QShape sh = kQVariants[V];
-  hipLaunchKernelGGL((k_quantize<T, Q, sh.slots, sh.rounds, sh.depth, sh.unroll>),
-                     dim3((unsigned)a.ntiles), dim3(kBlock), 0, s, a);
+  if constexpr (sh.cpw > 0) {
+    hipLaunchKernelGGL((k_quant_stage<T, Q, sh.cpw, sh.pf>), dim3((unsigned)a.ntiles),
+                       dim3(kBlock), 0, s, sq);
+    hipLaunchKernelGGL((k_quant_finish<T, Q>), dim3((unsigned)sq.ngroups), dim3(kBlock), 0, s,
+                       sq);
+  } else {
+    hipLaunchKernelGGL((k_quantize<T, Q, sh.slots, sh.rounds, sh.depth, sh.unroll>),
+                       dim3((unsigned)a.ntiles), dim3(kBlock), 0, s, a);
+  }
 }
 
 template <typename T, int Q>
-void launch_quantize_variant(int v, const PlainQ &a, hipStream_t s) {
+void launch_quantize_variant(int v, const PlainQ &a, const StageQ &sq, hipStream_t s) {
   switch (v) {
-    case 1: return launch_quantize<T, Q, 1>(a, s);
-    case 2: return launch_quantize<T, Q, 2>(a, s);
-    case 3: return launch_quantize<T, Q, 3>(a, s);
-    case 4: return launch_quantize<T, Q, 4>(a, s);
-    case 5: return launch_quantize<T, Q, 5>(a, s);
-    default: return launch_quantize<T, Q, 0>(a, s);
+    case 1: return launch_quantize<T, Q, 1>(a, sq, s);
+    case 2: return launch_quantize<T, Q, 2>(a, sq, s);
+    case 3: return launch_quantize<T, Q, 3>(a, sq, s);
+    case 4: return launch_quantize<T, Q, 4>(a, sq, s);
+    case 5: return launch_quantize<T, Q, 5>(a, sq, s);
+    case 6: return launch_quantize<T, Q, 6>(a, sq, s);
+    case 7: return launch_quantize<T, Q, 7>(a, sq, s);
+    case 8: return launch_quantize<T, Q, 8>(a, sq, s);
+    default: return launch_quantize<T, Q, 0>(a, sq, s);
   }
 }
 
 template <typename T, int V>
 void launch_dequantize(uint64_t ntiles, const PlainD &a, hipStream_t s) {
   constexpr Shape sh = kDVariants[V];
-  hipLaunchKernelGGL((k_dequantize<T, sh.slots, sh.rounds>), dim3((unsigned)ntiles), dim3(kBlock),
-                     0, s, a);
+  if constexpr (sh.cpw > 0) {
+    hipLaunchKernelGGL((k_dequantize_chunks<T, sh.cpw, sh.pf>), dim3((unsigned)ntiles),
+                       dim3(kBlock), 0, s, a);
+  } else {
+    hipLaunchKernelGGL((k_dequantize<T, sh.slots, sh.rounds>), dim3((unsigned)ntiles),
+                       dim3(kBlock), 0, s, a);
+  }
 }
 
 template <typename T>
@@ -278,6 +381,9 @@ void launch_dequantize_variant(int v, uint64_t ntiles, const PlainD &a, hipStrea
     case 3: return launch_dequantize<T, 3>(ntiles, a, s);
     case 4: return launch_dequantize<T, 4>(ntiles, a, s);
     case 5: return launch_dequantize<T, 5>(ntiles, a, s);
+    case 6: return launch_dequantize<T, 6>(ntiles, a, s);
+    case 7: return launch_dequantize<T, 7>(ntiles, a, s);
+    case 8: return launch_dequantize<T, 8>(ntiles, a, s);
     default: return launch_dequantize<T, 0>(ntiles, a, s);
   }
 }
@@ -312,9 +418,34 @@ lcq_status run_quantize(double eb, const void *d_in, uint64_t n, void *d_stream,
   const uint64_t tile = quant_tile_len((lcq_dtype)dt, v);
   a.ntiles = (n + tile - 1) / tile;
 
+  // two-pass variants: groups of whole workgroups, one pass-2 workgroup each
+  const bool staged = kQVariants[v].cpw > 0;
+  StageQ sq{};
+  uint64_t *clear_ptr = a.state;
+  uint64_t clear_count = a.ntiles;
+  if (staged) {
+    sq.in = d_in;
+    sq.n = n;
+    sq.stream = a.stream;
+    sq.stream_bytes = d_bytes;
+    sq.counts = reinterpret_cast<uint32_t *>(ws + ws_counts_off());
+    sq.stage = ws + ws_stage_off(n);
+    sq.group = reinterpret_cast<unsigned long long *>(ws + kWsState);
+    sq.tiles_per_group = std::max<uint64_t>(1, (a.ntiles + kMaxGroups - 1) / kMaxGroups);
+    sq.chunks_per_group = sq.tiles_per_group * (tile / kChunk);
+    sq.ngroups = (a.ntiles + sq.tiles_per_group - 1) / sq.tiles_per_group;
+    sq.noa = a.noa;
+    sq.step = a.step;
+    sq.inv = a.inv;
+    sq.bound = a.bound;
+    sq.low = a.low;
+    for (int i = 0; i < 8; i++) sq.hdr[i] = a.hdr[i];
+    clear_ptr = reinterpret_cast<uint64_t *>(sq.group);
+    clear_count = sq.ngroups;
+  }
+
   if (Q == kNOA) {
-    const uint64_t poff = (kWsState + 8 * a.ntiles + 255) & ~255ull;
-    T *partials = reinterpret_cast<T *>(ws + poff);
+    T *partials = reinterpret_cast<T *>(ws + ws_partials_off((lcq_dtype)dt, n));
     // each workgroup reduces a contiguous share of whole 128-bit vectors
     const uint64_t W = 16 / sizeof(T);
     const uint64_t per = (uint64_t)kBlock * W * 8;  // >= 8 vectors per thread
@@ -323,20 +454,20 @@ lcq_status run_quantize(double eb, const void *d_in, uint64_t n, void *d_stream,
     uint64_t share = (n + nb - 1) / nb;
     share = (share + W - 1) / W * W;
     hipLaunchKernelGGL(k_minmax<T>, dim3((unsigned)nb), dim3(kBlock), 0, s,
-                       static_cast<const T *>(d_in), n, share, partials, a.state, a.ntiles);
+                       static_cast<const T *>(d_in), n, share, partials, clear_ptr, clear_count);
     hipLaunchKernelGGL(k_noa_params<T>, dim3(1), dim3(kBlock), 0, s, partials, (int)nb,
                        from_bits((typename FT<T>::U)hp.eb_down),
                        reinterpret_cast<DevParams *>(ws + kWsParams));
-  } else if (a.ntiles) {
-    const unsigned nb = (unsigned)std::min<uint64_t>((a.ntiles + kBlock - 1) / kBlock, 1024);
-    hipLaunchKernelGGL(k_clear, dim3(nb), dim3(kBlock), 0, s, a.state, a.ntiles);
+  } else if (clear_count) {
+    const unsigned nb = (unsigned)std::min<uint64_t>((clear_count + kBlock - 1) / kBlock, 1024);
+    hipLaunchKernelGGL(k_clear, dim3(nb), dim3(kBlock), 0, s, clear_ptr, clear_count);
   }
   if (n == 0) {
     hipLaunchKernelGGL((k_header_only<T, Q>), dim3(1), dim3(1), 0, s, a);
     return check_launch();
   }
   if (g_ev_before) (void)hipEventRecord(g_ev_before, s);
-  launch_quantize_variant<T, Q>(v, a, s);
+  launch_quantize_variant<T, Q>(v, a, sq, s);
   if (g_ev_after) (void)hipEventRecord(g_ev_after, s);
   return check_launch();
 }

@@ -1,0 +1,394 @@
+// lcq_chunk.hpp -- chunk-per-wavefront quantize / dequantize for gfx950.
+//
+// One 64-lane wavefront owns one 1024-value chunk of the stream format (the
+// granularity of its chunk table).  Lane l holds values 256 j + 4 l + e of
+// the chunk (sub-block j = 0..3, e = 0..3): each sub-block is one contiguous
+// 256-value run, so every load and store of a wavefront is a contiguous
+// 1 KiB (codes, float32) or 2 KiB (float64) access.  Ranks of outliers
+// inside a chunk follow from ballots alone; no LDS and no barrier is needed
+// for them.
+//
+// Quantize runs as two passes instead of one pass with a decoupled
+// look-back:
+//   pass 1  per value classify / bin / reconstruct / verify (sections 2.2,
+//           3.1-3.3), int32 code stores, the chunk's outlier count, and the
+//           first kStageCap outliers' raw bits staged per chunk straight
+//           from registers; one atomic add per workgroup into the sum of
+//           its group of workgroups.
+//   pass 2  one workgroup per group: exclusive scan of the chunk counts
+//           (the chunk table), copy of staged outliers to their final,
+//           input-ordered place, header and size.  A chunk with more than
+//           kStageCap outliers has its codes rescanned and its raw bits
+//           read from the input.
+// Dequantize gathers each outlier's bits before the single store of its
+// values and checks every chunk-table entry against the counted sentinels.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "lcq_math.hpp"
+#include "lcq_tile.hpp"
+
+#pragma clang fp contract(off)
+
+namespace lcq {
+
+constexpr int kSub = 4;             // 256-value sub-blocks per chunk
+constexpr int kStageCap = 32;       // outliers staged per chunk in pass 1
+constexpr uint64_t kMaxGroups = 1024;  // pass-2 workgroups (groups) at most
+
+// Four consecutive values at i0 (zeros past n).
+template <typename T>
+__device__ __forceinline__ void load4(const T *in, uint64_t i0, uint64_t n, T (&x)[4]) {
+  if (i0 + 4 <= n) {
+    if constexpr (sizeof(T) == 4) {
+      const float4 v = *reinterpret_cast<const float4 *>(in + i0);
+      x[0] = v.x; x[1] = v.y; x[2] = v.z; x[3] = v.w;
+    } else {
+      const double2 a = *reinterpret_cast<const double2 *>(in + i0);
+      const double2 b = *reinterpret_cast<const double2 *>(in + i0 + 2);
+      x[0] = a.x; x[1] = a.y; x[2] = b.x; x[3] = b.y;
+    }
+  } else {
+#pragma unroll
+    for (int e = 0; e < 4; e++) x[e] = (i0 + e < n) ? in[i0 + e] : (T)0;
+  }
+}
+
+template <typename T>
+__device__ __forceinline__ void store4(T *out, uint64_t i0, uint64_t n, const T (&y)[4]) {
+  if (i0 + 4 <= n) {
+    if constexpr (sizeof(T) == 4) {
+      *reinterpret_cast<float4 *>(out + i0) = make_float4(y[0], y[1], y[2], y[3]);
+    } else {
+      *reinterpret_cast<double2 *>(out + i0) = make_double2(y[0], y[1]);
+      *reinterpret_cast<double2 *>(out + i0 + 2) = make_double2(y[2], y[3]);
+    }
+  } else {
+#pragma unroll
+    for (int e = 0; e < 4; e++)
+      if (i0 + e < n) out[i0 + e] = y[e];
+  }
+}
+
+__device__ __forceinline__ void load_codes4(const int32_t *codes, uint64_t i0, uint64_t n,
+                                            int32_t (&c)[4]) {
+  if (i0 + 4 <= n) {
+    const int4 v = *reinterpret_cast<const int4 *>(codes + i0);
+    c[0] = v.x; c[1] = v.y; c[2] = v.z; c[3] = v.w;
+  } else {
+#pragma unroll
+    for (int e = 0; e < 4; e++) c[e] = (i0 + e < n) ? codes[i0 + e] : 0;
+  }
+}
+
+// Sub-block j of chunk c, lane's first value.
+__device__ __forceinline__ uint64_t chunk_value(uint64_t c, int j, int lane) {
+  return c * kChunk + 256u * (unsigned)j + 4u * (unsigned)lane;
+}
+
+// Ranks of flagged values of one sub-block inside the wavefront's chunk:
+// returns the count of the sub-block to every lane, and in `pre` the number
+// of flagged values of lower lanes.  `f4` holds the lane's 4 flags.
+__device__ __forceinline__ unsigned sub_ranks(unsigned f4, uint64_t lt, unsigned &pre) {
+  unsigned tot = 0;
+  pre = 0;
+#pragma unroll
+  for (int e = 0; e < 4; e++) {
+    const uint64_t b = __ballot((f4 >> e) & 1u);
+    tot += (unsigned)__popcll(b);
+    pre += (unsigned)__popcll(b & lt);
+  }
+  return tot;
+}
+
+// ------------------------------------------------------------- pass 1 ---
+template <typename T> struct StageField {
+  const T *in;
+  uint64_t n;
+  int32_t *codes;                 // stream + 64
+  uint32_t *counts;               // one per chunk
+  typename FT<T>::U *stage;       // kStageCap per chunk
+  unsigned long long *group;      // one sum per group of workgroups
+  uint64_t tiles_per_group;
+  FieldParams<T> p;
+};
+
+// Pass 1 for the CPW * kWaves chunks of workgroup `tile`; PF chunks per
+// wavefront are loaded before any is encoded.
+template <typename T, int Q, int CPW, int PF>
+__device__ void quant_chunks(const StageField<T> &f, uint64_t tile) {
+  static_assert(CPW % PF == 0, "whole prefetch groups");
+  __shared__ unsigned s_cnt[kWaves];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const uint64_t n = f.n;
+  const uint64_t nch = n_chunks(n);
+  const uint64_t lt = __lanemask_lt();
+  unsigned wsum = 0;
+#pragma unroll
+  for (int r0 = 0; r0 < CPW; r0 += PF) {
+    T x[PF][kSub][4];
+#pragma unroll
+    for (int p = 0; p < PF; p++) {
+      const uint64_t c = (tile * CPW + r0 + p) * kWaves + wave;
+      if (c < nch) {
+#pragma unroll
+        for (int j = 0; j < kSub; j++) load4(f.in, chunk_value(c, j, lane), n, x[p][j]);
+      }
+    }
+#pragma unroll
+    for (int p = 0; p < PF; p++) {
+      const uint64_t c = (tile * CPW + r0 + p) * kWaves + wave;
+      if (c >= nch) continue;  // uniform over the wavefront
+      unsigned om = 0;
+#pragma unroll
+      for (int j = 0; j < kSub; j++) {
+        const uint64_t i0 = chunk_value(c, j, lane);
+        int32_t code[4];
+#pragma unroll
+        for (int e = 0; e < 4; e++) {
+          code[e] = encode<T, Q>(x[p][j][e], f.p);
+          if (code[e] == kSent && i0 + e < n) om |= 1u << (4 * j + e);
+        }
+        if (i0 + 4 <= n) {
+          *reinterpret_cast<int4 *>(f.codes + i0) = make_int4(code[0], code[1], code[2], code[3]);
+        } else {
+#pragma unroll
+          for (int e = 0; e < 4; e++)
+            if (i0 + e < n) f.codes[i0 + e] = code[e];
+        }
+      }
+      unsigned cnt = 0;
+      if (__ballot(om != 0)) {
+#pragma unroll
+        for (int j = 0; j < kSub; j++) {
+          unsigned pre;
+          const unsigned tot = sub_ranks((om >> (4 * j)) & 0xFu, lt, pre);
+          unsigned r = cnt + pre;
+#pragma unroll
+          for (int e = 0; e < 4; e++) {
+            if ((om >> (4 * j + e)) & 1u) {
+              if (r < (unsigned)kStageCap) f.stage[c * kStageCap + r] = to_bits(x[p][j][e]);
+              r++;
+            }
+          }
+          cnt += tot;
+        }
+      }
+      if (lane == 0) f.counts[c] = cnt;
+      wsum += cnt;
+    }
+  }
+  if (lane == 0) s_cnt[wave] = wsum;
+  __syncthreads();
+  if (tid == 0) {
+    unsigned long long t = 0;
+#pragma unroll
+    for (int w = 0; w < kWaves; w++) t += s_cnt[w];
+    if (t) atomicAdd(f.group + tile / f.tiles_per_group, t);
+  }
+}
+
+// ------------------------------------------------------------- pass 2 ---
+template <typename T> struct FinishField {
+  const T *in;
+  uint64_t n;
+  uint8_t *stream;
+  uint64_t *stream_bytes;
+  const uint32_t *counts;
+  const typename FT<T>::U *stage;
+  const unsigned long long *group;
+  uint64_t chunks_per_group;
+  uint64_t ngroups;
+  const DevParams *noa;  // NOA: header words 4-7 come from here
+  uint64_t hdr[8];
+};
+
+// Outliers of chunk c from its codes and the input (a chunk with more
+// outliers than were staged), written from index P on.  One wavefront.
+template <typename T>
+__device__ void rescan_chunk(const FinishField<T> &f, uint64_t c, uint64_t P, int lane) {
+  using U = typename FT<T>::U;
+  const int32_t *codes = reinterpret_cast<const int32_t *>(f.stream + 64);
+  U *outl = reinterpret_cast<U *>(f.stream + outlier_offset(f.n));
+  const U *inb = reinterpret_cast<const U *>(f.in);
+  const uint64_t lt = __lanemask_lt();
+  uint64_t run = P;
+#pragma unroll
+  for (int j = 0; j < kSub; j++) {
+    const uint64_t i0 = chunk_value(c, j, lane);
+    int32_t cc[4];
+    load_codes4(codes, i0, f.n, cc);
+    unsigned f4 = 0;
+#pragma unroll
+    for (int e = 0; e < 4; e++)
+      if (cc[e] == kSent && i0 + e < f.n) f4 |= 1u << e;
+    unsigned pre;
+    const unsigned tot = sub_ranks(f4, lt, pre);
+    uint64_t r = run + pre;
+#pragma unroll
+    for (int e = 0; e < 4; e++)
+      if ((f4 >> e) & 1u) outl[r++] = inb[i0 + e];
+    run += tot;
+  }
+}
+
+// Pass 2 for group g: chunk-table entries of its chunks, their outliers,
+// and (last group) header, padding and stream size.
+template <typename T>
+__device__ void quant_finish(const FinishField<T> &f, uint64_t g) {
+  using U = typename FT<T>::U;
+  __shared__ unsigned long long s_red[kWaves];
+  __shared__ unsigned s_wt[kWaves];
+  __shared__ uint64_t s_P[kBlock];
+  __shared__ unsigned s_c[kBlock];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const uint64_t n = f.n;
+  const uint64_t nch = n_chunks(n);
+  uint64_t *chunk_tab = reinterpret_cast<uint64_t *>(f.stream + chunk_table_offset(n));
+  U *outl = reinterpret_cast<U *>(f.stream + outlier_offset(n));
+
+  // outliers of all earlier groups
+  unsigned long long b = 0;
+  for (uint64_t i = tid; i < g; i += kBlock) b += f.group[i];
+  b = wave_sum(b);
+  if (lane == 0) s_red[wave] = b;
+  __syncthreads();
+  uint64_t run = 0;
+#pragma unroll
+  for (int w = 0; w < kWaves; w++) run += s_red[w];
+
+  const uint64_t c0 = g * f.chunks_per_group;
+  const uint64_t c1 = min(c0 + f.chunks_per_group, nch);
+  for (uint64_t cb = c0; cb < c1; cb += kBlock) {
+    const uint64_t c = cb + tid;
+    const unsigned cnt = c < c1 ? f.counts[c] : 0u;
+    unsigned incl = cnt;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      const unsigned t = __shfl_up(incl, o, 64);
+      if (lane >= o) incl += t;
+    }
+    if (lane == 63) s_wt[wave] = incl;
+    __syncthreads();
+    uint64_t before = 0, total = 0;
+#pragma unroll
+    for (int w = 0; w < kWaves; w++) {
+      if (w < wave) before += s_wt[w];
+      total += s_wt[w];
+    }
+    const uint64_t P = run + before + (incl - cnt);
+    if (c < c1) chunk_tab[c] = P;
+    s_P[tid] = P;
+    s_c[tid] = cnt;
+    __syncthreads();
+    const int m = (int)min<uint64_t>((uint64_t)kBlock, c1 - cb);
+    for (int i = wave; i < m; i += kWaves) {
+      const unsigned cn = s_c[i];
+      if (cn == 0) continue;
+      const uint64_t Pi = s_P[i];
+      const uint64_t ch = cb + (uint64_t)i;
+      if (cn <= (unsigned)kStageCap) {
+        if ((unsigned)lane < cn) outl[Pi + lane] = f.stage[ch * kStageCap + lane];
+      } else {
+        rescan_chunk<T>(f, ch, Pi, lane);
+      }
+    }
+    run += total;
+    __syncthreads();  // s_wt, s_P, s_c are rewritten by the next batch
+  }
+
+  if (g == f.ngroups - 1 && tid == 0) {
+    const uint64_t k = run;
+    const uint64_t ct = chunk_table_offset(n);
+    const uint64_t ce = ct + 8 * nch;
+    const uint64_t oo = outlier_offset(n);
+    for (uint64_t x = 64 + 4 * n; x < ct; x++) f.stream[x] = 0;
+    for (uint64_t x = ce; x < oo; x++) f.stream[x] = 0;
+    uint64_t h[8];
+#pragma unroll
+    for (int i = 0; i < 8; i++) h[i] = f.hdr[i];
+    h[2] = k;
+    if (f.noa) {
+      h[4] = f.noa->step;
+      h[5] = f.noa->bound;
+      h[6] = f.noa->lo;
+      h[7] = f.noa->hi;
+    }
+    uint64_t *hd = reinterpret_cast<uint64_t *>(f.stream);
+#pragma unroll
+    for (int i = 0; i < 8; i++) hd[i] = h[i];
+    *f.stream_bytes = oo + k * sizeof(T);
+  }
+}
+
+// ---------------------------------------------------------- dequantize ---
+// Decode the CPW * kWaves chunks of workgroup `tile`, PF chunks per
+// wavefront loaded at a time.
+template <typename T, int CPW, int PF>
+__device__ void dequant_chunks(const DField<T> &f, uint64_t tile) {
+  static_assert(CPW % PF == 0, "whole prefetch groups");
+  using U = typename FT<T>::U;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const uint64_t n = f.n;
+  const uint64_t nch = n_chunks(n);
+  const int32_t *codes = reinterpret_cast<const int32_t *>(f.stream + 64);
+  const uint64_t *chunk_tab = reinterpret_cast<const uint64_t *>(f.stream + chunk_table_offset(n));
+  const U *outl = reinterpret_cast<const U *>(f.stream + outlier_offset(n));
+  const uint64_t lt = __lanemask_lt();
+#pragma unroll
+  for (int r0 = 0; r0 < CPW; r0 += PF) {
+    int32_t cc[PF][kSub][4];
+#pragma unroll
+    for (int p = 0; p < PF; p++) {
+      const uint64_t c = (tile * CPW + r0 + p) * kWaves + wave;
+      if (c < nch) {
+#pragma unroll
+        for (int j = 0; j < kSub; j++) load_codes4(codes, chunk_value(c, j, lane), n, cc[p][j]);
+      }
+    }
+#pragma unroll
+    for (int p = 0; p < PF; p++) {
+      const uint64_t c = (tile * CPW + r0 + p) * kWaves + wave;
+      if (c >= nch) continue;  // uniform over the wavefront
+      const uint64_t cur = chunk_tab[c];
+      const uint64_t nxt = (c + 1 < nch) ? chunk_tab[c + 1] : f.k;
+      unsigned om = 0;
+      T y[kSub][4];
+#pragma unroll
+      for (int j = 0; j < kSub; j++) {
+        const uint64_t i0 = chunk_value(c, j, lane);
+#pragma unroll
+        for (int e = 0; e < 4; e++) {
+          const bool sent = cc[p][j][e] == kSent;
+          y[j][e] = sent ? (T)0 : decode<T>(cc[p][j][e], f.step, f.rel);
+          if (sent && i0 + e < n) om |= 1u << (4 * j + e);
+        }
+      }
+      uint64_t cnt = 0;
+      if (__ballot(om != 0)) {
+#pragma unroll
+        for (int j = 0; j < kSub; j++) {
+          unsigned pre;
+          const unsigned tot = sub_ranks((om >> (4 * j)) & 0xFu, lt, pre);
+          uint64_t r = cur + cnt + pre;
+#pragma unroll
+          for (int e = 0; e < 4; e++) {
+            if ((om >> (4 * j + e)) & 1u) {
+              // ranks are checked against the outlier count: never read past it
+              y[j][e] = (r < f.k) ? from_bits(outl[r]) : (T)0;
+              r++;
+            }
+          }
+          cnt += tot;
+        }
+      }
+      // the chunk-table entry must count exactly the sentinels before it
+      if (lane == 0 && (cur > f.k || nxt - cur != cnt || (c == 0 && cur != 0)))
+        report_status(f.status, f.tag, LCQ_ERR_STREAM);
+#pragma unroll
+      for (int j = 0; j < kSub; j++) store4(f.out, chunk_value(c, j, lane), n, y[j]);
+    }
+  }
+}
+
+}  // namespace lcq

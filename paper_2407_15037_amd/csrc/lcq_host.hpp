@@ -103,29 +103,37 @@ template <typename T> inline FieldParams<T> field_params(const HostParams &h) {
   return p;
 }
 
-// Launch-shape variants.  A slot is one 128-bit load per thread of a
-// 256-thread workgroup; a tile is slots x rounds of them.  Quantize variants
-// also choose the look-back depth (loads per lane per round trip) and
-// whether the rounds are unrolled.
+// Launch-shape variants.  Variants 0-5 are the single-pass kernels: a slot
+// is one 128-bit load per thread of a 256-thread workgroup and a tile is
+// slots x rounds of them; quantize variants also choose the look-back depth
+// (loads per lane per round trip) and whether the rounds are unrolled.
+// Variants 6-8 are the chunk-per-wavefront kernels (two-pass quantize):
+// cpw chunks per wavefront per workgroup, pf of them loaded at a time.
 struct Shape {
   int slots, rounds;
+  int cpw = 0, pf = 0;  // cpw > 0: chunk-per-wavefront kernel
 };
 struct QShape {
   int slots, rounds, depth;
   bool unroll;
+  int cpw = 0, pf = 0;  // cpw > 0: two-pass chunk-per-wavefront kernel
 };
-constexpr int kNumVariants = 6;
+constexpr int kNumVariants = 9;
 constexpr QShape kQVariants[kNumVariants] = {
     {4, 1, 1, true}, {4, 4, 1, true}, {4, 4, 4, true},
-    {4, 4, 1, false}, {4, 2, 2, true}, {4, 1, 4, true}};
-constexpr Shape kDVariants[kNumVariants] = {{4, 1}, {2, 2}, {4, 2}, {4, 4}, {2, 1}, {8, 1}};
+    {4, 4, 1, false}, {4, 2, 2, true}, {4, 1, 4, true},
+    {0, 0, 0, true, 1, 1}, {0, 0, 0, true, 2, 2}, {0, 0, 0, true, 4, 2}};
+constexpr Shape kDVariants[kNumVariants] = {{4, 1}, {2, 2}, {4, 2}, {4, 4}, {2, 1}, {8, 1},
+                                            {0, 0, 1, 1}, {0, 0, 2, 2}, {0, 0, 4, 2}};
 
 // Values per quantize tile / codes per dequantize tile of a variant.
 inline uint64_t quant_tile_len(lcq_dtype t, int v) {
+  if (kQVariants[v].cpw) return (uint64_t)kChunk * kWaves * kQVariants[v].cpw;
   const uint64_t w = t == LCQ_F64 ? 2 : 4;
   return (uint64_t)kBlock * w * kQVariants[v].slots * kQVariants[v].rounds;
 }
 inline uint64_t deq_tile_len(int v) {
+  if (kDVariants[v].cpw) return (uint64_t)kChunk * kWaves * kDVariants[v].cpw;
   return (uint64_t)kBlock * 4 * kDVariants[v].slots * kDVariants[v].rounds;
 }
 

@@ -196,6 +196,8 @@ def test_every_launch_variant_same_bytes():
     oracle's bytes, including ragged tails and multi-tile look-backs."""
     import torch
     import paper_2407_15037_amd as lcq
+    saved = {tdt: (lcq.tune_get("quantize", tdt), lcq.tune_get("dequantize", tdt))
+             for tdt in (torch.float32, torch.float64)}
     try:
         for v in range(lcq.tune_variants()):
             for dt, tdt in ((np.float32, torch.float32), (np.float64, torch.float64)):
@@ -205,9 +207,9 @@ def test_every_launch_variant_same_bytes():
                     x = _field(dt, 11 * 4096 + 2345, 101 + v, eb, q)
                     _parity(q, x, eb, f"variant {v}")
     finally:
-        for tdt in (torch.float32, torch.float64):
-            lcq.tune_set("quantize", tdt, 0)
-            lcq.tune_set("dequantize", tdt, 0)
+        for tdt, (qv, dv) in saved.items():
+            lcq.tune_set("quantize", tdt, qv)
+            lcq.tune_set("dequantize", tdt, dv)
 
 
 def test_status_word_ignores_workspace_contents():
