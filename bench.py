@@ -109,6 +109,17 @@ def run_plain(args, x, xr):
     t_end.record()
     torch.cuda.synchronize()
     ms_per_step = t_start.elapsed_time(t_end) / args.steps
+    # NOA as a whole operation: range pass, parameters and both quantize
+    # passes, events on the launch stream around the call
+    whole = []
+    for _ in range(max(3, args.steps // 4)):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        lcq.quantize(dx["noa"], "noa", eb, out=bufs["noa"], nbytes=nbs["noa"], ws=ws["noa"])
+        e1.record()
+        torch.cuda.synchronize()
+        whole.append(e0.elapsed_time(e1) * 1e3)
     ks = {q: header_k(bufs[q]) for q in order_q}
     kern = {}
     for (kind, q), pairs in ev.items():
@@ -125,6 +136,7 @@ def run_plain(args, x, xr):
     del dx, bufs, ws, outs
     torch.cuda.empty_cache()
     return dict(ms_per_step=ms_per_step, value=value, kern=kern, ks=ks, sizes=sizes, n=n,
+                noa_whole_us=sum(whole) / len(whole),
                 gpu_streams=gpu_streams, gpu_decodes=gpu_decodes)
 
 
@@ -453,6 +465,7 @@ def main():
                    "n": plain["n"], "eb": args.eb, "quantizers": ["abs", "noa", "rel"]},
         "ops": {k: {"us": round(v["avg_us"], 2), "input_GBs": round(v["gbs_input"], 1),
                     "alg_GBs": round(v["gbs_hbm"], 1)} for k, v in sorted(kern.items())},
+        "quantize_noa_whole_op_us": round(plain["noa_whole_us"], 2),
         "outlier_fraction": {q: plain["ks"][q] / plain["n"] for q in plain["ks"]},
         "stream_bytes": plain["sizes"],
         "autotune": tuned,

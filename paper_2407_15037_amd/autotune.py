@@ -1,11 +1,12 @@
 """Launch-shape autotuner for the per-value kernels.
 
-Every kernel comes in a few variants (loads in flight per thread x rounds per
-tile, see lcq_tune_variants in include/lcq.h); all of them produce the same
-bytes.  The tuner times each variant of quantize and dequantize per dtype on a
-synthetic field resident in HBM, keeps the fastest (median of repeats, HIP
-events around the per-value kernel only) and installs it process-wide.  The
-result can be cached as JSON keyed by the device name.
+Every operation comes in a few kernel variants (see lcq_tune_variants in
+include/lcq.h); all of them produce the same bytes.  The tuner times each
+variant of quantize and dequantize per dtype on two synthetic fields resident
+in HBM (an ABS field with few outliers, a REL field with 1 % of them), keeps
+the fastest total (medians of repeats, HIP events around the operation's
+kernels) and installs it process-wide.  The result can be cached as JSON
+keyed by the device name.
 """
 import json
 import os
@@ -22,51 +23,75 @@ def _field(n, dtype, device):
     return x.to(dtype).to(device)
 
 
-def tune(n=1 << 26, reps=7, quantizer="abs", eb=1e-3, device="cuda", dtypes=None, install=True,
-         log=None):
-    """Returns {dtype_name: {op: {"best": v, "us": [per-variant median us]}}}."""
+def _rel_field(n, dtype, device):
+    """Magnitudes log-uniform over 2^(+-40), random signs, 1 % zeros: a REL
+    field with about 1 % of its values stored losslessly."""
+    import torch
+    g = torch.Generator(device=device).manual_seed(4321)
+    u = torch.rand(n, generator=g, device=device, dtype=torch.float64)
+    s = torch.rand(n, generator=g, device=device, dtype=torch.float64)
+    x = torch.exp2(u * 80.0 - 40.0) * torch.where(s < 0.5, -1.0, 1.0)
+    x = torch.where(s > 0.99, torch.zeros_like(x), x)
+    return x.to(dtype)
+
+
+def tune(n=1 << 26, reps=7, eb=1e-3, device="cuda", dtypes=None, install=True, log=None):
+    """Time every launch variant of quantize and dequantize on an ABS field
+    (smooth, few outliers) and a REL field (1 % outliers) per dtype; the
+    fastest total wins.  Returns {dtype_name: {op: {"best": v, "us":
+    [per-variant summed median us]}}}."""
     import torch
     dtypes = dtypes or (torch.float32, torch.float64)
     result = {}
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
     e0.record(); e1.record()
+
+    def timed(fn):
+        ts = []
+        for r in range(reps + 2):
+            lcq.profile_events(e0, e1)
+            fn()
+            lcq.profile_events(None, None)
+            torch.cuda.synchronize()
+            if r >= 2:
+                ts.append(e0.elapsed_time(e1) * 1e3)
+        ts.sort()
+        return ts[len(ts) // 2]
+
     for dt in dtypes:
         m = n if dt == torch.float32 else n // 2
-        x = _field(m, dt, device)
+        cases = [("abs", _field(m, dt, device)), ("rel", _rel_field(m, dt, device))]
         cap = lcq.max_stream_bytes(dt, m)
-        buf = torch.empty(cap, dtype=torch.uint8, device=device)
-        nb = torch.empty(1, dtype=torch.int64, device=device)
-        ws = torch.empty(lcq.workspace_bytes(quantizer, dt, m), dtype=torch.uint8, device=device)
+        bufs = [torch.empty(cap, dtype=torch.uint8, device=device) for _ in cases]
+        nbs = [torch.empty(1, dtype=torch.int64, device=device) for _ in cases]
+        ws = torch.empty(lcq.workspace_bytes("noa", dt, m), dtype=torch.uint8, device=device)
         out = torch.empty(m, dtype=dt, device=device)
         name = str(dt).replace("torch.", "")
         result[name] = {}
         saved = {op: lcq.tune_get(op, dt) for op in OPS}
+        for (q, x), buf, nb in zip(cases, bufs, nbs):
+            lcq.quantize(x, q, eb, out=buf, nbytes=nb, ws=ws)
+        torch.cuda.synchronize()
+        sizes = [int(nb.item()) for nb in nbs]
         for op in OPS:
-            med = []
+            tot = []
             for v in range(lcq.tune_variants()):
                 lcq.tune_set(op, dt, v)
-                ts = []
-                for r in range(reps + 2):
-                    lcq.profile_events(e0, e1)
+                t = 0.0
+                for (q, x), buf, nb, size in zip(cases, bufs, nbs, sizes):
                     if op == "quantize":
-                        lcq.quantize(x, quantizer, eb, out=buf, nbytes=nb, ws=ws)
+                        t += timed(lambda: lcq.quantize(x, q, eb, out=buf, nbytes=nb, ws=ws))
                     else:
-                        lcq.dequantize(buf, dt, m, out=out, ws=ws)
-                    lcq.profile_events(None, None)
-                    torch.cuda.synchronize()
-                    if r >= 2:
-                        ts.append(e0.elapsed_time(e1) * 1e3)
-                ts.sort()
-                med.append(ts[len(ts) // 2])
-                if op == "quantize":
-                    lcq.tune_set(op, dt, saved[op])
-            best = min(range(len(med)), key=lambda i: med[i])
-            result[name][op] = {"best": best, "us": [round(t, 1) for t in med]}
+                        t += timed(lambda: lcq.dequantize(buf, dt, m, stream_bytes=size, out=out,
+                                                          ws=ws))
+                tot.append(t)
+            best = min(range(len(tot)), key=lambda i: tot[i])
+            result[name][op] = {"best": best, "us": [round(t, 1) for t in tot]}
             lcq.tune_set(op, dt, best if install else saved[op])
             if log:
                 log(f"autotune {name} {op}: {result[name][op]}")
-        del x, buf, out, ws
+        del cases, bufs, out, ws
     return result
 
 

@@ -46,7 +46,7 @@ namespace {
 // then       NOA per-workgroup (min, max) pairs
 constexpr uint64_t kWsParams = 64;
 constexpr uint64_t kWsState = 256;
-constexpr int kMinmaxBlocks = 2048;
+constexpr int kMinmaxBlocks = 8192;
 constexpr uint64_t kMinTileF32 = 4096, kMinTileF64 = 2048;  // smallest quantize tile of any variant
 
 thread_local hipEvent_t g_ev_before = nullptr, g_ev_after = nullptr;

@@ -32,6 +32,12 @@
 
 namespace lcq {
 
+// Streamed data is touched once: its loads and stores are non-temporal
+// (clang's nontemporal builtins need native vector types).
+typedef float nt_f4 __attribute__((ext_vector_type(4)));
+typedef double nt_d2 __attribute__((ext_vector_type(2)));
+typedef int nt_i4 __attribute__((ext_vector_type(4)));
+
 constexpr int kSub = 4;             // 256-value sub-blocks per chunk
 constexpr int kStageCap = 32;       // outliers staged per chunk in pass 1
 constexpr uint64_t kMaxGroups = 1024;  // pass-2 workgroups (groups) at most
@@ -41,11 +47,11 @@ template <typename T>
 __device__ __forceinline__ void load4(const T *in, uint64_t i0, uint64_t n, T (&x)[4]) {
   if (i0 + 4 <= n) {
     if constexpr (sizeof(T) == 4) {
-      const float4 v = *reinterpret_cast<const float4 *>(in + i0);
+      const nt_f4 v = __builtin_nontemporal_load(reinterpret_cast<const nt_f4 *>(in + i0));
       x[0] = v.x; x[1] = v.y; x[2] = v.z; x[3] = v.w;
     } else {
-      const double2 a = *reinterpret_cast<const double2 *>(in + i0);
-      const double2 b = *reinterpret_cast<const double2 *>(in + i0 + 2);
+      const nt_d2 a = __builtin_nontemporal_load(reinterpret_cast<const nt_d2 *>(in + i0));
+      const nt_d2 b = __builtin_nontemporal_load(reinterpret_cast<const nt_d2 *>(in + i0 + 2));
       x[0] = a.x; x[1] = a.y; x[2] = b.x; x[3] = b.y;
     }
   } else {
@@ -58,10 +64,12 @@ template <typename T>
 __device__ __forceinline__ void store4(T *out, uint64_t i0, uint64_t n, const T (&y)[4]) {
   if (i0 + 4 <= n) {
     if constexpr (sizeof(T) == 4) {
-      *reinterpret_cast<float4 *>(out + i0) = make_float4(y[0], y[1], y[2], y[3]);
+      const nt_f4 o = {y[0], y[1], y[2], y[3]};
+      __builtin_nontemporal_store(o, reinterpret_cast<nt_f4 *>(out + i0));
     } else {
-      *reinterpret_cast<double2 *>(out + i0) = make_double2(y[0], y[1]);
-      *reinterpret_cast<double2 *>(out + i0 + 2) = make_double2(y[2], y[3]);
+      const nt_d2 o0 = {y[0], y[1]}, o1 = {y[2], y[3]};
+      __builtin_nontemporal_store(o0, reinterpret_cast<nt_d2 *>(out + i0));
+      __builtin_nontemporal_store(o1, reinterpret_cast<nt_d2 *>(out + i0 + 2));
     }
   } else {
 #pragma unroll
@@ -73,7 +81,7 @@ __device__ __forceinline__ void store4(T *out, uint64_t i0, uint64_t n, const T 
 __device__ __forceinline__ void load_codes4(const int32_t *codes, uint64_t i0, uint64_t n,
                                             int32_t (&c)[4]) {
   if (i0 + 4 <= n) {
-    const int4 v = *reinterpret_cast<const int4 *>(codes + i0);
+    const nt_i4 v = __builtin_nontemporal_load(reinterpret_cast<const nt_i4 *>(codes + i0));
     c[0] = v.x; c[1] = v.y; c[2] = v.z; c[3] = v.w;
   } else {
 #pragma unroll
@@ -150,7 +158,8 @@ __device__ void quant_chunks(const StageField<T> &f, uint64_t tile) {
           if (code[e] == kSent && i0 + e < n) om |= 1u << (4 * j + e);
         }
         if (i0 + 4 <= n) {
-          *reinterpret_cast<int4 *>(f.codes + i0) = make_int4(code[0], code[1], code[2], code[3]);
+          const nt_i4 o = {code[0], code[1], code[2], code[3]};
+          __builtin_nontemporal_store(o, reinterpret_cast<nt_i4 *>(f.codes + i0));
         } else {
 #pragma unroll
           for (int e = 0; e < 4; e++)
