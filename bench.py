@@ -156,7 +156,7 @@ def run_inline(args, x, xr, plain):
     dx["rel"] = torch.from_numpy(xr).to(dev)
     nb = lcq.inline_stream_bytes(torch.float32, n)
     bufs = {q: torch.empty(nb, dtype=torch.uint8, device=dev) for q in order_q}
-    ws = torch.empty(1 << 16, dtype=torch.uint8, device=dev)
+    ws = torch.empty(lcq.inline_workspace_bytes("noa"), dtype=torch.uint8, device=dev)
     outs = {q: torch.empty(n, dtype=torch.float32, device=dev) for q in order_q}
     ev = {}
     reps = max(3, args.steps // 2)

@@ -11,7 +11,7 @@ import os
 __all__ = ["ABS", "REL", "NOA", "F32", "F64", "LCQError", "lib", "max_stream_bytes",
            "workspace_bytes", "quantize", "dequantize", "stream_status", "profile_events",
            "set_lookback_spin", "tune_variants", "tune_set", "tune_get",
-           "inline_stream_bytes", "quantize_inline", "dequantize_inline", "SO_PATH"]
+           "inline_stream_bytes", "inline_workspace_bytes", "quantize_inline", "dequantize_inline", "SO_PATH"]
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 SO_PATH = os.path.join(HERE, "liblcq.so")
@@ -153,6 +153,10 @@ def dequantize(stream_buf, dtype, n, *, stream_bytes=None, out=None, ws=None, st
 
 def inline_stream_bytes(dtype, n):
     return int(_lib.lcq_inline_stream_bytes(_dtype_code(dtype), n))
+
+
+def inline_workspace_bytes(q):
+    return int(_lib.lcq_inline_workspace_bytes(_q(q)))
 
 
 def quantize_inline(x, q, eb, *, out=None, ws=None, stream=None):

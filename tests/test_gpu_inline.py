@@ -139,7 +139,7 @@ def test_inline_buffer_reuse():
     xt = torch.from_numpy(x).cuda()
     out = torch.full((lcq.inline_stream_bytes(torch.float32, x.size),), 0xAB, dtype=torch.uint8,
                      device="cuda")
-    ws = torch.empty(1 << 16, dtype=torch.uint8, device="cuda")
+    ws = torch.empty(lcq.inline_workspace_bytes("noa"), dtype=torch.uint8, device="cuda")
     announce("inline reuse")
     for m in (x.size, 4096 + 5, 13):
         for q in ("abs", "noa", "rel"):
