@@ -145,7 +145,22 @@ template <typename T>
 __global__ __launch_bounds__(kBlock) void k_noa_params(const T *partials, int nparts, T eb_down,
                                                        DevParams *out) {
   T lo = (T)INFINITY, hi = (T)-INFINITY;
-  for (int i = threadIdx.x; i < nparts; i += kBlock) {
+  // eight (min, max) pairs in flight per thread, then the rest one by one
+  int i = threadIdx.x;
+  for (; i + 7 * kBlock < nparts; i += 8 * kBlock) {
+    T l[8], h[8];
+#pragma unroll
+    for (int u = 0; u < 8; u++) {
+      l[u] = partials[2 * (i + u * kBlock)];
+      h[u] = partials[2 * (i + u * kBlock) + 1];
+    }
+#pragma unroll
+    for (int u = 0; u < 8; u++) {
+      lo = fmin(lo, l[u]);
+      hi = fmax(hi, h[u]);
+    }
+  }
+  for (; i < nparts; i += kBlock) {
     lo = fmin(lo, partials[2 * i]);
     hi = fmax(hi, partials[2 * i + 1]);
   }

@@ -1,12 +1,12 @@
 // lcq_chunk.hpp -- chunk-per-wavefront quantize / dequantize for gfx950.
 //
 // One 64-lane wavefront owns one 1024-value chunk of the stream format (the
-// granularity of its chunk table).  Lane l holds values 256 j + 4 l + e of
-// the chunk (sub-block j = 0..3, e = 0..3): each sub-block is one contiguous
-// 256-value run, so every load and store of a wavefront is a contiguous
-// 1 KiB (codes, float32) or 2 KiB (float64) access.  Ranks of outliers
-// inside a chunk follow from ballots alone; no LDS and no barrier is needed
-// for them.
+// granularity of its chunk table).  With W = 16 / sizeof(T), lane l holds
+// values 64 W j + W l + e of the chunk (e < W): each sub-block j is one
+// contiguous run of 64 W values, so every load and store instruction of a
+// wavefront covers one contiguous 1 KiB (values) or 1 KiB / 512 B (codes,
+// float32 / float64) range.  Ranks of outliers inside a chunk follow from
+// ballots alone; no LDS and no barrier is needed for them.
 //
 // Quantize runs as two passes instead of one pass with a decoupled
 // look-back:
@@ -37,72 +37,105 @@ namespace lcq {
 typedef float nt_f4 __attribute__((ext_vector_type(4)));
 typedef double nt_d2 __attribute__((ext_vector_type(2)));
 typedef int nt_i4 __attribute__((ext_vector_type(4)));
+typedef int nt_i2 __attribute__((ext_vector_type(2)));
 
-constexpr int kSub = 4;             // 256-value sub-blocks per chunk
 constexpr int kStageCap = 32;       // outliers staged per chunk in pass 1
 constexpr uint64_t kMaxGroups = 1024;  // pass-2 workgroups (groups) at most
 
-// Four consecutive values at i0 (zeros past n).
-template <typename T>
-__device__ __forceinline__ void load4(const T *in, uint64_t i0, uint64_t n, T (&x)[4]) {
-  if (i0 + 4 <= n) {
+// A lane holds W = 16 / sizeof(T) consecutive values of each sub-block (one
+// 128-bit access), so a chunk is NSUB = 1024 / (64 W) sub-blocks and every
+// lane holds 16 values of it: 4 x 4 (float32) or 8 x 2 (float64).
+template <typename T> struct ChunkShape {
+  static constexpr int W = 16 / (int)sizeof(T);
+  static constexpr int NSUB = (int)kChunk / (64 * W);
+  static_assert(W * NSUB == 16, "16 values per lane per chunk");
+};
+
+// W consecutive values at i0 (zeros past n).
+template <typename T, int W>
+__device__ __forceinline__ void load_vals(const T *in, uint64_t i0, uint64_t n, T (&x)[W]) {
+  if (i0 + W <= n) {
     if constexpr (sizeof(T) == 4) {
       const nt_f4 v = __builtin_nontemporal_load(reinterpret_cast<const nt_f4 *>(in + i0));
       x[0] = v.x; x[1] = v.y; x[2] = v.z; x[3] = v.w;
     } else {
-      const nt_d2 a = __builtin_nontemporal_load(reinterpret_cast<const nt_d2 *>(in + i0));
-      const nt_d2 b = __builtin_nontemporal_load(reinterpret_cast<const nt_d2 *>(in + i0 + 2));
-      x[0] = a.x; x[1] = a.y; x[2] = b.x; x[3] = b.y;
+      const nt_d2 v = __builtin_nontemporal_load(reinterpret_cast<const nt_d2 *>(in + i0));
+      x[0] = v.x; x[1] = v.y;
     }
   } else {
 #pragma unroll
-    for (int e = 0; e < 4; e++) x[e] = (i0 + e < n) ? in[i0 + e] : (T)0;
+    for (int e = 0; e < W; e++) x[e] = (i0 + e < n) ? in[i0 + e] : (T)0;
   }
 }
 
-template <typename T>
-__device__ __forceinline__ void store4(T *out, uint64_t i0, uint64_t n, const T (&y)[4]) {
-  if (i0 + 4 <= n) {
+template <typename T, int W>
+__device__ __forceinline__ void store_vals(T *out, uint64_t i0, uint64_t n, const T (&y)[W]) {
+  if (i0 + W <= n) {
     if constexpr (sizeof(T) == 4) {
       const nt_f4 o = {y[0], y[1], y[2], y[3]};
       __builtin_nontemporal_store(o, reinterpret_cast<nt_f4 *>(out + i0));
     } else {
-      const nt_d2 o0 = {y[0], y[1]}, o1 = {y[2], y[3]};
-      __builtin_nontemporal_store(o0, reinterpret_cast<nt_d2 *>(out + i0));
-      __builtin_nontemporal_store(o1, reinterpret_cast<nt_d2 *>(out + i0 + 2));
+      const nt_d2 o = {y[0], y[1]};
+      __builtin_nontemporal_store(o, reinterpret_cast<nt_d2 *>(out + i0));
     }
   } else {
 #pragma unroll
-    for (int e = 0; e < 4; e++)
+    for (int e = 0; e < W; e++)
       if (i0 + e < n) out[i0 + e] = y[e];
   }
 }
 
-__device__ __forceinline__ void load_codes4(const int32_t *codes, uint64_t i0, uint64_t n,
-                                            int32_t (&c)[4]) {
-  if (i0 + 4 <= n) {
-    const nt_i4 v = __builtin_nontemporal_load(reinterpret_cast<const nt_i4 *>(codes + i0));
-    c[0] = v.x; c[1] = v.y; c[2] = v.z; c[3] = v.w;
+template <int W>
+__device__ __forceinline__ void load_codes(const int32_t *codes, uint64_t i0, uint64_t n,
+                                           int32_t (&c)[W]) {
+  if (i0 + W <= n) {
+    if constexpr (W == 4) {
+      const nt_i4 v = __builtin_nontemporal_load(reinterpret_cast<const nt_i4 *>(codes + i0));
+      c[0] = v.x; c[1] = v.y; c[2] = v.z; c[3] = v.w;
+    } else {
+      const nt_i2 v = __builtin_nontemporal_load(reinterpret_cast<const nt_i2 *>(codes + i0));
+      c[0] = v.x; c[1] = v.y;
+    }
   } else {
 #pragma unroll
-    for (int e = 0; e < 4; e++) c[e] = (i0 + e < n) ? codes[i0 + e] : 0;
+    for (int e = 0; e < W; e++) c[e] = (i0 + e < n) ? codes[i0 + e] : 0;
+  }
+}
+
+template <int W>
+__device__ __forceinline__ void store_codes(int32_t *codes, uint64_t i0, uint64_t n,
+                                            const int32_t (&c)[W]) {
+  if (i0 + W <= n) {
+    if constexpr (W == 4) {
+      const nt_i4 o = {c[0], c[1], c[2], c[3]};
+      __builtin_nontemporal_store(o, reinterpret_cast<nt_i4 *>(codes + i0));
+    } else {
+      const nt_i2 o = {c[0], c[1]};
+      __builtin_nontemporal_store(o, reinterpret_cast<nt_i2 *>(codes + i0));
+    }
+  } else {
+#pragma unroll
+    for (int e = 0; e < W; e++)
+      if (i0 + e < n) codes[i0 + e] = c[e];
   }
 }
 
 // Sub-block j of chunk c, lane's first value.
+template <int W>
 __device__ __forceinline__ uint64_t chunk_value(uint64_t c, int j, int lane) {
-  return c * kChunk + 256u * (unsigned)j + 4u * (unsigned)lane;
+  return c * kChunk + (uint64_t)(64 * W) * (unsigned)j + (uint64_t)W * (unsigned)lane;
 }
 
 // Ranks of flagged values of one sub-block inside the wavefront's chunk:
 // returns the count of the sub-block to every lane, and in `pre` the number
-// of flagged values of lower lanes.  `f4` holds the lane's 4 flags.
-__device__ __forceinline__ unsigned sub_ranks(unsigned f4, uint64_t lt, unsigned &pre) {
+// of flagged values of lower lanes.  `fl` holds the lane's W flags.
+template <int W>
+__device__ __forceinline__ unsigned sub_ranks(unsigned fl, uint64_t lt, unsigned &pre) {
   unsigned tot = 0;
   pre = 0;
 #pragma unroll
-  for (int e = 0; e < 4; e++) {
-    const uint64_t b = __ballot((f4 >> e) & 1u);
+  for (int e = 0; e < W; e++) {
+    const uint64_t b = __ballot((fl >> e) & 1u);
     tot += (unsigned)__popcll(b);
     pre += (unsigned)__popcll(b & lt);
   }
@@ -126,6 +159,8 @@ template <typename T> struct StageField {
 template <typename T, int Q, int CPW, int PF>
 __device__ void quant_chunks(const StageField<T> &f, uint64_t tile) {
   static_assert(CPW % PF == 0, "whole prefetch groups");
+  constexpr int W = ChunkShape<T>::W, NSUB = ChunkShape<T>::NSUB;
+  constexpr unsigned kLaneMask = (1u << W) - 1;
   __shared__ unsigned s_cnt[kWaves];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const uint64_t n = f.n;
@@ -134,13 +169,13 @@ __device__ void quant_chunks(const StageField<T> &f, uint64_t tile) {
   unsigned wsum = 0;
 #pragma unroll
   for (int r0 = 0; r0 < CPW; r0 += PF) {
-    T x[PF][kSub][4];
+    T x[PF][NSUB][W];
 #pragma unroll
     for (int p = 0; p < PF; p++) {
       const uint64_t c = (tile * CPW + r0 + p) * kWaves + wave;
       if (c < nch) {
 #pragma unroll
-        for (int j = 0; j < kSub; j++) load4(f.in, chunk_value(c, j, lane), n, x[p][j]);
+        for (int j = 0; j < NSUB; j++) load_vals<T, W>(f.in, chunk_value<W>(c, j, lane), n, x[p][j]);
       }
     }
 #pragma unroll
@@ -149,33 +184,26 @@ __device__ void quant_chunks(const StageField<T> &f, uint64_t tile) {
       if (c >= nch) continue;  // uniform over the wavefront
       unsigned om = 0;
 #pragma unroll
-      for (int j = 0; j < kSub; j++) {
-        const uint64_t i0 = chunk_value(c, j, lane);
-        int32_t code[4];
+      for (int j = 0; j < NSUB; j++) {
+        const uint64_t i0 = chunk_value<W>(c, j, lane);
+        int32_t code[W];
 #pragma unroll
-        for (int e = 0; e < 4; e++) {
+        for (int e = 0; e < W; e++) {
           code[e] = encode<T, Q>(x[p][j][e], f.p);
-          if (code[e] == kSent && i0 + e < n) om |= 1u << (4 * j + e);
+          if (code[e] == kSent && i0 + e < n) om |= 1u << (W * j + e);
         }
-        if (i0 + 4 <= n) {
-          const nt_i4 o = {code[0], code[1], code[2], code[3]};
-          __builtin_nontemporal_store(o, reinterpret_cast<nt_i4 *>(f.codes + i0));
-        } else {
-#pragma unroll
-          for (int e = 0; e < 4; e++)
-            if (i0 + e < n) f.codes[i0 + e] = code[e];
-        }
+        store_codes<W>(f.codes, i0, n, code);
       }
       unsigned cnt = 0;
       if (__ballot(om != 0)) {
 #pragma unroll
-        for (int j = 0; j < kSub; j++) {
+        for (int j = 0; j < NSUB; j++) {
           unsigned pre;
-          const unsigned tot = sub_ranks((om >> (4 * j)) & 0xFu, lt, pre);
+          const unsigned tot = sub_ranks<W>((om >> (W * j)) & kLaneMask, lt, pre);
           unsigned r = cnt + pre;
 #pragma unroll
-          for (int e = 0; e < 4; e++) {
-            if ((om >> (4 * j + e)) & 1u) {
+          for (int e = 0; e < W; e++) {
+            if ((om >> (W * j + e)) & 1u) {
               if (r < (unsigned)kStageCap) f.stage[c * kStageCap + r] = to_bits(x[p][j][e]);
               r++;
             }
@@ -217,26 +245,27 @@ template <typename T> struct FinishField {
 template <typename T>
 __device__ void rescan_chunk(const FinishField<T> &f, uint64_t c, uint64_t P, int lane) {
   using U = typename FT<T>::U;
+  constexpr int W = ChunkShape<T>::W, NSUB = ChunkShape<T>::NSUB;
   const int32_t *codes = reinterpret_cast<const int32_t *>(f.stream + 64);
   U *outl = reinterpret_cast<U *>(f.stream + outlier_offset(f.n));
   const U *inb = reinterpret_cast<const U *>(f.in);
   const uint64_t lt = __lanemask_lt();
   uint64_t run = P;
 #pragma unroll
-  for (int j = 0; j < kSub; j++) {
-    const uint64_t i0 = chunk_value(c, j, lane);
-    int32_t cc[4];
-    load_codes4(codes, i0, f.n, cc);
-    unsigned f4 = 0;
+  for (int j = 0; j < NSUB; j++) {
+    const uint64_t i0 = chunk_value<W>(c, j, lane);
+    int32_t cc[W];
+    load_codes<W>(codes, i0, f.n, cc);
+    unsigned fl = 0;
 #pragma unroll
-    for (int e = 0; e < 4; e++)
-      if (cc[e] == kSent && i0 + e < f.n) f4 |= 1u << e;
+    for (int e = 0; e < W; e++)
+      if (cc[e] == kSent && i0 + e < f.n) fl |= 1u << e;
     unsigned pre;
-    const unsigned tot = sub_ranks(f4, lt, pre);
+    const unsigned tot = sub_ranks<W>(fl, lt, pre);
     uint64_t r = run + pre;
 #pragma unroll
-    for (int e = 0; e < 4; e++)
-      if ((f4 >> e) & 1u) outl[r++] = inb[i0 + e];
+    for (int e = 0; e < W; e++)
+      if ((fl >> e) & 1u) outl[r++] = inb[i0 + e];
     run += tot;
   }
 }
@@ -287,20 +316,25 @@ __device__ void quant_finish(const FinishField<T> &f, uint64_t g) {
     }
     const uint64_t P = run + before + (incl - cnt);
     if (c < c1) chunk_tab[c] = P;
-    s_P[tid] = P;
+    s_P[tid] = before + (incl - cnt);  // batch-relative first outlier of each chunk
     s_c[tid] = cnt;
     __syncthreads();
     const int m = (int)min<uint64_t>((uint64_t)kBlock, c1 - cb);
-    for (int i = wave; i < m; i += kWaves) {
-      const unsigned cn = s_c[i];
-      if (cn == 0) continue;
-      const uint64_t Pi = s_P[i];
-      const uint64_t ch = cb + (uint64_t)i;
-      if (cn <= (unsigned)kStageCap) {
-        if ((unsigned)lane < cn) outl[Pi + lane] = f.stage[ch * kStageCap + lane];
-      } else {
-        rescan_chunk<T>(f, ch, Pi, lane);
+    // staged outliers: thread t moves outliers t, t + 256, ... of the batch;
+    // its chunk is the last one starting at or before that rank
+    for (uint64_t o = tid; o < total; o += kBlock) {
+      int lo = 0, hi = m - 1;
+      while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (s_P[mid] <= o) lo = mid;
+        else hi = mid - 1;
       }
+      if (s_c[lo] <= (unsigned)kStageCap)
+        outl[run + o] = f.stage[(cb + (uint64_t)lo) * kStageCap + (o - s_P[lo])];
+    }
+    // chunks with more outliers than were staged: rescanned by a wavefront
+    for (int i = wave; i < m; i += kWaves) {
+      if (s_c[i] > (unsigned)kStageCap) rescan_chunk<T>(f, cb + (uint64_t)i, run + s_P[i], lane);
     }
     run += total;
     __syncthreads();  // s_wt, s_P, s_c are rewritten by the next batch
@@ -337,6 +371,8 @@ template <typename T, int CPW, int PF>
 __device__ void dequant_chunks(const DField<T> &f, uint64_t tile) {
   static_assert(CPW % PF == 0, "whole prefetch groups");
   using U = typename FT<T>::U;
+  constexpr int W = ChunkShape<T>::W, NSUB = ChunkShape<T>::NSUB;
+  constexpr unsigned kLaneMask = (1u << W) - 1;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const uint64_t n = f.n;
   const uint64_t nch = n_chunks(n);
@@ -346,13 +382,13 @@ __device__ void dequant_chunks(const DField<T> &f, uint64_t tile) {
   const uint64_t lt = __lanemask_lt();
 #pragma unroll
   for (int r0 = 0; r0 < CPW; r0 += PF) {
-    int32_t cc[PF][kSub][4];
+    int32_t cc[PF][NSUB][W];
 #pragma unroll
     for (int p = 0; p < PF; p++) {
       const uint64_t c = (tile * CPW + r0 + p) * kWaves + wave;
       if (c < nch) {
 #pragma unroll
-        for (int j = 0; j < kSub; j++) load_codes4(codes, chunk_value(c, j, lane), n, cc[p][j]);
+        for (int j = 0; j < NSUB; j++) load_codes<W>(codes, chunk_value<W>(c, j, lane), n, cc[p][j]);
       }
     }
 #pragma unroll
@@ -362,27 +398,27 @@ __device__ void dequant_chunks(const DField<T> &f, uint64_t tile) {
       const uint64_t cur = chunk_tab[c];
       const uint64_t nxt = (c + 1 < nch) ? chunk_tab[c + 1] : f.k;
       unsigned om = 0;
-      T y[kSub][4];
+      T y[NSUB][W];
 #pragma unroll
-      for (int j = 0; j < kSub; j++) {
-        const uint64_t i0 = chunk_value(c, j, lane);
+      for (int j = 0; j < NSUB; j++) {
+        const uint64_t i0 = chunk_value<W>(c, j, lane);
 #pragma unroll
-        for (int e = 0; e < 4; e++) {
+        for (int e = 0; e < W; e++) {
           const bool sent = cc[p][j][e] == kSent;
           y[j][e] = sent ? (T)0 : decode<T>(cc[p][j][e], f.step, f.rel);
-          if (sent && i0 + e < n) om |= 1u << (4 * j + e);
+          if (sent && i0 + e < n) om |= 1u << (W * j + e);
         }
       }
       uint64_t cnt = 0;
       if (__ballot(om != 0)) {
 #pragma unroll
-        for (int j = 0; j < kSub; j++) {
+        for (int j = 0; j < NSUB; j++) {
           unsigned pre;
-          const unsigned tot = sub_ranks((om >> (4 * j)) & 0xFu, lt, pre);
+          const unsigned tot = sub_ranks<W>((om >> (W * j)) & kLaneMask, lt, pre);
           uint64_t r = cur + cnt + pre;
 #pragma unroll
-          for (int e = 0; e < 4; e++) {
-            if ((om >> (4 * j + e)) & 1u) {
+          for (int e = 0; e < W; e++) {
+            if ((om >> (W * j + e)) & 1u) {
               // ranks are checked against the outlier count: never read past it
               y[j][e] = (r < f.k) ? from_bits(outl[r]) : (T)0;
               r++;
@@ -395,7 +431,7 @@ __device__ void dequant_chunks(const DField<T> &f, uint64_t tile) {
       if (lane == 0 && (cur > f.k || nxt - cur != cnt || (c == 0 && cur != 0)))
         report_status(f.status, f.tag, LCQ_ERR_STREAM);
 #pragma unroll
-      for (int j = 0; j < kSub; j++) store4(f.out, chunk_value(c, j, lane), n, y[j]);
+      for (int j = 0; j < NSUB; j++) store_vals<T, W>(f.out, chunk_value<W>(c, j, lane), n, y[j]);
     }
   }
 }
