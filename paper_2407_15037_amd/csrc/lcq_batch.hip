@@ -8,12 +8,17 @@
 // fields first).  A phase-A item reduces its slice's finite min / max; the
 // field's last slice to finish derives the field's parameters on the device
 // and raises the field's ready flag.  A phase-B item of a NOA field waits for
-// that flag, then runs the same quant_tile as the plain path; the outlier-
-// offset look-back runs inside each field.  Both waits are bounded, with a
-// fallback that computes the awaited value from the input.
+// that flag (bounded, with a fallback that derives the parameters from the
+// input), then runs the plain path's per-tile code:
+//   chunk variant  the streaming pass of the two-pass quantize (codes, chunk
+//                  counts, staged outliers); a second kernel then runs one
+//                  workgroup per (field, chunk group) to write chunk tables,
+//                  outliers and headers;
+//   tile variants  quant_tile with its decoupled look-back inside each field
+//                  (bounded wait, fallback counting from the input).
 //
 // Dequantize: one kernel with a workgroup per dequantize tile of every field
-// (independent tiles), mapped through an item table.
+// (independent tiles, one wavefront per chunk), mapped through an item table.
 //
 // Both are captured once into HIP graphs at plan creation; running the batch
 // is one hipGraphLaunch.  Every field's stream and decode are byte-identical
@@ -33,6 +38,7 @@
 #include "lcq_host.hpp"
 #include "lcq_math.hpp"
 #include "lcq_tile.hpp"
+#include "lcq_chunk.hpp"
 
 #pragma clang fp contract(off)
 
@@ -40,19 +46,23 @@ using namespace lcq;
 
 namespace {
 
-// Batch tile shapes (slots, rounds) per dtype; the tuner picks one.
+// Batch quantize variants: variant 0 is the two-pass chunk form (4 chunks,
+// 4096 values, per workgroup); 1-3 are look-back tile shapes (slots, rounds)
+// per dtype.  The tuner picks one.
 struct BatchShape {
   Shape f32, f64;
+  bool chunk;
 };
-constexpr int kNumBatchVariants = 3;
+constexpr int kNumBatchVariants = 4;
 constexpr BatchShape kBatchVariants[kNumBatchVariants] = {
-    {{4, 4}, {4, 8}},  // 16384-value tiles
-    {{4, 2}, {4, 4}},  // 8192
-    {{4, 1}, {4, 2}},  // 4096
+    {{0, 0}, {0, 0}, true},     // chunk-per-wavefront, two passes
+    {{4, 4}, {4, 8}, false},    // 16384-value tiles
+    {{4, 2}, {4, 4}, false},    // 8192
+    {{4, 1}, {4, 2}, false},    // 4096
 };
+constexpr uint64_t kChunkTile = kChunk * kWaves;  // values per chunk-form workgroup
 constexpr uint64_t kSlice = 1ull << 18;  // values per NOA range item
-constexpr int kDeqSlots = 4, kDeqRounds = 1;
-constexpr uint64_t kDeqTile = (uint64_t)kBlock * 4 * kDeqSlots * kDeqRounds;
+constexpr uint64_t kDeqTile = kChunk * kWaves;  // codes per dequantize workgroup
 
 // Device descriptor of one field.
 struct BField {
@@ -62,8 +72,10 @@ struct BField {
   uint64_t stream_cap;
   uint64_t *stream_bytes;
   void *out;
-  uint64_t state_off;    // first look-back word of this field
+  uint64_t state_off;    // first look-back word of this field (tile variants)
   uint64_t ntiles;       // quantize tiles
+  uint64_t counts_off, stage_off, group_off;  // chunk variant: workspace offsets
+  uint64_t tiles_per_group, chunks_per_group, ngroups;
   uint64_t step, inv, bound, low;  // host-derived parameters (ABS / REL)
   uint64_t hdr[8];
   uint64_t eb_down;      // NOA: RD_T(eb)
@@ -75,7 +87,8 @@ struct BField {
 
 // Workspace layout of a plan (byte offsets).
 struct Layout {
-  uint64_t head, fields, items_q, items_d, params, done, state, partials, dstatus, args, total;
+  uint64_t head, fields, items_q, items_d, items_f, params, done, state, groups, counts, stage,
+      partials, dstatus, args, total;
   uint64_t clear_begin, clear_words;  // u64 words zeroed before each quantize
 };
 
@@ -83,6 +96,8 @@ struct BatchQArgs {
   const BField *fields;
   const uint64_t *items;  // (field << 32) | (local index); phase A first
   uint64_t n_a, n_items;
+  const uint64_t *items_f;  // chunk variant: (field << 32) | group
+  uint8_t *ws;              // workspace base (chunk variant areas)
   unsigned *head;
   DevParams *params;
   unsigned *done;
@@ -167,9 +182,64 @@ __device__ __forceinline__ void range_item(const BatchQArgs &a, const BField &f,
   }
 }
 
+// Parameters of a NOA field for one of its phase-B workgroups.  Every range
+// item of the field left the queue before this one and never waits, so the
+// ready flag comes; the wait is bounded all the same: past the bound this
+// workgroup derives the same parameters from the whole field itself (min /
+// max do not depend on order).
+template <typename T>
+__device__ DevParams noa_field_params(const BatchQArgs &a, const BField &bf) {
+  DevParams *dp = a.params + bf.noa_idx;
+  __shared__ int s_ready;
+  __shared__ DevParams s_dp;
+  if (threadIdx.x == 0) {
+    int r = __hip_atomic_load(&dp->ready, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+    for (unsigned polls = 0; r == 0 && polls < a.ready_polls; polls++) {
+      __builtin_amdgcn_s_sleep(2);
+      r = __hip_atomic_load(&dp->ready, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    s_ready = r;
+  }
+  __syncthreads();
+  DevParams d;
+  if (__builtin_amdgcn_readfirstlane(s_ready)) {
+    d.step = __hip_atomic_load(&dp->step, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    d.inv = __hip_atomic_load(&dp->inv, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    d.bound = __hip_atomic_load(&dp->bound, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    d.lo = __hip_atomic_load(&dp->lo, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    d.hi = __hip_atomic_load(&dp->hi, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    d.lossless_all =
+        __hip_atomic_load(&dp->lossless_all, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  } else {
+    T lo, hi;
+    block_minmax<T>(static_cast<const T *>(bf.in), 0, bf.n, lo, hi);
+    if (threadIdx.x == 0) s_dp = noa_params<T>(lo, hi, from_bits((typename FT<T>::U)bf.eb_down));
+    __syncthreads();
+    d = s_dp;
+  }
+  return d;
+}
+
+template <typename T, int Q>
+__device__ __forceinline__ FieldParams<T> field_params(const BatchQArgs &a, const BField &bf,
+                                                       DevParams *noa_out) {
+  using U = typename FT<T>::U;
+  if constexpr (Q == kNOA) {
+    const DevParams d = noa_field_params<T>(a, bf);
+    if (noa_out) *noa_out = d;
+    return params_from<T>(d);
+  }
+  FieldParams<T> p;
+  p.step = from_bits((U)bf.step);
+  p.inv = from_bits((U)bf.inv);
+  p.bound = from_bits((U)bf.bound);
+  p.low = from_bits((U)bf.low);
+  p.lossless_all = 0;
+  return p;
+}
+
 template <typename T, int Q, int SL, int RD>
 __device__ __forceinline__ void tile_item(const BatchQArgs &a, const BField &bf, uint64_t tile) {
-  using U = typename FT<T>::U;
   QField<T> f;
   f.in = static_cast<const T *>(bf.in);
   f.n = bf.n;
@@ -179,54 +249,31 @@ __device__ __forceinline__ void tile_item(const BatchQArgs &a, const BField &bf,
   f.ntiles = bf.ntiles;
 #pragma unroll
   for (int i = 0; i < 8; i++) f.hdr[i] = bf.hdr[i];
+  DevParams d;
+  f.p = field_params<T, Q>(a, bf, &d);
   if constexpr (Q == kNOA) {
-    // Wait for the field's parameters.  Every range item of the field left
-    // the queue before this tile and never waits, so the flag comes; the
-    // wait is bounded all the same: past the bound this workgroup derives
-    // the same parameters from the whole field itself (min / max do not
-    // depend on order).
-    DevParams *dp = a.params + bf.noa_idx;
-    __shared__ int s_ready;
-    __shared__ DevParams s_dp;
-    if (threadIdx.x == 0) {
-      int r = __hip_atomic_load(&dp->ready, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
-      for (unsigned polls = 0; r == 0 && polls < a.ready_polls; polls++) {
-        __builtin_amdgcn_s_sleep(2);
-        r = __hip_atomic_load(&dp->ready, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
-      }
-      s_ready = r;
-    }
-    __syncthreads();
-    DevParams d;
-    if (__builtin_amdgcn_readfirstlane(s_ready)) {
-      d.step = __hip_atomic_load(&dp->step, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      d.inv = __hip_atomic_load(&dp->inv, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      d.bound = __hip_atomic_load(&dp->bound, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      d.lo = __hip_atomic_load(&dp->lo, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      d.hi = __hip_atomic_load(&dp->hi, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      d.lossless_all =
-          __hip_atomic_load(&dp->lossless_all, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    } else {
-      T lo, hi;
-      block_minmax<T>(static_cast<const T *>(bf.in), 0, bf.n, lo, hi);
-      if (threadIdx.x == 0)
-        s_dp = noa_params<T>(lo, hi, from_bits((typename FT<T>::U)bf.eb_down));
-      __syncthreads();
-      d = s_dp;
-    }
-    f.p = params_from<T>(d);
     f.hdr[4] = d.step;
     f.hdr[5] = d.bound;
     f.hdr[6] = d.lo;
     f.hdr[7] = d.hi;
-  } else {
-    f.p.step = from_bits((U)bf.step);
-    f.p.inv = from_bits((U)bf.inv);
-    f.p.bound = from_bits((U)bf.bound);
-    f.p.low = from_bits((U)bf.low);
-    f.p.lossless_all = 0;
   }
   quant_tile<T, Q, SL, RD>(f, tile, a.spin_limit);
+}
+
+// Chunk variant, pass 1: the workgroup's 4 chunks of one field.
+template <typename T, int Q>
+__device__ __forceinline__ void chunk_item(const BatchQArgs &a, const BField &bf, uint64_t tile) {
+  using U = typename FT<T>::U;
+  StageField<T> f;
+  f.in = static_cast<const T *>(bf.in);
+  f.n = bf.n;
+  f.codes = reinterpret_cast<int32_t *>(bf.stream + 64);
+  f.counts = reinterpret_cast<uint32_t *>(a.ws + bf.counts_off);
+  f.stage = reinterpret_cast<U *>(a.ws + bf.stage_off);
+  f.group = reinterpret_cast<unsigned long long *>(a.ws + bf.group_off);
+  f.tiles_per_group = bf.tiles_per_group;
+  f.p = field_params<T, Q>(a, bf, nullptr);
+  quant_chunks<T, Q, 1, 1>(f, tile);
 }
 
 // One workgroup per work item, in queue order: the hardware dispatcher hands
@@ -235,7 +282,7 @@ __device__ __forceinline__ void tile_item(const BatchQArgs &a, const BField &bf,
 // wait inside an item (a NOA field's parameters, a predecessor tile's
 // outlier count) is bounded with a fallback that computes the awaited value
 // from the input, so no dispatch order can stall the grid.
-template <int SL32, int RD32, int SL64, int RD64>
+template <int SL32, int RD32, int SL64, int RD64, bool CHUNK>
 __global__ __launch_bounds__(kBlock) void k_batch_quantize(const BatchQArgs *ap) {
   const BatchQArgs a = uload(ap);
   const unsigned cur = blockIdx.x;
@@ -247,15 +294,58 @@ __global__ __launch_bounds__(kBlock) void k_batch_quantize(const BatchQArgs *ap)
     else range_item<double>(a, f, local);
     return;
   }
-  if (f.dtype == LCQ_F32) {
-    if (f.q == kABS) tile_item<float, kABS, SL32, RD32>(a, f, local);
-    else if (f.q == kREL) tile_item<float, kREL, SL32, RD32>(a, f, local);
-    else tile_item<float, kNOA, SL32, RD32>(a, f, local);
+  if constexpr (CHUNK) {
+    if (f.dtype == LCQ_F32) {
+      if (f.q == kABS) chunk_item<float, kABS>(a, f, local);
+      else if (f.q == kREL) chunk_item<float, kREL>(a, f, local);
+      else chunk_item<float, kNOA>(a, f, local);
+    } else {
+      if (f.q == kABS) chunk_item<double, kABS>(a, f, local);
+      else if (f.q == kREL) chunk_item<double, kREL>(a, f, local);
+      else chunk_item<double, kNOA>(a, f, local);
+    }
   } else {
-    if (f.q == kABS) tile_item<double, kABS, SL64, RD64>(a, f, local);
-    else if (f.q == kREL) tile_item<double, kREL, SL64, RD64>(a, f, local);
-    else tile_item<double, kNOA, SL64, RD64>(a, f, local);
+    if (f.dtype == LCQ_F32) {
+      if (f.q == kABS) tile_item<float, kABS, SL32, RD32>(a, f, local);
+      else if (f.q == kREL) tile_item<float, kREL, SL32, RD32>(a, f, local);
+      else tile_item<float, kNOA, SL32, RD32>(a, f, local);
+    } else {
+      if (f.q == kABS) tile_item<double, kABS, SL64, RD64>(a, f, local);
+      else if (f.q == kREL) tile_item<double, kREL, SL64, RD64>(a, f, local);
+      else tile_item<double, kNOA, SL64, RD64>(a, f, local);
+    }
   }
+}
+
+// Chunk variant, pass 2: one workgroup per (field, chunk group).  Every NOA
+// field's range items finished in the previous kernel, so its parameters
+// are published.
+template <typename T>
+__device__ __forceinline__ void finish_item(const BatchQArgs &a, const BField &bf, uint64_t g) {
+  using U = typename FT<T>::U;
+  FinishField<T> f;
+  f.in = static_cast<const T *>(bf.in);
+  f.n = bf.n;
+  f.stream = bf.stream;
+  f.stream_bytes = bf.stream_bytes;
+  f.counts = reinterpret_cast<const uint32_t *>(a.ws + bf.counts_off);
+  f.stage = reinterpret_cast<const U *>(a.ws + bf.stage_off);
+  f.group = reinterpret_cast<const unsigned long long *>(a.ws + bf.group_off);
+  f.chunks_per_group = bf.chunks_per_group;
+  f.ngroups = bf.ngroups;
+  f.noa = bf.q == kNOA ? a.params + bf.noa_idx : nullptr;
+#pragma unroll
+  for (int i = 0; i < 8; i++) f.hdr[i] = bf.hdr[i];
+  quant_finish<T>(f, g);
+}
+
+__global__ __launch_bounds__(kBlock) void k_batch_finish(const BatchQArgs *ap) {
+  const BatchQArgs a = uload(ap);
+  const uint64_t it = uload(a.items_f + blockIdx.x);
+  const BField f = uload(a.fields + (it >> 32));
+  const uint64_t g = it & 0xFFFFFFFFull;
+  if (f.dtype == LCQ_F32) finish_item<float>(a, f, g);
+  else finish_item<double>(a, f, g);
 }
 
 struct BatchDArgs {
@@ -288,7 +378,7 @@ __device__ void deq_item(const BatchDArgs &a, const BField &bf, uint32_t fi, uin
   f.out = static_cast<T *>(bf.out);
   f.status = a.status + fi;
   f.tag = 0;
-  dequant_tile<T, kDeqSlots, kDeqRounds>(f, tile);
+  dequant_chunks<T, 1, 1>(f, tile);
 }
 
 __global__ __launch_bounds__(kBlock) void k_batch_dequantize(BatchDArgs a) {
@@ -309,22 +399,47 @@ __global__ void k_batch_clear(uint64_t *p, uint64_t count) {
 uint64_t up256(uint64_t v) { return (v + 255) & ~255ull; }
 
 struct Counts {
-  uint64_t n_a = 0, n_b = 0, n_d = 0, states = 0, partial_bytes = 0;
+  uint64_t n_a = 0, n_b = 0, n_d = 0, n_f = 0, states = 0, partial_bytes = 0;
+  uint64_t group_words = 0, count_bytes = 0, stage_bytes = 0;
   uint32_t n_noa = 0;
 };
 
 uint64_t qtile_len(int dtype, int bv) {
+  if (kBatchVariants[bv].chunk) return kChunkTile;
   const Shape s = dtype == LCQ_F64 ? kBatchVariants[bv].f64 : kBatchVariants[bv].f32;
   return (uint64_t)kBlock * (dtype == LCQ_F64 ? 2 : 4) * s.slots * s.rounds;
 }
 
+// Quantize workgroups of a field: chunk variant n = 0 has none (its header
+// comes from pass 2); tile variants give n = 0 one header-only tile.
+uint64_t field_tiles(const lcq_field &x, int bv) {
+  const uint64_t tl = qtile_len(x.t, bv);
+  if (kBatchVariants[bv].chunk) return (x.n + tl - 1) / tl;
+  return x.n ? (x.n + tl - 1) / tl : 1;
+}
+
+// Chunk variant: pass-2 groups of a field (at most kMaxGroups, at least 1).
+void field_groups(uint64_t ntiles, uint64_t &tiles_per_group, uint64_t &ngroups) {
+  tiles_per_group = std::max<uint64_t>(1, (ntiles + kMaxGroups - 1) / kMaxGroups);
+  ngroups = std::max<uint64_t>(1, (ntiles + tiles_per_group - 1) / tiles_per_group);
+}
+
 Counts count(const lcq_field *f, uint32_t nf, int bv) {
   Counts c;
+  const bool chunk = kBatchVariants[bv].chunk;
   for (uint32_t i = 0; i < nf; i++) {
-    const uint64_t tl = qtile_len(f[i].t, bv);
-    const uint64_t nt = f[i].n ? (f[i].n + tl - 1) / tl : 1;  // n = 0: one header-only tile
+    const uint64_t nt = field_tiles(f[i], bv);
     c.n_b += nt;
-    c.states += nt;
+    if (chunk) {
+      uint64_t tpg, ng;
+      field_groups(nt, tpg, ng);
+      c.n_f += ng;
+      c.group_words += ng;
+      c.count_bytes += up256(4 * n_chunks(f[i].n));
+      c.stage_bytes += up256((uint64_t)kStageCap * (f[i].t == LCQ_F64 ? 8 : 4) * n_chunks(f[i].n));
+    } else {
+      c.states += nt;
+    }
     c.n_d += (f[i].n + kDeqTile - 1) / kDeqTile;
     if (f[i].q == LCQ_NOA) {
       const uint64_t ns = std::max<uint64_t>(1, (f[i].n + kSlice - 1) / kSlice);
@@ -344,12 +459,16 @@ Layout layout_for(const Counts &c, uint32_t nf) {
   L.done = o;          o += up256(4ull * std::max<uint32_t>(c.n_noa, 1));
   L.dstatus = o;       o += up256(8ull * std::max<uint32_t>(nf, 1));
   L.state = o;         o += up256(8 * std::max<uint64_t>(c.states, 1));
+  L.groups = o;        o += up256(8 * std::max<uint64_t>(c.group_words, 1));
   L.clear_begin = 0;
-  L.clear_words = o / 8;  // head, params (ready flags), done, status, state
+  L.clear_words = o / 8;  // head, params (ready flags), done, status, state, group sums
   L.args = o;          o += up256(sizeof(BatchQArgs));
   L.fields = o;        o += up256(sizeof(BField) * std::max<uint32_t>(nf, 1));
   L.items_q = o;       o += up256(8 * std::max<uint64_t>(c.n_a + c.n_b, 1));
   L.items_d = o;       o += up256(8 * std::max<uint64_t>(c.n_d, 1));
+  L.items_f = o;       o += up256(8 * std::max<uint64_t>(c.n_f, 1));
+  L.counts = o;        o += std::max<uint64_t>(c.count_bytes, 256);
+  L.stage = o;         o += std::max<uint64_t>(c.stage_bytes, 256);
   L.partials = o;      o += std::max<uint64_t>(c.partial_bytes, 256);
   L.total = o;
   return L;
@@ -366,9 +485,10 @@ int parse_variant(const char *tune) {
 lcq_status launch_batch_quantize(int bv, const BatchQArgs *a, unsigned grid, hipStream_t s) {
   const dim3 g(grid), b(kBlock);
   switch (bv) {
-    case 1: hipLaunchKernelGGL((k_batch_quantize<4, 2, 4, 4>), g, b, 0, s, a); break;
-    case 2: hipLaunchKernelGGL((k_batch_quantize<4, 1, 4, 2>), g, b, 0, s, a); break;
-    default: hipLaunchKernelGGL((k_batch_quantize<4, 4, 4, 8>), g, b, 0, s, a); break;
+    case 1: hipLaunchKernelGGL((k_batch_quantize<4, 4, 4, 8, false>), g, b, 0, s, a); break;
+    case 2: hipLaunchKernelGGL((k_batch_quantize<4, 2, 4, 4, false>), g, b, 0, s, a); break;
+    case 3: hipLaunchKernelGGL((k_batch_quantize<4, 1, 4, 2, false>), g, b, 0, s, a); break;
+    default: hipLaunchKernelGGL((k_batch_quantize<0, 0, 0, 0, true>), g, b, 0, s, a); break;
   }
   return hipGetLastError() == hipSuccess ? LCQ_OK : LCQ_ERR_HIP;
 }
@@ -418,15 +538,17 @@ lcq_status lcq_batch_plan_create(const lcq_field *f, uint32_t nf, const char *tu
   const Counts c = count(f, nf, bv);
   const Layout L = layout_for(c, nf);
   if (ws_bytes < L.total) return LCQ_ERR_CAPACITY;
-  if (c.n_a + c.n_b >= (1ull << 32)) return LCQ_ERR_ARG;
+  if (c.n_a + c.n_b >= (1ull << 32) || c.n_f >= (1ull << 32) || c.n_d >= (1ull << 32))
+    return LCQ_ERR_ARG;
 
   // descriptors and item tables
   std::vector<BField> bf(nf);
-  std::vector<uint64_t> items_a, items_b, items_d;
+  std::vector<uint64_t> items_a, items_b, items_d, items_f;
   items_a.reserve(c.n_a);
   items_b.reserve(c.n_b);
   items_d.reserve(c.n_d);
-  uint64_t state_off = 0, part_off = 0;
+  items_f.reserve(c.n_f);
+  uint64_t state_off = 0, part_off = 0, group_off = 0, count_off = 0, stage_off = 0;
   uint32_t noa_idx = 0;
   for (uint32_t i = 0; i < nf; i++) {
     const lcq_field &x = f[i];
@@ -454,10 +576,21 @@ lcq_status lcq_batch_plan_create(const lcq_field *f, uint32_t nf, const char *tu
     d.hdr[5] = hp.bound;
     d.hdr[6] = hp.aux0;
     d.hdr[7] = hp.aux1;
-    const uint64_t tl = qtile_len(x.t, bv);
-    d.ntiles = x.n ? (x.n + tl - 1) / tl : 1;  // n = 0: one tile that writes the header
-    d.state_off = state_off;
-    state_off += d.ntiles;
+    d.ntiles = field_tiles(x, bv);
+    if (kBatchVariants[bv].chunk) {
+      field_groups(d.ntiles, d.tiles_per_group, d.ngroups);
+      d.chunks_per_group = d.tiles_per_group * (kChunkTile / kChunk);
+      d.group_off = L.groups + 8 * group_off;
+      d.counts_off = L.counts + count_off;
+      d.stage_off = L.stage + stage_off;
+      group_off += d.ngroups;
+      count_off += up256(4 * n_chunks(x.n));
+      stage_off += up256((uint64_t)kStageCap * (x.t == LCQ_F64 ? 8 : 4) * n_chunks(x.n));
+      for (uint64_t g = 0; g < d.ngroups; g++) items_f.push_back(((uint64_t)i << 32) | g);
+    } else {
+      d.state_off = state_off;
+      state_off += d.ntiles;
+    }
     if (x.q == LCQ_NOA) {
       d.noa_idx = noa_idx++;
       d.nslices = (uint32_t)std::max<uint64_t>(1, (x.n + kSlice - 1) / kSlice);
@@ -485,6 +618,7 @@ lcq_status lcq_batch_plan_create(const lcq_field *f, uint32_t nf, const char *tu
   if (nf && hipMemcpyAsync(ws + L.fields, bf.data(), sizeof(BField) * nf, hipMemcpyHostToDevice, stream) != hipSuccess) return LCQ_ERR_HIP;
   if (!items_q.empty() && hipMemcpyAsync(ws + L.items_q, items_q.data(), 8 * items_q.size(), hipMemcpyHostToDevice, stream) != hipSuccess) return LCQ_ERR_HIP;
   if (!items_d.empty() && hipMemcpyAsync(ws + L.items_d, items_d.data(), 8 * items_d.size(), hipMemcpyHostToDevice, stream) != hipSuccess) return LCQ_ERR_HIP;
+  if (!items_f.empty() && hipMemcpyAsync(ws + L.items_f, items_f.data(), 8 * items_f.size(), hipMemcpyHostToDevice, stream) != hipSuccess) return LCQ_ERR_HIP;
   if (hipStreamSynchronize(stream) != hipSuccess) return LCQ_ERR_HIP;
 
   lcq_batch_plan *p = new (std::nothrow) lcq_batch_plan();
@@ -507,6 +641,8 @@ lcq_status lcq_batch_plan_create(const lcq_field *f, uint32_t nf, const char *tu
   qa.done = reinterpret_cast<unsigned *>(ws + L.done);
   qa.state = reinterpret_cast<uint64_t *>(ws + L.state);
   qa.partials = ws + L.partials;
+  qa.items_f = reinterpret_cast<const uint64_t *>(ws + L.items_f);
+  qa.ws = ws;
   qa.spin_limit = g_spin_limit.load();
   qa.ready_polls = g_spin_limit.load() ? (1u << 15) : 0u;
   BatchDArgs da{};
@@ -532,6 +668,10 @@ lcq_status lcq_batch_plan_create(const lcq_field *f, uint32_t nf, const char *tu
     hipLaunchKernelGGL(k_batch_clear, dim3(cgrid), dim3(kBlock), 0, cs,
                        reinterpret_cast<uint64_t *>(ws), L.clear_words);
     if (qa.n_items) st = launch_batch_quantize(bv, qa_dev, p->grid, cs);
+    if (st == LCQ_OK && kBatchVariants[bv].chunk && c.n_f) {
+      hipLaunchKernelGGL(k_batch_finish, dim3((unsigned)c.n_f), dim3(kBlock), 0, cs, qa_dev);
+      if (hipGetLastError() != hipSuccess) st = LCQ_ERR_HIP;
+    }
     if (hipStreamEndCapture(cs, &p->gq) != hipSuccess) st = LCQ_ERR_HIP;
   }
   if (st == LCQ_OK && hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) != hipSuccess) st = LCQ_ERR_HIP;

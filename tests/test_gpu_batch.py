@@ -32,12 +32,18 @@ def _fields(seed, nf, max_n):
     return out
 
 
-@pytest.mark.parametrize("variant", [0, 1, 2])
+@pytest.mark.parametrize("variant", [0, 1, 2, 3])
 def test_batch_matches_oracle_and_plain(variant):
     import torch
     import paper_2407_15037_amd as lcq
     from paper_2407_15037_amd.batch import BatchPlan
     fl = _fields(100 + variant, 60, 300000)
+    # fields where every value is stored losslessly (more outliers per chunk
+    # than are staged), one per quantizer and dtype
+    for j, (q, dt) in enumerate([("abs", np.float32), ("rel", np.float64), ("noa", np.float32)]):
+        x, _, _ = synth.inject_specials(synth.sines_1d(5000 + 777 * j, 90 + j, dtype=dt),
+                                        5000 + 777 * j, 91 + j, 1e-3)
+        fl.append(dict(x_np=x, q=q, eb=1e-3))
     dev_fields = [dict(x=torch.from_numpy(f["x_np"]).cuda(), q=f["q"], eb=f["eb"]) for f in fl]
     announce("batch plan", variant, len(fl))
     plan = BatchPlan(dev_fields, variant=variant)
@@ -88,10 +94,12 @@ def test_batch_dequant_reports_bad_field():
     plan.close()
 
 
-def test_batch_fallback_paths_same_bytes():
+@pytest.mark.parametrize("variant", [0, 3])
+def test_batch_fallback_paths_same_bytes(variant):
     """With the look-back and NOA-parameter waits forced to fall back at once
     (every wait recomputes what it waits for from the input), the batch still
-    produces the oracle's bytes."""
+    produces the oracle's bytes (chunk form: NOA parameter wait; tile form:
+    both waits)."""
     import torch
     import paper_2407_15037_amd as lcq
     from paper_2407_15037_amd.batch import BatchPlan
@@ -99,8 +107,8 @@ def test_batch_fallback_paths_same_bytes():
     dev_fields = [dict(x=torch.from_numpy(f["x_np"]).cuda(), q=f["q"], eb=f["eb"]) for f in fl]
     try:
         lcq.set_lookback_spin(0)
-        announce("batch fallback plan")
-        plan = BatchPlan(dev_fields, variant=2)
+        announce("batch fallback plan", variant)
+        plan = BatchPlan(dev_fields, variant=variant)
     finally:
         lcq.set_lookback_spin(4096)
     plan.quantize()
