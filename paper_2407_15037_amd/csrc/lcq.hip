@@ -446,7 +446,7 @@ lcq_status run_quantize(double eb, const void *d_in, uint64_t n, void *d_stream,
     sq.counts = reinterpret_cast<uint32_t *>(ws + ws_counts_off());
     sq.stage = ws + ws_stage_off(n);
     sq.group = reinterpret_cast<unsigned long long *>(ws + kWsState);
-    sq.tiles_per_group = std::max<uint64_t>(1, (a.ntiles + kMaxGroups - 1) / kMaxGroups);
+    sq.tiles_per_group = tiles_per_group(a.ntiles, tile / kChunk);
     sq.chunks_per_group = sq.tiles_per_group * (tile / kChunk);
     sq.ngroups = (a.ntiles + sq.tiles_per_group - 1) / sq.tiles_per_group;
     sq.noa = a.noa;

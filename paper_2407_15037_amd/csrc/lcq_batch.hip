@@ -420,7 +420,7 @@ uint64_t field_tiles(const lcq_field &x, int bv) {
 
 // Chunk variant: pass-2 groups of a field (at most kMaxGroups, at least 1).
 void field_groups(uint64_t ntiles, uint64_t &tiles_per_group, uint64_t &ngroups) {
-  tiles_per_group = std::max<uint64_t>(1, (ntiles + kMaxGroups - 1) / kMaxGroups);
+  tiles_per_group = lcq::tiles_per_group(ntiles, kChunkTile / kChunk);
   ngroups = std::max<uint64_t>(1, (ntiles + tiles_per_group - 1) / tiles_per_group);
 }
 

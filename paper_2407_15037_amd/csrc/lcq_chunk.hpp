@@ -41,6 +41,16 @@ typedef int nt_i2 __attribute__((ext_vector_type(2)));
 
 constexpr int kStageCap = 32;       // outliers staged per chunk in pass 1
 constexpr uint64_t kMaxGroups = 1024;  // pass-2 workgroups (groups) at most
+constexpr uint64_t kGroupChunks = 256;  // chunks per group at least (one scan batch)
+
+// Pass-1 workgroups per pass-2 group for a field of `ntiles` pass-1
+// workgroups of `chunks_per_tile` chunks each: at least one full scan batch
+// per group, at most kMaxGroups groups.
+__host__ __device__ inline uint64_t tiles_per_group(uint64_t ntiles, uint64_t chunks_per_tile) {
+  const uint64_t by_size = (kGroupChunks + chunks_per_tile - 1) / chunks_per_tile;
+  const uint64_t by_count = (ntiles + kMaxGroups - 1) / kMaxGroups;
+  return by_size > by_count ? by_size : by_count;
+}
 
 // A lane holds W = 16 / sizeof(T) consecutive values of each sub-block (one
 // 128-bit access), so a chunk is NSUB = 1024 / (64 W) sub-blocks and every
