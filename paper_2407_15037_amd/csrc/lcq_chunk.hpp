@@ -330,31 +330,16 @@ __device__ void quant_finish(const FinishField<T> &f, uint64_t g) {
     s_c[tid] = cnt;
     __syncthreads();
     const int m = (int)min<uint64_t>((uint64_t)kBlock, c1 - cb);
-    // staged outliers: thread t moves outliers t, t + 256, ... of the batch,
-    // kCopyUnroll of them at a time (independent loads in flight); an
-    // outlier's chunk is the last one starting at or before its rank
-    constexpr int kCopyUnroll = 8;
-    for (uint64_t o0 = tid; o0 < total; o0 += (uint64_t)kCopyUnroll * kBlock) {
-      U v[kCopyUnroll];
-      bool mv[kCopyUnroll];
+    // staged outliers: thread t moves its own chunk's staged row (up to
+    // kStageCap words, all loads issued before the first store)
+    if (c < c1 && cnt != 0 && cnt <= (unsigned)kStageCap) {
+      const U *row = f.stage + c * kStageCap;
+      U v[kStageCap];
 #pragma unroll
-      for (int u = 0; u < kCopyUnroll; u++) {
-        const uint64_t o = o0 + (uint64_t)u * kBlock;
-        int lo = 0, hi = m - 1;
-        while (lo < hi) {
-          const int mid = (lo + hi + 1) >> 1;
-          if (s_P[mid] <= o) lo = mid;
-          else hi = mid - 1;
-        }
-        mv[u] = o < total && s_c[lo] <= (unsigned)kStageCap;
-        // index 0 for lanes with nothing to move keeps even a speculated
-        // load inside the staging area
-        const uint64_t si = mv[u] ? (cb + (uint64_t)lo) * kStageCap + (o - s_P[lo]) : 0;
-        v[u] = mv[u] ? f.stage[si] : (U)0;
-      }
+      for (int r = 0; r < kStageCap; r++) v[r] = (unsigned)r < cnt ? row[r] : (U)0;
 #pragma unroll
-      for (int u = 0; u < kCopyUnroll; u++)
-        if (mv[u]) outl[run + o0 + (uint64_t)u * kBlock] = v[u];
+      for (int r = 0; r < kStageCap; r++)
+        if ((unsigned)r < cnt) outl[P + r] = v[r];
     }
     // chunks with more outliers than were staged: rescanned by a wavefront
     for (int i = wave; i < m; i += kWaves) {
