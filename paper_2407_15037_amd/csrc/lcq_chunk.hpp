@@ -295,6 +295,11 @@ __device__ void quant_finish(const FinishField<T> &f, uint64_t g) {
   uint64_t *chunk_tab = reinterpret_cast<uint64_t *>(f.stream + chunk_table_offset(n));
   U *outl = reinterpret_cast<U *>(f.stream + outlier_offset(n));
 
+  const uint64_t c0 = g * f.chunks_per_group;
+  const uint64_t c1 = min(c0 + f.chunks_per_group, nch);
+  // the first batch's count is loaded before the earlier groups are summed
+  unsigned cnt_next = c0 + tid < c1 ? f.counts[c0 + tid] : 0u;
+
   // outliers of all earlier groups
   unsigned long long b = 0;
   for (uint64_t i = tid; i < g; i += kBlock) b += f.group[i];
@@ -305,11 +310,10 @@ __device__ void quant_finish(const FinishField<T> &f, uint64_t g) {
 #pragma unroll
   for (int w = 0; w < kWaves; w++) run += s_red[w];
 
-  const uint64_t c0 = g * f.chunks_per_group;
-  const uint64_t c1 = min(c0 + f.chunks_per_group, nch);
   for (uint64_t cb = c0; cb < c1; cb += kBlock) {
     const uint64_t c = cb + tid;
-    const unsigned cnt = c < c1 ? f.counts[c] : 0u;
+    const unsigned cnt = cnt_next;
+    cnt_next = cb + kBlock + tid < c1 ? f.counts[cb + kBlock + tid] : 0u;
     unsigned incl = cnt;
 #pragma unroll
     for (int o = 1; o < 64; o <<= 1) {
@@ -327,8 +331,7 @@ __device__ void quant_finish(const FinishField<T> &f, uint64_t g) {
     const uint64_t P = run + before + (incl - cnt);
     if (c < c1) chunk_tab[c] = P;
     s_P[tid] = before + (incl - cnt);  // batch-relative first outlier of each chunk
-    s_c[tid] = cnt;
-    __syncthreads();
+    s_c[tid] = cnt;                    // (read after the barrier below)
     const int m = (int)min<uint64_t>((uint64_t)kBlock, c1 - cb);
     // staged outliers: thread t moves its own chunk's staged row (up to
     // kStageCap words, all loads issued before the first store)
@@ -341,9 +344,12 @@ __device__ void quant_finish(const FinishField<T> &f, uint64_t g) {
       for (int r = 0; r < kStageCap; r++)
         if ((unsigned)r < cnt) outl[P + r] = v[r];
     }
-    // chunks with more outliers than were staged: rescanned by a wavefront
-    for (int i = wave; i < m; i += kWaves) {
-      if (s_c[i] > (unsigned)kStageCap) rescan_chunk<T>(f, cb + (uint64_t)i, run + s_P[i], lane);
+    // chunks with more outliers than were staged (rare): rescanned by a
+    // wavefront each; the batch skips this when it has none
+    if (__syncthreads_or(cnt > (unsigned)kStageCap)) {
+      for (int i = wave; i < m; i += kWaves) {
+        if (s_c[i] > (unsigned)kStageCap) rescan_chunk<T>(f, cb + (uint64_t)i, run + s_P[i], lane);
+      }
     }
     run += total;
     __syncthreads();  // s_wt, s_P, s_c are rewritten by the next batch
