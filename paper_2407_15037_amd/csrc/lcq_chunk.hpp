@@ -41,11 +41,12 @@ typedef int nt_i2 __attribute__((ext_vector_type(2)));
 
 constexpr int kStageCap = 32;       // outliers staged per chunk in pass 1
 constexpr uint64_t kMaxGroups = 1024;  // pass-2 workgroups (groups) at most
-constexpr uint64_t kGroupChunks = 256;  // chunks per group at least (one scan batch)
+constexpr uint64_t kGroupChunks = 64;  // chunks per group at least
 
 // Pass-1 workgroups per pass-2 group for a field of `ntiles` pass-1
-// workgroups of `chunks_per_tile` chunks each: at least one full scan batch
-// per group, at most kMaxGroups groups.
+// workgroups of `chunks_per_tile` chunks each: at least kGroupChunks chunks
+// per group (fewer, fuller pass-2 workgroups for many small fields), at
+// most kMaxGroups groups.
 __host__ __device__ inline uint64_t tiles_per_group(uint64_t ntiles, uint64_t chunks_per_tile) {
   const uint64_t by_size = (kGroupChunks + chunks_per_tile - 1) / chunks_per_tile;
   const uint64_t by_count = (ntiles + kMaxGroups - 1) / kMaxGroups;

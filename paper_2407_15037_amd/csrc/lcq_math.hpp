@@ -110,8 +110,10 @@ template <typename T, int Q> LCQ_HD int32_t encode(T x, const FieldParams<T> &p)
     const T q = rint_t(log2approx(a) * p.inv);
     // section 3.3: both range tests, on the float, before any conversion
     ok = ok && (q > (T)-kMaxBin) && (q < (T)kMaxBin);
-    const int32_t b = (int32_t)(ok ? q : (T)0);
-    const T rec = pow2approx((T)b * p.step);
+    // qb is integral and inside (-2^30, 2^30), so (T)(int)qb == qb exactly
+    const T qb = ok ? q : (T)0;
+    const int32_t b = (int32_t)qb;
+    const T rec = pow2approx(qb * p.step);
     // section 3.1 double-check against both sides of the section 2.1.2 range
     // |rec - a| equals (a - rec) when rec < a: round-to-nearest is
     // symmetric under negation, so one subtraction serves both sides
@@ -124,8 +126,9 @@ template <typename T, int Q> LCQ_HD int32_t encode(T x, const FieldParams<T> &p)
   } else {
     const T q = rint_t(x * p.inv);
     ok = ok && (q > (T)-kMaxBin) && (q < (T)kMaxBin);
-    const int32_t b = (int32_t)(ok ? q : (T)0);
-    const T rec = (T)b * p.step;
+    const T qb = ok ? q : (T)0;  // integral, in range: (T)(int)qb == qb
+    const int32_t b = (int32_t)qb;
+    const T rec = qb * p.step;
     ok = ok && (abs_t(x - rec) <= p.bound);
     return ok ? b : kSent;
   }
