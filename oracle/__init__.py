@@ -15,7 +15,9 @@ SO = os.path.join(HERE, "liblcq_oracle.so")
 F32, F64 = 0, 1
 ABS, REL, NOA = 0, 1, 2
 OK, ERR_ARG, ERR_CAPACITY, ERR_STREAM, ERR_FPENV = 0, 1, 2, 3, 5
-QNAMES = {"abs": ABS, "rel": REL, "noa": NOA}
+ABS_UNCHECKED, REL_LIBM = 3, 4  # the two ablations of section 6
+QNAMES = {"abs": ABS, "rel": REL, "noa": NOA, "abs_unchecked": ABS_UNCHECKED,
+          "rel_libm": REL_LIBM}
 
 
 class Params(ctypes.Structure):

@@ -22,6 +22,10 @@
  *      their place (the separate-list layout the paper contrasts with its
  *      in-line one, sec. 3.1)
  *
+ * The two ablations of sec. 6 are extra quantizer codes: ABS_UNCHECKED
+ * skips step 6 (the double-check), REL_LIBM uses the C library's log2 and
+ * exp2 for step 3 / step 5 and for the log-space bin width.
+ *
  * Compiled with -ffp-contract=off and no fast-math (sec. 3.2: no FMA, only
  * IEEE-754 operations), SSE arithmetic, round-to-nearest-even.
  *
@@ -203,20 +207,21 @@ static void noa_range_f64(const double *x, uint64_t n, double *lo, double *hi) {
 static int derive_f32(int q, double eb, const float *x, uint64_t n, params_t *p) {
   memset(p, 0, sizeof *p);
   p->q = q;
-  if (q == ORC_ABS) {
+  if (q == ORC_ABS || q == ORC_ABS_UNCHECKED) {
     /* sec. 2.2: bins of width 2e, value -> nearest bin centre */
     float e = round_down_f32(eb);
     p->boundf = e;
     p->stepf = e + e;
     p->invf = 1.0f / p->stepf;
-  } else if (q == ORC_REL) {
+  } else if (q == ORC_REL || q == ORC_REL_LIBM) {
     /* Upper side |x'| <= |x|(1+eb) is checked against eh = RD(eb), the
      * lower side |x'| >= |x|/(1+eb) against el = RD(eb/(1+eb)) (sec. 2.1.2,
      * the second, stricter form).  Bins of width 2*lambda in approximate-
-     * log2 space with lambda = log2approx(1 + eh). */
+     * log2 space with lambda = log2approx(1 + eh) (the library-log2
+     * ablation: lambda = log2(1 + eh)). */
     float eh = round_down_f32(eb);
     float el = round_down_f32(rel_low_double(eb));
-    float lam = log2approx_f32(1.0f + eh);
+    float lam = q == ORC_REL_LIBM ? log2f(1.0f + eh) : log2approx_f32(1.0f + eh);
     p->boundf = eh;
     p->aux0f = el;
     p->lambdaf = lam;
@@ -252,15 +257,15 @@ static int derive_f32(int q, double eb, const float *x, uint64_t n, params_t *p)
 static int derive_f64(int q, double eb, const double *x, uint64_t n, params_t *p) {
   memset(p, 0, sizeof *p);
   p->q = q;
-  if (q == ORC_ABS) {
+  if (q == ORC_ABS || q == ORC_ABS_UNCHECKED) {
     double e = eb;
     p->bound = e;
     p->step = e + e;
     p->inv = 1.0 / p->step;
-  } else if (q == ORC_REL) {
+  } else if (q == ORC_REL || q == ORC_REL_LIBM) {
     double eh = eb;
     double el = rel_low_double(eb);
-    double lam = log2approx_f64(1.0 + eh);
+    double lam = q == ORC_REL_LIBM ? log2(1.0 + eh) : log2approx_f64(1.0 + eh);
     p->bound = eh;
     p->aux0 = el;
     p->lambda = lam;
@@ -291,11 +296,13 @@ static int derive_f64(int q, double eb, const double *x, uint64_t n, params_t *p
   return ORC_OK;
 }
 
+static int is_rel(int q) { return q == ORC_REL || q == ORC_REL_LIBM; }
+
 static int check_args(int q, int dtype, double eb) {
-  if (q != ORC_ABS && q != ORC_REL && q != ORC_NOA) return ORC_ERR_ARG;
+  if (q < ORC_ABS || q > ORC_REL_LIBM) return ORC_ERR_ARG;
   if (dtype != ORC_F32 && dtype != ORC_F64) return ORC_ERR_ARG;
   if (!(eb > 0.0) || !isfinite(eb)) return ORC_ERR_ARG;
-  if (q == ORC_REL && !(eb < 1.0)) return ORC_ERR_ARG;
+  if (is_rel(q) && !(eb < 1.0)) return ORC_ERR_ARG;
   return ORC_OK;
 }
 
@@ -342,18 +349,19 @@ static int encode_f32(const params_t *p, float x, int32_t *code) {
   /* special values: INF/NaN, denormals; REL also zeros (sec. 2.2, 3.1) */
   if (E == 0xFFu) return 1;
   if (E == 0 && F != 0) return 1;
-  if (p->q == ORC_REL && E == 0) return 1;
+  if (is_rel(p->q) && E == 0) return 1;
   if (p->q == ORC_NOA && p->degenerate) return 1;
 
-  if (p->q == ORC_REL) {
+  if (is_rel(p->q)) {
+    const int libm = p->q == ORC_REL_LIBM;
     float a = from32(u & 0x7FFFFFFFu);
-    float lg = log2approx_f32(a);
+    float lg = libm ? log2f(a) : log2approx_f32(a);
     float qf = rintf(lg * p->invf);
     /* sec. 3.3: two one-sided range tests, here on the float so that no
      * out-of-range float-to-int conversion ever happens */
     if (!(qf > -(float)MAXBIN && qf < (float)MAXBIN)) return 1;
     int32_t b = (int32_t)qf;
-    float rec = pow2approx_f32((float)b * p->stepf);
+    float rec = libm ? exp2f((float)b * p->stepf) : pow2approx_f32((float)b * p->stepf);
     /* sec. 3.1 double-check, against the sec. 2.1.2 range */
     int ok;
     if (rec >= a) ok = (rec - a) < (p->boundf * a);
@@ -367,7 +375,7 @@ static int encode_f32(const params_t *p, float x, int32_t *code) {
   if (!(qf > -(float)MAXBIN && qf < (float)MAXBIN)) return 1;
   int32_t b = (int32_t)qf;
   float rec = (float)b * p->stepf;
-  if (!(fabsf(x - rec) <= p->boundf)) return 1;
+  if (p->q != ORC_ABS_UNCHECKED && !(fabsf(x - rec) <= p->boundf)) return 1;
   *code = b;
   return 0;
 }
@@ -379,16 +387,17 @@ static int encode_f64(const params_t *p, double x, int32_t *code) {
 
   if (E == 0x7FFu) return 1;
   if (E == 0 && F != 0) return 1;
-  if (p->q == ORC_REL && E == 0) return 1;
+  if (is_rel(p->q) && E == 0) return 1;
   if (p->q == ORC_NOA && p->degenerate) return 1;
 
-  if (p->q == ORC_REL) {
+  if (is_rel(p->q)) {
+    const int libm = p->q == ORC_REL_LIBM;
     double a = from64(u & 0x7FFFFFFFFFFFFFFFull);
-    double lg = log2approx_f64(a);
+    double lg = libm ? log2(a) : log2approx_f64(a);
     double qd = rint(lg * p->inv);
     if (!(qd > -MAXBIN && qd < MAXBIN)) return 1;
     int32_t b = (int32_t)qd;
-    double rec = pow2approx_f64((double)b * p->step);
+    double rec = libm ? exp2((double)b * p->step) : pow2approx_f64((double)b * p->step);
     int ok;
     if (rec >= a) ok = (rec - a) < (p->bound * a);
     else ok = (a - rec) < (p->aux0 * a);
@@ -401,27 +410,27 @@ static int encode_f64(const params_t *p, double x, int32_t *code) {
   if (!(qd > -MAXBIN && qd < MAXBIN)) return 1;
   int32_t b = (int32_t)qd;
   double rec = (double)b * p->step;
-  if (!(fabs(x - rec) <= p->bound)) return 1;
+  if (p->q != ORC_ABS_UNCHECKED && !(fabs(x - rec) <= p->bound)) return 1;
   *code = b;
   return 0;
 }
 
 /* Decoder side of one non-sentinel code. */
 static float decode_f32(int q, float step, int32_t c) {
-  if (q == ORC_REL) {
+  if (is_rel(q)) {
     int32_t sgn = c & 1;
     int32_t b = (c - sgn) / 2; /* exact: c - sgn is even */
-    float a = pow2approx_f32((float)b * step);
+    float a = q == ORC_REL_LIBM ? exp2f((float)b * step) : pow2approx_f32((float)b * step);
     return from32(bits32(a) | ((uint32_t)sgn << 31));
   }
   return (float)c * step;
 }
 
 static double decode_f64(int q, double step, int32_t c) {
-  if (q == ORC_REL) {
+  if (is_rel(q)) {
     int32_t sgn = c & 1;
     int32_t b = (c - sgn) / 2;
-    double a = pow2approx_f64((double)b * step);
+    double a = q == ORC_REL_LIBM ? exp2((double)b * step) : pow2approx_f64((double)b * step);
     return from64(bits64(a) | ((uint64_t)sgn << 63));
   }
   return (double)c * step;
@@ -502,7 +511,7 @@ int orc_dequantize(int dtype, const void *stream, uint64_t bytes, void *out_v,
   const uint8_t *S = (const uint8_t *)stream;
   const uint64_t s = dtype == ORC_F64 ? 8 : 4;
 
-  if (get_u32(S) != MAGIC || S[4] != 1 || S[5] != dtype || S[6] > 2 ||
+  if (get_u32(S) != MAGIC || S[4] != 1 || S[5] != dtype || S[6] > ORC_REL_LIBM ||
       S[7] != LOG2_CHUNK)
     return ORC_ERR_STREAM;
   if (get_u64(S + 8) != n) return ORC_ERR_STREAM;
@@ -624,7 +633,8 @@ int orc_dequantize_inline(int dtype, const void *stream, uint64_t bytes, void *o
   if (bytes < 64) return ORC_ERR_STREAM;
   const uint8_t *S = (const uint8_t *)stream;
   const uint64_t s = dtype == ORC_F64 ? 8 : 4;
-  if (get_u32(S) != MAGIC_INLINE || S[4] != 1 || S[5] != dtype || S[6] > 2 || S[7] != 0)
+  if (get_u32(S) != MAGIC_INLINE || S[4] != 1 || S[5] != dtype || S[6] > ORC_REL_LIBM ||
+      S[7] != 0)
     return ORC_ERR_STREAM;
   if (get_u64(S + 8) != n || bytes < orc_inline_stream_bytes(dtype, n)) return ORC_ERR_STREAM;
   const int q = S[6];

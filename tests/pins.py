@@ -446,8 +446,78 @@ def pin_inline_format(L):
         assert np.array_equal(bits(dec), bits(O.dequantize(st, dt, n, L=L)))
 
 
+# ------------------------------------------------- section 6 ablations ---
+def pin_ablation_abs_unchecked(L):
+    """ABS without the double-check: specials stay lossless, every finite
+    normal whose bin is in range gets the nearest-bin code rint(x * inv)
+    (replayed with numpy's IEEE operations of the field type), codes agree
+    with the protected stream wherever that one has a code, and on bin-border
+    inputs some codes decode outside the bound -- exactly at values the
+    protected stream stores raw (the check is what the guarantee rests on)."""
+    for dt in (np.float32, np.float64):
+        eb = 1e-3
+        x = np.concatenate([_config0_like(dt, 3000, 41, eb),
+                            synth.adversarial_abs(6000, eb, 42, dt)]).astype(dt)
+        st_u = O.quantize("abs_unchecked", x, eb, L=L)
+        st_p = O.quantize("abs", x, eb, L=L)
+        Pu, Pp = parse(st_u, dt), parse(st_p, dt)
+        assert Pu["hdr"]["q"] == 3 and not check_structure(Pu, x, dt)
+        assert Pu["hdr"]["step"] == Pp["hdr"]["step"] and Pu["hdr"]["bound"] == Pp["hdr"]["bound"]
+        inv = O.params("abs", dt, eb, L=L)["inv"]
+        sp = is_special(x)
+        with np.errstate(all="ignore"):
+            qf = np.rint(x * inv)
+        inr = ~sp & (qf > -(2.0 ** 30)) & (qf < 2.0 ** 30)
+        cu, cp = Pu["codes"], Pp["codes"]
+        assert np.all(cu[~inr] == SENT), dt
+        assert np.array_equal(cu[inr].astype(np.int64), qf[inr].astype(np.int64)), dt
+        assert np.array_equal(cu[cp != SENT], cp[cp != SENT]), dt
+        xd = O.dequantize(st_u, dt, x.size, L=L)
+        bad, bad_sp = abs_violations(x, xd, Fraction(eb))
+        assert bad.size > 0 and bad_sp.size == 0, (dt, bad.size)
+        assert np.all(cp[bad] == SENT), dt
+
+
+def pin_ablation_rel_libm(L):
+    """REL with the C library's log2 / exp2: same eh / el, lambda =
+    log2(1 (+) eh) (within an ulp of the exact value, wider than the
+    approximation's (1 + eh) - 1 since 1/ln 2 > 1), the double-check still
+    bounds every decoded value exactly, and exact powers of two -- whose
+    log2 is an integer in any library -- get the bin rint(k * inv) unless
+    they are stored raw."""
+    for dt in (np.float32, np.float64):
+        for eb in (1e-2, 1e-3):
+            pm = O.params("rel", dt, eb, L=L)
+            pl = O.params("rel_libm", dt, eb, L=L)
+            assert pl["bound"] == pm["bound"] and pl["aux0"] == pm["aux0"], (dt, eb)
+            lam = pl["lambda"]
+            exact = math.log2(float(dt(1) + pm["bound"]))  # log2 of 1 (+) eh, the type's sum
+            assert abs(Fraction(float(lam)) - Fraction(exact)) <= Fraction(float(np.spacing(lam))), (dt, eb)
+            assert lam > pm["lambda"], (dt, eb)
+            assert Fraction(float(pl["step"])) == 2 * Fraction(float(lam))
+            x = synth.rel_variant(np.nan_to_num(_config0_like(dt, 3000, 51, eb).astype(np.float64)),
+                                  52, dtype=dt)
+            x, _, _ = synth.inject_specials(x, 60, 53, eb)
+            x = np.concatenate([x, synth.adversarial_rel(4000, eb, 54, dt)]).astype(dt)
+            st = O.quantize("rel_libm", x, eb, L=L)
+            P = parse(st, dt)
+            assert P["hdr"]["q"] == 4 and not check_structure(P, x, dt), (dt, eb)
+            xd = O.dequantize(st, dt, x.size, L=L)
+            bad, bad_sp = rel_violations(x, xd, eb)
+            assert bad.size == 0 and bad_sp.size == 0, (dt, eb)
+            k = np.arange(-100, 101)
+            sgn = (k % 2 == 0)
+            a = (np.ldexp(1.0, k) * np.where(sgn, -1.0, 1.0)).astype(dt)
+            codes = parse(O.quantize("rel_libm", a, eb, L=L), dt)["codes"]
+            qf = np.rint(k.astype(dt) * pl["inv"])
+            want = (qf.astype(np.int64) * 2 + sgn.astype(np.int64)).astype(np.int32)
+            coded = codes != SENT
+            assert coded.mean() > 0.9 and np.array_equal(codes[coded], want[coded]), (dt, eb)
+
+
 PINS = [pin_mitchell_golden, pin_mitchell_powers_of_two, pin_mitchell_log2_error,
         pin_mitchell_log2_monotone, pin_mitchell_pow2_error, pin_params_abs,
         pin_params_rel, pin_params_noa, pin_arg_errors, pin_structure, pin_bounds,
         pin_specials, pin_abs_nearest_bin, pin_rel_nearest_bin, pin_bin_range,
-        pin_roundtrip_sizes, pin_stream_errors, pin_noa_degenerate, pin_inline_format]
+        pin_roundtrip_sizes, pin_stream_errors, pin_noa_degenerate, pin_inline_format,
+        pin_ablation_abs_unchecked, pin_ablation_rel_libm]

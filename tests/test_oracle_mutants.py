@@ -22,18 +22,18 @@ MUTANTS = {
     # section 3.2 pow2: fraction rebuilt from the wrong integer
     "pow2_frac": ("float g = t - (float)(k - 1);", "float g = t - (float)k;"),
     # double-check against the bin width instead of the bound (sec. 3.1)
-    "abs_verify_loose": ("if (!(fabsf(x - rec) <= p->boundf)) return 1;",
-                         "if (!(fabsf(x - rec) <= p->stepf)) return 1;"),
+    "abs_verify_loose": ("if (p->q != ORC_ABS_UNCHECKED && !(fabsf(x - rec) <= p->boundf)) return 1;",
+                         "if (p->q != ORC_ABS_UNCHECKED && !(fabsf(x - rec) <= p->stepf)) return 1;"),
     # double-check dropped entirely for float64
-    "abs_verify_dropped_f64": ("if (!(fabs(x - rec) <= p->bound)) return 1;", ""),
+    "abs_verify_dropped_f64": ("if (p->q != ORC_ABS_UNCHECKED && !(fabs(x - rec) <= p->bound)) return 1;", ""),
     # nearest bin replaced by truncation
     "bin_trunc": ("float qf = rintf(x * p->invf);", "float qf = truncf(x * p->invf);"),
     # bin range test admits +2^30 (sec. 3.3)
     "range_inclusive": ("if (!(qf > -(float)MAXBIN && qf < (float)MAXBIN)) return 1;\n  int32_t b = (int32_t)qf;\n  float rec = (float)b * p->stepf;",
                         "if (!(qf > -(float)MAXBIN && qf <= (float)MAXBIN)) return 1;\n  int32_t b = (int32_t)qf;\n  float rec = (float)b * p->stepf;"),
     # denormals quantized instead of stored losslessly
-    "denormal_binned": ("  if (E == 0 && F != 0) return 1;\n  if (p->q == ORC_REL && E == 0) return 1;\n  if (p->q == ORC_NOA && p->degenerate) return 1;\n\n  if (p->q == ORC_REL) {\n    float a",
-                        "  if (p->q == ORC_REL && E == 0) return 1;\n  if (p->q == ORC_NOA && p->degenerate) return 1;\n\n  if (p->q == ORC_REL) {\n    float a"),
+    "denormal_binned": ("  if (E == 0 && F != 0) return 1;\n  if (is_rel(p->q) && E == 0) return 1;\n  if (p->q == ORC_NOA && p->degenerate) return 1;\n\n  if (is_rel(p->q)) {\n    const int libm = p->q == ORC_REL_LIBM;\n    float a",
+                        "  if (is_rel(p->q) && E == 0) return 1;\n  if (p->q == ORC_NOA && p->degenerate) return 1;\n\n  if (is_rel(p->q)) {\n    const int libm = p->q == ORC_REL_LIBM;\n    float a"),
     # REL lower side checked against eh instead of eb/(1+eb)
     "rel_low_side": ("else ok = (a - rec) < (p->aux0f * a);", "else ok = (a - rec) < (p->boundf * a);"),
     # REL sign bit lost
@@ -54,6 +54,15 @@ MUTANTS = {
     "rel_el": ("float el = round_down_f32(rel_low_double(eb));", "float el = round_down_f32(eb);"),
     # ABS step taken as e instead of 2e
     "abs_step": ("    p->stepf = e + e;", "    p->stepf = e;"),
+    # ablation: the unchecked ABS still runs the double-check
+    "unchecked_checks": ("if (p->q != ORC_ABS_UNCHECKED && !(fabsf(x - rec) <= p->boundf)) return 1;",
+                         "if (!(fabsf(x - rec) <= p->boundf)) return 1;"),
+    # ablation: library-log2 REL keeps the approximation's bin width
+    "libm_lambda": ("float lam = q == ORC_REL_LIBM ? log2f(1.0f + eh) : log2approx_f32(1.0f + eh);",
+                    "float lam = log2approx_f32(1.0f + eh);"),
+    # ablation: library-log2 REL decoded with the approximate 2^y
+    "libm_decode": ("float a = q == ORC_REL_LIBM ? exp2f((float)b * step) : pow2approx_f32((float)b * step);",
+                    "float a = pow2approx_f32((float)b * step);"),
 }
 
 
