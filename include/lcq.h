@@ -111,6 +111,35 @@ const char *lcq_status_string(lcq_status s);
  * kernel (the per-value pass), on the call's stream.  Pass nulls to clear. */
 void lcq_profile_events(hipEvent_t before, hipEvent_t after);
 
+/* ------------------------------------------------- section 6 ablations --
+ * The two variants the paper measures its guarantee against (section 6,
+ * Table 7 and Tables 5-6).  They do NOT guarantee the bound / CPU-GPU
+ * parity; they exist to measure what the guarantee costs.
+ *   LCQ_ABL_ABS_UNCHECKED  ABS without the double-check of section 3.1:
+ *                          every finite normal value whose bin is in range
+ *                          gets its bin, even where the reconstruction
+ *                          misses the bound.
+ *   LCQ_ABL_REL_LIBM       REL with the math library's log2 / exp2 (on the
+ *                          device: the GPU's; for the bin width on the host:
+ *                          the host's) in place of the approximations of
+ *                          section 3.2.  The double-check still bounds every
+ *                          value, but codes may differ between CPU and GPU.
+ * Streams use the LCQ1 layout with the kind as the header's quantizer byte;
+ * lcq_dequantize rejects them, lcq_dequantize_ablation decodes exactly the
+ * given kind.  Arguments, buffers and errors as for lcq_quantize /
+ * lcq_dequantize; the workspace is lcq_workspace_bytes(LCQ_ABS or LCQ_REL,
+ * t, n).  Both always use the default (chunk-per-wavefront) kernels. */
+typedef enum { LCQ_ABL_ABS_UNCHECKED = 3, LCQ_ABL_REL_LIBM = 4 } lcq_ablation;
+
+lcq_status lcq_quantize_ablation(lcq_ablation kind, lcq_dtype t, double eb,
+                                 const void *d_in, uint64_t n,
+                                 void *d_stream, uint64_t stream_cap, uint64_t *d_stream_bytes,
+                                 void *d_ws, uint64_t ws_bytes, hipStream_t stream);
+lcq_status lcq_dequantize_ablation(lcq_ablation kind, lcq_dtype t,
+                                   const void *d_stream, uint64_t stream_bytes,
+                                   void *d_out, uint64_t n,
+                                   void *d_ws, uint64_t ws_bytes, hipStream_t stream);
+
 /* ---------------------------------------------- in-line outlier layout --
  * The paper's own layout (section 3.1): outliers stored in-line with the
  * bins.  One word of the field type's width per value -- its code (the same

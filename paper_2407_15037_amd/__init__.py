@@ -11,7 +11,8 @@ import os
 __all__ = ["ABS", "REL", "NOA", "F32", "F64", "LCQError", "lib", "max_stream_bytes",
            "workspace_bytes", "quantize", "dequantize", "stream_status", "profile_events",
            "set_lookback_spin", "tune_variants", "tune_set", "tune_get",
-           "inline_stream_bytes", "inline_workspace_bytes", "quantize_inline", "dequantize_inline", "SO_PATH"]
+           "inline_stream_bytes", "inline_workspace_bytes", "quantize_inline",
+           "quantize_ablation", "dequantize_ablation", "ABL_ABS_UNCHECKED", "ABL_REL_LIBM", "dequantize_inline", "SO_PATH"]
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 SO_PATH = os.path.join(HERE, "liblcq.so")
@@ -20,6 +21,8 @@ F32, F64 = 0, 1
 ABS, REL, NOA = 0, 1, 2
 OK, ERR_ARG, ERR_CAPACITY, ERR_STREAM, ERR_HIP = 0, 1, 2, 3, 4
 _QNAMES = {"abs": ABS, "rel": REL, "noa": NOA}
+ABL_ABS_UNCHECKED, ABL_REL_LIBM = 3, 4  # section 6 ablations (no guarantee by design)
+_ABLATIONS = {"abs_unchecked": ABL_ABS_UNCHECKED, "rel_libm": ABL_REL_LIBM}
 _OPS = {"quantize": 0, "dequantize": 1}
 
 if not os.path.exists(SO_PATH):
@@ -45,6 +48,10 @@ _lib.lcq_quantize_inline.argtypes = [_i32, _i32, _dbl, _vp, _u64, _vp, _u64, _vp
 _lib.lcq_quantize_inline.restype = _i32
 _lib.lcq_dequantize_inline.argtypes = [_i32, _vp, _u64, _vp, _u64, _vp, _u64, _vp]
 _lib.lcq_dequantize_inline.restype = _i32
+_lib.lcq_quantize_ablation.argtypes = [_i32, _i32, _dbl, _vp, _u64, _vp, _u64, _vp, _vp, _u64, _vp]
+_lib.lcq_quantize_ablation.restype = _i32
+_lib.lcq_dequantize_ablation.argtypes = [_i32, _i32, _vp, _u64, _vp, _u64, _vp, _u64, _vp]
+_lib.lcq_dequantize_ablation.restype = _i32
 _lib.lcq_stream_status.argtypes = [_vp, _vp, ctypes.POINTER(ctypes.c_int32)]
 _lib.lcq_stream_status.restype = _i32
 _lib.lcq_status_string.argtypes = [_i32]
@@ -148,6 +155,50 @@ def dequantize(stream_buf, dtype, n, *, stream_bytes=None, out=None, ws=None, st
     st = _lib.lcq_dequantize(dt, _ptr(stream_buf), sb, _ptr(out) if n else None, n, _ptr(ws),
                              ws.numel(), _stream_handle(stream))
     _check(st, "lcq_dequantize")
+    return out
+
+
+def _abl(kind):
+    return _ABLATIONS[kind] if isinstance(kind, str) else int(kind)
+
+
+def quantize_ablation(x, kind, eb, *, out=None, nbytes=None, ws=None, stream=None):
+    """One of the section 6 ablations ('abs_unchecked' or 'rel_libm'); same
+    buffers and return value as quantize().  Not error-bounded by design."""
+    import torch
+    if not x.is_cuda or not x.is_contiguous():
+        raise ValueError("x must be a contiguous CUDA tensor")
+    dt = _dtype_code(x.dtype)
+    n = x.numel()
+    k = _abl(kind)
+    if out is None:
+        out = torch.empty(int(_lib.lcq_max_stream_bytes(dt, n)), dtype=torch.uint8, device=x.device)
+    if nbytes is None:
+        nbytes = torch.empty(1, dtype=torch.int64, device=x.device)
+    if ws is None:
+        base = ABS if k == ABL_ABS_UNCHECKED else REL
+        ws = torch.empty(int(_lib.lcq_workspace_bytes(base, dt, n)), dtype=torch.uint8,
+                         device=x.device)
+    st = _lib.lcq_quantize_ablation(k, dt, float(eb), _ptr(x) if n else None, n, _ptr(out),
+                                    out.numel(), _ptr(nbytes), _ptr(ws), ws.numel(),
+                                    _stream_handle(stream))
+    _check(st, "lcq_quantize_ablation")
+    return out, nbytes
+
+
+def dequantize_ablation(stream_buf, kind, dtype, n, *, stream_bytes=None, out=None, ws=None,
+                        stream=None):
+    """Decode a stream of the given ablation kind (header status in ws)."""
+    import torch
+    dt = _dtype_code(dtype)
+    if out is None:
+        out = torch.empty(n, dtype=dtype, device=stream_buf.device)
+    if ws is None:
+        ws = torch.empty(64, dtype=torch.uint8, device=stream_buf.device)
+    sb = stream_buf.numel() if stream_bytes is None else int(stream_bytes)
+    st = _lib.lcq_dequantize_ablation(_abl(kind), dt, _ptr(stream_buf), sb, _ptr(out) if n else None,
+                                      n, _ptr(ws), ws.numel(), _stream_handle(stream))
+    _check(st, "lcq_dequantize_ablation")
     return out
 
 

@@ -268,8 +268,10 @@ struct PlainD {
 
 // Header check shared by the dequantize kernels; fills f and returns false
 // (after recording the status) when the stream does not describe this call.
+// `want_q` < 0 accepts the three quantizers, else exactly that (ablation)
+// quantizer code.
 template <typename T>
-__device__ __forceinline__ bool deq_setup(const PlainD &a, DField<T> &f) {
+__device__ __forceinline__ bool deq_setup(const PlainD &a, DField<T> &f, int want_q = -1) {
   using U = typename FT<T>::U;
   const uint64_t n = a.n;
   const uint64_t *hd = reinterpret_cast<const uint64_t *>(a.stream);
@@ -278,7 +280,8 @@ __device__ __forceinline__ bool deq_setup(const PlainD &a, DField<T> &f) {
   const int q = (int)((h0 >> 48) & 0xFF);
   const uint64_t oo = outlier_offset(n);
   // the header must describe exactly this call's stream (dtype, n, layout)
-  const bool bad = (h0 & ~(0xFFull << 48)) != header_word0(a.dtype, 0) || q > 2 ||
+  const bool bad_q = want_q < 0 ? q > 2 : q != want_q;
+  const bool bad = (h0 & ~(0xFFull << 48)) != header_word0(a.dtype, 0) || bad_q ||
                    hd[1] != n || k > n || oo + k * sizeof(T) > a.stream_bytes;
   const unsigned long long tag = (unsigned long long)(a.epoch << 16);
   if (blockIdx.x == 0 && threadIdx.x == 0)
@@ -288,7 +291,7 @@ __device__ __forceinline__ bool deq_setup(const PlainD &a, DField<T> &f) {
   f.n = n;
   f.k = k;
   f.step = from_bits((U)hd[4]);
-  f.rel = (q == kREL);
+  f.rel = (q == kREL || q == kREL_LIBM);
   f.out = static_cast<T *>(a.out);
   f.status = a.status;
   f.tag = tag;
@@ -299,6 +302,13 @@ template <typename T, int CPW, int PF>
 __global__ __launch_bounds__(kBlock) void k_dequantize_chunks(PlainD a) {
   DField<T> f;
   if (deq_setup<T>(a, f)) dequant_chunks<T, CPW, PF>(f, blockIdx.x);
+}
+
+// Decoder of the section 6 ablation streams (quantizer code Q in the header).
+template <typename T, int Q>
+__global__ __launch_bounds__(kBlock) void k_dequantize_ablation(PlainD a) {
+  DField<T> f;
+  if (deq_setup<T>(a, f, Q)) dequant_chunks<T, 1, 1, Q == kREL_LIBM>(f, blockIdx.x);
 }
 
 template <typename T, int SL, int RD>
@@ -346,6 +356,10 @@ uint64_t ws_need(lcq_quantizer q, lcq_dtype t, uint64_t n) {
 }
 
 lcq_status check_launch() { return hipGetLastError() == hipSuccess ? LCQ_OK : LCQ_ERR_HIP; }
+
+constexpr int kAblationVariant = 6;  // the default chunk-per-wavefront kernels
+static_assert(kQVariants[kAblationVariant].cpw > 0 && kDVariants[kAblationVariant].cpw == 1,
+              "ablation variant is the two-pass chunk form");
 
 template <typename T, int Q, int V>
 void launch_quantize(const PlainQ &a, const StageQ &sq, hipStream_t s) {
@@ -407,7 +421,10 @@ template <typename T, int Q>
 lcq_status run_quantize(double eb, const void *d_in, uint64_t n, void *d_stream,
                         uint64_t *d_bytes, void *d_ws, hipStream_t s) {
   const int dt = sizeof(T) == 8 ? LCQ_F64 : LCQ_F32;
-  const int v = g_variant[0][dt].load(std::memory_order_relaxed);
+  // the ablations always run the default chunk kernels, so their timing
+  // compares like with like
+  const int v = Q >= kABS_UNCHECKED ? kAblationVariant
+                                    : g_variant[0][dt].load(std::memory_order_relaxed);
   const HostParams hp = host_params<T>(Q, eb);
   uint8_t *ws = static_cast<uint8_t *>(d_ws);
   PlainQ a{};
@@ -482,7 +499,8 @@ lcq_status run_quantize(double eb, const void *d_in, uint64_t n, void *d_stream,
     return check_launch();
   }
   if (g_ev_before) (void)hipEventRecord(g_ev_before, s);
-  launch_quantize_variant<T, Q>(v, a, sq, s);
+  if constexpr (Q >= kABS_UNCHECKED) launch_quantize<T, Q, kAblationVariant>(a, sq, s);
+  else launch_quantize_variant<T, Q>(v, a, sq, s);
   if (g_ev_after) (void)hipEventRecord(g_ev_after, s);
   return check_launch();
 }
@@ -603,6 +621,68 @@ lcq_status lcq_dequantize(lcq_dtype t, const void *d_stream, uint64_t stream_byt
   if (g_ev_before) (void)hipEventRecord(g_ev_before, stream);
   if (t == LCQ_F32) launch_dequantize_variant<float>(v, ntiles, a, stream);
   else launch_dequantize_variant<double>(v, ntiles, a, stream);
+  if (g_ev_after) (void)hipEventRecord(g_ev_after, stream);
+  return check_launch();
+}
+
+lcq_status lcq_quantize_ablation(lcq_ablation kind, lcq_dtype t, double eb, const void *d_in,
+                                 uint64_t n, void *d_stream, uint64_t stream_cap,
+                                 uint64_t *d_stream_bytes, void *d_ws, uint64_t ws_bytes,
+                                 hipStream_t stream) {
+  if (kind != LCQ_ABL_ABS_UNCHECKED && kind != LCQ_ABL_REL_LIBM) return LCQ_ERR_ARG;
+  if (t != LCQ_F32 && t != LCQ_F64) return LCQ_ERR_ARG;
+  if (!(eb > 0.0) || !std::isfinite(eb) || (kind == LCQ_ABL_REL_LIBM && !(eb < 1.0)))
+    return LCQ_ERR_ARG;
+  if (n > LCQ_MAX_N) return LCQ_ERR_ARG;
+  if ((n && !d_in) || !d_stream || !d_stream_bytes || !d_ws) return LCQ_ERR_ARG;
+  if ((n && !aligned16(d_in)) || !aligned16(d_stream) || !aligned16(d_ws) ||
+      ((uintptr_t)d_stream_bytes & 7u))
+    return LCQ_ERR_ARG;
+  if (stream_cap < lcq_max_stream_bytes(t, n)) return LCQ_ERR_CAPACITY;
+  const lcq_quantizer base = kind == LCQ_ABL_ABS_UNCHECKED ? LCQ_ABS : LCQ_REL;
+  if (ws_bytes < ws_need(base, t, n)) return LCQ_ERR_CAPACITY;
+  if (t == LCQ_F32) {
+    if (kind == LCQ_ABL_ABS_UNCHECKED)
+      return run_quantize<float, kABS_UNCHECKED>(eb, d_in, n, d_stream, d_stream_bytes, d_ws, stream);
+    return run_quantize<float, kREL_LIBM>(eb, d_in, n, d_stream, d_stream_bytes, d_ws, stream);
+  }
+  if (kind == LCQ_ABL_ABS_UNCHECKED)
+    return run_quantize<double, kABS_UNCHECKED>(eb, d_in, n, d_stream, d_stream_bytes, d_ws, stream);
+  return run_quantize<double, kREL_LIBM>(eb, d_in, n, d_stream, d_stream_bytes, d_ws, stream);
+}
+
+lcq_status lcq_dequantize_ablation(lcq_ablation kind, lcq_dtype t, const void *d_stream,
+                                   uint64_t stream_bytes, void *d_out, uint64_t n, void *d_ws,
+                                   uint64_t ws_bytes, hipStream_t stream) {
+  if (kind != LCQ_ABL_ABS_UNCHECKED && kind != LCQ_ABL_REL_LIBM) return LCQ_ERR_ARG;
+  if (t != LCQ_F32 && t != LCQ_F64) return LCQ_ERR_ARG;
+  if (n > LCQ_MAX_N) return LCQ_ERR_ARG;
+  if (!d_stream || (n && !d_out) || !d_ws) return LCQ_ERR_ARG;
+  if (!aligned16(d_stream) || (n && !aligned16(d_out)) || !aligned16(d_ws)) return LCQ_ERR_ARG;
+  if (ws_bytes < 8) return LCQ_ERR_CAPACITY;
+  if (stream_bytes < outlier_offset(n)) return LCQ_ERR_STREAM;
+  PlainD a{};
+  a.stream = static_cast<const uint8_t *>(d_stream);
+  a.stream_bytes = stream_bytes;
+  a.n = n;
+  a.out = d_out;
+  a.status = static_cast<unsigned long long *>(d_ws);
+  a.epoch = g_epoch.fetch_add(1) + 1;
+  a.dtype = (int)t;
+  const uint64_t tile = deq_tile_len(kAblationVariant);
+  const dim3 grid((unsigned)(n ? (n + tile - 1) / tile : 1));
+  if (g_ev_before) (void)hipEventRecord(g_ev_before, stream);
+  if (t == LCQ_F32) {
+    if (kind == LCQ_ABL_ABS_UNCHECKED)
+      hipLaunchKernelGGL((k_dequantize_ablation<float, kABS_UNCHECKED>), grid, dim3(kBlock), 0, stream, a);
+    else
+      hipLaunchKernelGGL((k_dequantize_ablation<float, kREL_LIBM>), grid, dim3(kBlock), 0, stream, a);
+  } else {
+    if (kind == LCQ_ABL_ABS_UNCHECKED)
+      hipLaunchKernelGGL((k_dequantize_ablation<double, kABS_UNCHECKED>), grid, dim3(kBlock), 0, stream, a);
+    else
+      hipLaunchKernelGGL((k_dequantize_ablation<double, kREL_LIBM>), grid, dim3(kBlock), 0, stream, a);
+  }
   if (g_ev_after) (void)hipEventRecord(g_ev_after, stream);
   return check_launch();
 }

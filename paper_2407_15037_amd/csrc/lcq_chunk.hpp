@@ -382,8 +382,8 @@ __device__ void quant_finish(const FinishField<T> &f, uint64_t g) {
 
 // ---------------------------------------------------------- dequantize ---
 // Decode the CPW * kWaves chunks of workgroup `tile`, PF chunks per
-// wavefront loaded at a time.
-template <typename T, int CPW, int PF>
+// wavefront loaded at a time (LIBM: the library-exp2 REL ablation).
+template <typename T, int CPW, int PF, bool LIBM = false>
 __device__ void dequant_chunks(const DField<T> &f, uint64_t tile) {
   static_assert(CPW % PF == 0, "whole prefetch groups");
   using U = typename FT<T>::U;
@@ -421,7 +421,7 @@ __device__ void dequant_chunks(const DField<T> &f, uint64_t tile) {
 #pragma unroll
         for (int e = 0; e < W; e++) {
           const bool sent = cc[p][j][e] == kSent;
-          y[j][e] = sent ? (T)0 : decode<T>(cc[p][j][e], f.step, f.rel);
+          y[j][e] = sent ? (T)0 : decode<T, LIBM>(cc[p][j][e], f.step, f.rel);
           if (sent && i0 + e < n) om |= 1u << (W * j + e);
         }
       }

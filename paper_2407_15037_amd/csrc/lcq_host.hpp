@@ -71,17 +71,18 @@ template <typename T> inline HostParams host_params(int q, double eb) {
   HostParams h{};
   const T e = rd_t<T>(eb);
   h.eb_down = to_bits(e);
-  if (q == kABS) {
+  if (q == kABS || q == kABS_UNCHECKED) {
     const T step = e + e;  // bins of width 2e (section 2.2)
     h.step = to_bits(step);
     h.inv = to_bits((T)1 / step);
     h.bound = to_bits(e);
-  } else if (q == kREL) {
+  } else if (q == kREL || q == kREL_LIBM) {
     // upper side checked against eh = RD(eb), lower side against
     // el = RD(eb/(1+eb)); bins of width 2*lambda in approximate-log2 space
-    // with lambda = log2approx(1 + eh)  (section 3.2)
+    // with lambda = log2approx(1 + eh)  (section 3.2; the library-log2
+    // ablation takes lambda = log2(1 + eh))
     const T el = rd_t<T>(rel_low_double(eb));
-    const T lam = log2approx<T>((T)1 + e);
+    const T lam = q == kREL_LIBM ? lib_log2((T)1 + e) : log2approx<T>((T)1 + e);
     const T step = lam + lam;
     h.step = to_bits(step);
     h.inv = to_bits((T)1 / step);

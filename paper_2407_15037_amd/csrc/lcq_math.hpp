@@ -91,6 +91,16 @@ template <typename T> struct FieldParams {
 };
 
 enum : int { kABS = 0, kREL = 1, kNOA = 2 };
+// The two ablations of section 6 (no guarantee by design): ABS without the
+// double-check, and REL with the math library's log2 / exp2 in place of the
+// section 3.2 approximations.
+enum : int { kABS_UNCHECKED = 3, kREL_LIBM = 4 };
+template <int Q> constexpr bool is_rel_q() { return Q == kREL || Q == kREL_LIBM; }
+
+LCQ_HD float lib_log2(float x) { return log2f(x); }
+LCQ_HD double lib_log2(double x) { return log2(x); }
+LCQ_HD float lib_exp2(float x) { return exp2f(x); }
+LCQ_HD double lib_exp2(double x) { return exp2(x); }
 
 // One value -> its int32 code, or kSent if it must be stored losslessly.
 // Evaluates every step for every lane (no data-dependent branches) and only
@@ -102,18 +112,18 @@ template <typename T, int Q> LCQ_HD int32_t encode(T x, const FieldParams<T> &p)
   const U E = (u >> F::kMant) & F::kExpMask;
   const U frac = u & F::kFracMask;
   // section 2.2 / 3.1: INF, NaN and denormals (REL: also zeros) are lossless
-  bool ok = (E != F::kExpMask) && (E != 0 || (Q != kREL && frac == 0));
+  bool ok = (E != F::kExpMask) && (E != 0 || (!is_rel_q<Q>() && frac == 0));
   if (Q == kNOA) ok = ok && !p.lossless_all;
 
-  if (Q == kREL) {
+  if constexpr (is_rel_q<Q>()) {
     const T a = from_bits((U)(u & ~F::kSign));
-    const T q = rint_t(log2approx(a) * p.inv);
+    const T q = rint_t((Q == kREL_LIBM ? lib_log2(a) : log2approx(a)) * p.inv);
     // section 3.3: both range tests, on the float, before any conversion
     ok = ok && (q > (T)-kMaxBin) && (q < (T)kMaxBin);
     // qb is integral and inside (-2^30, 2^30), so (T)(int)qb == qb exactly
     const T qb = ok ? q : (T)0;
     const int32_t b = (int32_t)qb;
-    const T rec = pow2approx(qb * p.step);
+    const T rec = Q == kREL_LIBM ? lib_exp2(qb * p.step) : pow2approx(qb * p.step);
     // section 3.1 double-check against both sides of the section 2.1.2 range
     // |rec - a| equals (a - rec) when rec < a: round-to-nearest is
     // symmetric under negation, so one subtraction serves both sides
@@ -129,19 +139,20 @@ template <typename T, int Q> LCQ_HD int32_t encode(T x, const FieldParams<T> &p)
     const T qb = ok ? q : (T)0;  // integral, in range: (T)(int)qb == qb
     const int32_t b = (int32_t)qb;
     const T rec = qb * p.step;
-    ok = ok && (abs_t(x - rec) <= p.bound);
+    if constexpr (Q != kABS_UNCHECKED) ok = ok && (abs_t(x - rec) <= p.bound);
     return ok ? b : kSent;
   }
 }
 
-// One non-sentinel code -> its value (the decoder side of encode).
-template <typename T> LCQ_HD T decode(int32_t c, T step, bool rel) {
+// One non-sentinel code -> its value (the decoder side of encode; LIBM: the
+// library-exp2 ablation).
+template <typename T, bool LIBM = false> LCQ_HD T decode(int32_t c, T step, bool rel) {
   using F = FT<T>;
   using U = typename F::U;
   if (rel) {
     const U sgn = (U)(c & 1);
     const int32_t b = c >> 1;  // arithmetic shift: c = 2b + sign
-    const T a = pow2approx((T)b * step);
+    const T a = LIBM ? lib_exp2((T)b * step) : pow2approx((T)b * step);
     return from_bits((U)(to_bits(a) | (sgn << (sizeof(T) * 8 - 1))));
   }
   return (T)c * step;
