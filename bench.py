@@ -12,6 +12,8 @@ produced by the library's HIP kernels through the C ABI.
 Also reported on the same JSON line:
   ops          per-kernel time and GB/s (HIP events around each main kernel)
   roofline     the dominant kernel against the 8 TB/s HBM peak
+  ablation     section 6: ABS with vs without the double-check, REL with the
+               section 3.2 approximations vs the device math library
   inline_layout the same fields in the in-line outlier layout (section 3.1):
                per-kernel time, decodes equal to the list layout's
   batched      2,000 fields, log-uniform 4 KiB - 64 MiB, 70 % float32, random
@@ -229,6 +231,83 @@ def run_inline(args, x, xr, plain):
             "decode_equals_list_layout": same}
 
 
+# ---------------------------------------------------------------- ablation --
+ABL_SAMPLE = 1 << 20  # REL-libm codes kept for the CPU/GPU comparison
+
+
+def run_ablation(args, x, xr, plain):
+    """The paper's two ablations (section 6) on the plain step's fields, same
+    kernels and launch shape: ABS with vs without the double-check, and REL
+    with the section 3.2 approximations vs the device math library's
+    log2 / exp2.  Event-timed like the plain ops; the unchecked ABS decode is
+    counted against the bound on the device."""
+    import numpy as np
+    import torch
+    import paper_2407_15037_amd as lcq
+    dev = torch.device("cuda:0")
+    eb = args.eb
+    n = x.size
+    xa = torch.from_numpy(x).to(dev)
+    xl = torch.from_numpy(xr).to(dev)
+    cap = lcq.max_stream_bytes(torch.float32, n)
+    buf = torch.empty(cap, dtype=torch.uint8, device=dev)
+    nb = torch.zeros(1, dtype=torch.int64, device=dev)
+    ws = torch.empty(lcq.workspace_bytes("rel", torch.float32, n), dtype=torch.uint8, device=dev)
+    out = torch.empty(n, dtype=torch.float32, device=dev)
+    reps = max(3, args.steps // 2)
+
+    def timed(fn):
+        ts = []
+        for r in range(reps + 1):
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(); e1.record()
+            lcq.profile_events(e0, e1)
+            fn()
+            lcq.profile_events(None, None)
+            torch.cuda.synchronize()
+            if r:
+                ts.append(e0.elapsed_time(e1) * 1e3)
+        return sum(ts) / len(ts)
+
+    res = {}
+    for kind, xt in (("abs_unchecked", xa), ("rel_libm", xl)):
+        tq = timed(lambda: lcq.quantize_ablation(xt, kind, eb, out=buf, nbytes=nb, ws=ws))
+        size = int(nb.item())
+        td = timed(lambda: lcq.dequantize_ablation(buf, kind, torch.float32, n, stream_bytes=size,
+                                                   out=out, ws=ws))
+        k = header_k(buf)
+        fin = torch.isfinite(xt)
+        if kind == "abs_unchecked":
+            e = np.float32(eb)  # the float32 bound: largest float32 not above eb
+            if float(e) > eb:
+                e = np.nextafter(e, np.float32(0))
+            e = float(e)
+            err = (xt.double() - out.double()).abs()
+            viol = int(((err > e) & fin).sum().item())
+            base = plain["kern"]
+            res["abs"] = {
+                "protected_quantize_us": round(base["quantize_abs"]["avg_us"], 2),
+                "unchecked_quantize_us": round(tq, 2),
+                "check_cost_pct": round(100.0 * (base["quantize_abs"]["avg_us"] - tq) / tq, 2),
+                "protected_dequantize_us": round(base["dequantize_abs"]["avg_us"], 2),
+                "unchecked_dequantize_us": round(td, 2),
+                "unchecked_outliers": k, "protected_outliers": plain["ks"]["abs"],
+                "unchecked_values_outside_bound": viol}
+        else:
+            base = plain["kern"]
+            res["rel"] = {
+                "mitchell_quantize_us": round(base["quantize_rel"]["avg_us"], 2),
+                "libm_quantize_us": round(tq, 2),
+                "mitchell_dequantize_us": round(base["dequantize_rel"]["avg_us"], 2),
+                "libm_dequantize_us": round(td, 2),
+                "mitchell_outliers": plain["ks"]["rel"], "libm_outliers": k}
+            codes = buf[64: 64 + 4 * ABL_SAMPLE].view(torch.int32).cpu().numpy().copy()
+    del xa, xl, buf, ws, out
+    torch.cuda.empty_cache()
+    return res, codes
+
+
 # ----------------------------------------------------------------- batched --
 def make_batch_specs(nf, seed=3):
     import synth
@@ -408,7 +487,7 @@ def run_serving(args):
 
 
 # ------------------------------------------------------------ CPU baseline --
-def cpu_baseline_leg(x, xr, eb, plain, batch_sample):
+def cpu_baseline_leg(x, xr, eb, plain, batch_sample, abl_codes=None):
     """The CPU oracle, single thread, timed on the plain step's three fields
     (quantize + dequantize each); its streams also check the GPU's."""
     import numpy as np
@@ -429,6 +508,13 @@ def cpu_baseline_leg(x, xr, eb, plain, batch_sample):
     bparity = 0
     for sp, xv, gs in batch_sample:
         bparity += int(np.array_equal(oracle.quantize(sp["q"], xv, sp["eb"]), gs))
+    if abl_codes is not None:
+        # REL-libm ablation: the host library's codes for the first values of
+        # the field vs the GPU's (REL codes depend on the value alone)
+        st = oracle.quantize("rel_libm", xr[: abl_codes.size], eb)
+        oc = st[64: 64 + 4 * abl_codes.size].view(np.int32)
+        parity["rel_libm_codes_differing_cpu_vs_gpu"] = (
+            f"{int(np.count_nonzero(oc != abl_codes))} of {abl_codes.size}")
     base = {"value": round(3 * n * 4 / tsum / 1e9, 4), "unit": "GB/s", "cores": 1, "kind": "oracle",
             "sample": f"the plain step's three fields ({n} float32 values each): one "
                       "single-threaded oracle quantize + dequantize per field"}
@@ -451,6 +537,7 @@ def main():
                          "the same kernels)")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-inline", action="store_true")
+    ap.add_argument("--no-ablation", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--fields", type=int, default=2000)
     ap.add_argument("--batch-reps", type=int, default=5)
@@ -516,13 +603,16 @@ def main():
     }
     if not args.no_inline:
         result["inline_layout"] = run_inline(args, x, xr, plain)
+    abl_codes = None
+    if not args.no_ablation:
+        result["ablation"], abl_codes = run_ablation(args, x, xr, plain)
     sample = []
     if not args.no_batched:
         result["batched"], sample = run_batched(args)
     if not args.no_serving:
         result["serving"] = run_serving(args)
     if not args.no_cpu_baseline:
-        base, parity, bpar = cpu_baseline_leg(x, xr, args.eb, plain, sample)
+        base, parity, bpar = cpu_baseline_leg(x, xr, args.eb, plain, sample, abl_codes)
         result["cpu_baseline"] = base
         result["parity_vs_oracle"] = {"plain": parity, "batched_sample": bpar}
     print(json.dumps(result), flush=True)
