@@ -569,6 +569,7 @@ uint64_t orc_inline_stream_bytes(int dtype, uint64_t n) {
 int orc_quantize_inline(int q, int dtype, double eb, const void *in, uint64_t n,
                         void *stream, uint64_t cap, uint64_t *stream_bytes) {
   if (!fpenv_ok()) return ORC_ERR_FPENV;
+  if (q > ORC_NOA) return ORC_ERR_ARG; /* the ablations use the list layout only */
   int st = check_args(q, dtype, eb);
   if (st) return st;
   if (!stream || !stream_bytes || (n > 0 && !in)) return ORC_ERR_ARG;
@@ -633,8 +634,7 @@ int orc_dequantize_inline(int dtype, const void *stream, uint64_t bytes, void *o
   if (bytes < 64) return ORC_ERR_STREAM;
   const uint8_t *S = (const uint8_t *)stream;
   const uint64_t s = dtype == ORC_F64 ? 8 : 4;
-  if (get_u32(S) != MAGIC_INLINE || S[4] != 1 || S[5] != dtype || S[6] > ORC_REL_LIBM ||
-      S[7] != 0)
+  if (get_u32(S) != MAGIC_INLINE || S[4] != 1 || S[5] != dtype || S[6] > ORC_NOA || S[7] != 0)
     return ORC_ERR_STREAM;
   if (get_u64(S + 8) != n || bytes < orc_inline_stream_bytes(dtype, n)) return ORC_ERR_STREAM;
   const int q = S[6];
