@@ -65,6 +65,11 @@ def _bind(L):
     L.orc_quantize_inline.restype = i32
     L.orc_dequantize_inline.argtypes = [i32, vp, u64, vp, u64]
     L.orc_dequantize_inline.restype = i32
+    L.orc_pack_max_bytes.argtypes = [i32, u64]
+    L.orc_pack_max_bytes.restype = u64
+    for name in ("orc_pack", "orc_unpack"):
+        getattr(L, name).argtypes = [i32, vp, u64, u64, vp, u64, ctypes.POINTER(u64)]
+        getattr(L, name).restype = i32
     for name in ("orc_log2approx_f32", "orc_pow2approx_f32",
                  "orc_log2approx_f64", "orc_pow2approx_f64"):
         getattr(L, name).argtypes = [vp, vp, u64]
@@ -139,6 +144,34 @@ def dequantize_inline(stream, dtype, n, L=None):
     if st != OK:
         raise OracleError(st, "orc_dequantize_inline")
     return out
+
+
+def pack(stream, dtype, n, L=None):
+    """Lossless packing stage: an LCQ1 stream (uint8 array) -> packed stream."""
+    L = L or lib()
+    stream = np.ascontiguousarray(stream, dtype=np.uint8)
+    dt = F64 if np.dtype(dtype) == np.float64 else F32
+    cap = int(L.orc_pack_max_bytes(dt, n))
+    buf = np.zeros(cap, dtype=np.uint8)
+    nbytes = ctypes.c_uint64(0)
+    st = L.orc_pack(dt, stream.ctypes.data, stream.size, n, buf.ctypes.data, cap, ctypes.byref(nbytes))
+    if st != OK:
+        raise OracleError(st, "orc_pack")
+    return buf[: nbytes.value].copy()
+
+
+def unpack(packed, dtype, n, L=None):
+    """Inverse of pack(): the LCQ1 stream, byte for byte."""
+    L = L or lib()
+    packed = np.ascontiguousarray(packed, dtype=np.uint8)
+    dt = F64 if np.dtype(dtype) == np.float64 else F32
+    cap = int(L.orc_max_stream_bytes(dt, n))
+    buf = np.zeros(cap, dtype=np.uint8)
+    nbytes = ctypes.c_uint64(0)
+    st = L.orc_unpack(dt, packed.ctypes.data, packed.size, n, buf.ctypes.data, cap, ctypes.byref(nbytes))
+    if st != OK:
+        raise OracleError(st, "orc_unpack")
+    return buf[: nbytes.value].copy()
 
 
 def params(q, dtype, eb, x=None, L=None):

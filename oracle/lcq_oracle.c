@@ -658,3 +658,177 @@ int orc_dequantize_inline(int dtype, const void *stream, uint64_t bytes, void *o
   }
   return ORC_OK;
 }
+
+/* --------------------------------------------- lossless packing stage ----
+ * A lossless back-end for the code stream (the paper passes the quantizer's
+ * output to further lossless stages of its framework without naming them;
+ * this one is defined here).  It rewrites an LCQ1 stream, chunk by chunk of
+ * 1024 codes, at the smallest bit width that holds the chunk:
+ *
+ *   c'_j = code_j, or 0 where code_j is the outlier sentinel
+ *   plain mode: z_j = zigzag(c'_j)
+ *   delta mode: z_j = zigzag(c'_j - c'_{j-1}), c'_{-1} = 0 (mod 2^32)
+ *   zigzag(v) = (v << 1) ^ (v >> 31) on 32-bit two's complement
+ *   w = bit length of the largest z_j of the chunk (0..32); the mode with
+ *   the smaller w is kept (plain on a tie)
+ *
+ *   [0,64)            LCQ1 header with magic "LCQP"
+ *   [64, 64+8C)       the LCQ1 chunk table, verbatim
+ *   ot = align16(64+8C):   u64 offset of each chunk record in the payload,
+ *                     C+1 entries (the last is the payload size)
+ *   pl = align16(ot + 8(C+1)): records, each starting 16-byte aligned:
+ *       16-byte record header: u8 w, u8 mode (0 plain, 1 delta),
+ *                     u8 has_bitmap, 13 zero bytes
+ *       if has_bitmap: 128 bytes, bit i%8 of byte i/8 set when value i of
+ *                     the chunk is an outlier (chunks with outliers only)
+ *       ceil(len*w/8) bytes: z_j in bits [j*w, j*w+w), least significant
+ *                     bit first; then zeros to the next 16-byte boundary
+ *   oo = align16(pl + payload): the k raw outlier words, verbatim
+ *   total = oo + k*s; every padding byte is zero
+ */
+#define MAGIC_PACKED 0x5051434Cu /* bytes 'L','C','Q','P' */
+
+static uint32_t zigzag32(uint32_t v) { return (v << 1) ^ (uint32_t)((int32_t)v >> 31); }
+static uint32_t unzigzag32(uint32_t z) { return (z >> 1) ^ (0u - (z & 1u)); }
+static unsigned bitlen32(uint32_t v) { unsigned b = 0; while (v) { b++; v >>= 1; } return b; }
+
+static int32_t code_at(const uint8_t *codes, uint64_t i) {
+  int32_t c;
+  memcpy(&c, codes + 4 * i, 4);
+  return c;
+}
+
+/* Width, mode and bitmap flag of a chunk of len codes. */
+static void pack_plan(const uint8_t *codes, uint64_t len, unsigned *w, unsigned *mode,
+                      unsigned *has_bm) {
+  uint32_t prev = 0, mp = 0, md = 0;
+  *has_bm = 0;
+  for (uint64_t j = 0; j < len; j++) {
+    const int32_t cj = code_at(codes, j);
+    uint32_t c = cj == SENT ? 0u : (uint32_t)cj;
+    if (cj == SENT) *has_bm = 1;
+    uint32_t zp = zigzag32(c), zd = zigzag32(c - prev);
+    if (zp > mp) mp = zp;
+    if (zd > md) md = zd;
+    prev = c;
+  }
+  unsigned wp = bitlen32(mp), wd = bitlen32(md);
+  *mode = wd < wp;
+  *w = *mode ? wd : wp;
+}
+
+static uint64_t record_bytes(uint64_t len, unsigned w, unsigned has_bm) {
+  return 16 + (has_bm ? 128 : 0) + align16((len * w + 7) / 8);
+}
+
+uint64_t orc_pack_max_bytes(int dtype, uint64_t n) {
+  uint64_t s = dtype == ORC_F64 ? 8 : 4, C = n_chunks(n);
+  uint64_t ot = align16(64 + 8 * C), pl = align16(ot + 8 * (C + 1));
+  return align16(pl + C * record_bytes(CHUNK, 32, 1)) + s * n;
+}
+
+int orc_pack(int dtype, const void *stream, uint64_t bytes, uint64_t n, void *out_v,
+             uint64_t cap, uint64_t *out_bytes) {
+  if (dtype != ORC_F32 && dtype != ORC_F64) return ORC_ERR_ARG;
+  if (!stream || !out_v || !out_bytes) return ORC_ERR_ARG;
+  const uint8_t *S = (const uint8_t *)stream;
+  const uint64_t s = dtype == ORC_F64 ? 8 : 4;
+  if (bytes < 64 || get_u32(S) != MAGIC || S[4] != 1 || S[5] != dtype || S[6] > ORC_NOA ||
+      S[7] != LOG2_CHUNK || get_u64(S + 8) != n)
+    return ORC_ERR_STREAM;
+  const uint64_t k = get_u64(S + 16), C = n_chunks(n);
+  if (k > n || bytes < out_offset(n) + s * k) return ORC_ERR_STREAM;
+  if (cap < orc_pack_max_bytes(dtype, n)) return ORC_ERR_CAPACITY;
+  uint8_t *P = (uint8_t *)out_v;
+  const uint64_t ot = align16(64 + 8 * C), pl = align16(ot + 8 * (C + 1));
+  const uint8_t *codes = S + 64;
+  memcpy(P, S, 64);
+  put_u32(P, MAGIC_PACKED);
+  memcpy(P + 64, S + ct_offset(n), 8 * C);
+  memset(P + 64 + 8 * C, 0, ot - (64 + 8 * C));
+  memset(P + ot + 8 * (C + 1), 0, pl - (ot + 8 * (C + 1)));
+  uint64_t off = 0;
+  for (uint64_t c = 0; c < C; c++) {
+    const uint64_t b = c * CHUNK, len = n - b < CHUNK ? n - b : CHUNK;
+    unsigned w, mode, hb;
+    pack_plan(codes + 4 * b, len, &w, &mode, &hb);
+    const uint64_t rb = record_bytes(len, w, hb);
+    put_u64(P + ot + 8 * c, off);
+    uint8_t *R = P + pl + off;
+    memset(R, 0, rb);
+    R[0] = (uint8_t)w;
+    R[1] = (uint8_t)mode;
+    R[2] = (uint8_t)hb;
+    uint8_t *bits = R + 16 + (hb ? 128 : 0);
+    uint32_t prev = 0;
+    for (uint64_t j = 0; j < len; j++) {
+      const int32_t cj = code_at(codes, b + j);
+      const int sent = cj == SENT;
+      const uint32_t cv = sent ? 0u : (uint32_t)cj;
+      if (sent) R[16 + j / 8] |= (uint8_t)(1u << (j % 8));
+      const uint32_t z = zigzag32(mode ? cv - prev : cv);
+      prev = cv;
+      for (unsigned t = 0; t < w; t++) /* bit t of z goes to stream bit j*w+t */
+        if ((z >> t) & 1u) bits[(j * w + t) / 8] |= (uint8_t)(1u << ((j * w + t) % 8));
+    }
+    off += rb;
+  }
+  put_u64(P + ot + 8 * C, off);
+  const uint64_t oo = align16(pl + off);
+  memset(P + pl + off, 0, oo - (pl + off));
+  memcpy(P + oo, S + out_offset(n), s * k);
+  *out_bytes = oo + s * k;
+  return ORC_OK;
+}
+
+int orc_unpack(int dtype, const void *packed, uint64_t bytes, uint64_t n, void *out_v,
+               uint64_t cap, uint64_t *out_bytes) {
+  if (dtype != ORC_F32 && dtype != ORC_F64) return ORC_ERR_ARG;
+  if (!packed || !out_v || !out_bytes) return ORC_ERR_ARG;
+  const uint8_t *P = (const uint8_t *)packed;
+  const uint64_t s = dtype == ORC_F64 ? 8 : 4, C = n_chunks(n);
+  if (bytes < 64 || get_u32(P) != MAGIC_PACKED || P[4] != 1 || P[5] != dtype || P[6] > ORC_NOA ||
+      P[7] != LOG2_CHUNK || get_u64(P + 8) != n)
+    return ORC_ERR_STREAM;
+  const uint64_t k = get_u64(P + 16);
+  const uint64_t ot = align16(64 + 8 * C), pl = align16(ot + 8 * (C + 1));
+  if (k > n || bytes < pl) return ORC_ERR_STREAM;
+  const uint64_t payload = get_u64(P + ot + 8 * C);
+  if (payload > bytes - pl) return ORC_ERR_STREAM;
+  const uint64_t oo = align16(pl + payload);
+  if (oo > bytes || bytes - oo < s * k) return ORC_ERR_STREAM;
+  if (cap < out_offset(n) + s * k) return ORC_ERR_CAPACITY;
+  uint8_t *S = (uint8_t *)out_v;
+  memcpy(S, P, 64);
+  put_u32(S, MAGIC);
+  memcpy(S + ct_offset(n), P + 64, 8 * C);
+  memset(S + 64 + 4 * n, 0, ct_offset(n) - (64 + 4 * n));
+  memset(S + ct_offset(n) + 8 * C, 0, out_offset(n) - (ct_offset(n) + 8 * C));
+  memcpy(S + out_offset(n), P + oo, s * k);
+  for (uint64_t c = 0; c < C; c++) {
+    const uint64_t b = c * CHUNK, len = n - b < CHUNK ? n - b : CHUNK;
+    const uint64_t off = get_u64(P + ot + 8 * c);
+    if (off > payload || payload - off < 16) return ORC_ERR_STREAM;
+    const uint8_t *R = P + pl + off;
+    const unsigned w = R[0], mode = R[1], hb = R[2];
+    if (w > 32 || mode > 1 || hb > 1) return ORC_ERR_STREAM;
+    if (payload - off < record_bytes(len, w, hb)) return ORC_ERR_STREAM;
+    /* records are contiguous: the next offset must follow this record */
+    if (get_u64(P + ot + 8 * (c + 1)) != off + record_bytes(len, w, hb)) return ORC_ERR_STREAM;
+    const uint8_t *bits = R + 16 + (hb ? 128 : 0);
+    uint32_t prev = 0;
+    for (uint64_t j = 0; j < len; j++) {
+      uint32_t z = 0;
+      for (unsigned t = 0; t < w; t++)
+        z |= (uint32_t)((bits[(j * w + t) / 8] >> ((j * w + t) % 8)) & 1u) << t;
+      const uint32_t v = unzigzag32(z);
+      const uint32_t cv = mode ? prev + v : v;
+      prev = cv;
+      const int sent = hb && ((R[16 + j / 8] >> (j % 8)) & 1u);
+      const int32_t code = sent ? SENT : (int32_t)cv;
+      memcpy(S + 64 + 4 * (b + j), &code, 4);
+    }
+  }
+  *out_bytes = out_offset(n) + s * k;
+  return ORC_OK;
+}

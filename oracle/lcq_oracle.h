@@ -84,6 +84,16 @@ int orc_quantize_inline(int q, int dtype, double eb, const void *in, uint64_t n,
 int orc_dequantize_inline(int dtype, const void *stream, uint64_t bytes, void *out,
                           uint64_t n);
 
+/* Lossless packing stage for LCQ1 streams (per 1024-code chunk: plain or
+ * delta zigzag codes at the chunk's smallest bit width, an outlier bitmap
+ * for chunks with outliers; layout in lcq_oracle.c).  orc_pack rewrites an
+ * LCQ1 stream, orc_unpack restores it byte for byte. */
+uint64_t orc_pack_max_bytes(int dtype, uint64_t n);
+int orc_pack(int dtype, const void *stream, uint64_t bytes, uint64_t n, void *out,
+             uint64_t cap, uint64_t *out_bytes);
+int orc_unpack(int dtype, const void *packed, uint64_t bytes, uint64_t n, void *out,
+               uint64_t cap, uint64_t *out_bytes);
+
 #ifdef __cplusplus
 }
 #endif

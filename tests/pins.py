@@ -515,9 +515,132 @@ def pin_ablation_rel_libm(L):
             assert coded.mean() > 0.9 and np.array_equal(codes[coded], want[coded]), (dt, eb)
 
 
+# --------------------------------------------------- lossless packing ---
+def _lcq1_by_hand(codes, dtype=np.float32, outliers=()):
+    """An LCQ1 stream assembled field by field from its layout (ABS header
+    words zero apart from magic / version / dtype / n / k)."""
+    codes = np.asarray(codes, dtype=np.int32)
+    n = codes.size
+    s = np.dtype(dtype).itemsize
+    C = (n + 1023) // 1024
+    ct = (64 + 4 * n + 15) // 16 * 16
+    out = (ct + 8 * C + 15) // 16 * 16
+    k = len(outliers)
+    b = np.zeros(out + s * k, dtype=np.uint8)
+    b[0:4] = np.frombuffer(b"LCQ1", dtype=np.uint8)
+    b[4], b[5], b[6], b[7] = 1, (0 if s == 4 else 1), 0, 10
+    b[8:16] = np.array([n], dtype=np.uint64).view(np.uint8)
+    b[16:24] = np.array([k], dtype=np.uint64).view(np.uint8)
+    b[64: 64 + 4 * n] = codes.view(np.uint8)
+    sent = codes == np.iinfo(np.int32).min
+    before = np.concatenate([[0], np.cumsum(sent)])[::1024][:C]
+    b[ct: ct + 8 * C] = before.astype(np.uint64).view(np.uint8)
+    if k:
+        b[out:] = np.asarray(outliers, dtype=np.uint32 if s == 4 else np.uint64).view(np.uint8)
+    return b
+
+
+def pin_pack_golden(L):
+    """Codes 0, 1, 2, 3 by hand: plain zigzag 0, 2, 4, 6 needs 3 bits, deltas
+    0, 1, 1, 1 -> zigzag 0, 2, 2, 2 need 2: delta mode, w = 2, and the bits
+    00 01 01 01 (value j at bits 2j..2j+1, least significant first) make the
+    single byte 0b10101000."""
+    st = _lcq1_by_hand([0, 1, 2, 3])
+    want = np.zeros(128, dtype=np.uint8)
+    want[:64] = st[:64]
+    want[0:4] = np.frombuffer(b"LCQP", dtype=np.uint8)
+    # [64,72) chunk table entry 0 = 0; [80,88) record offset 0; [88,96) payload 32
+    want[88] = 32
+    want[96], want[97], want[98] = 2, 1, 0
+    want[112] = 0xA8
+    got = O.pack(st, np.float32, 4, L=L)
+    assert np.array_equal(got, want), (got, want)
+    assert np.array_equal(O.unpack(got, np.float32, 4, L=L), st)
+
+
+def _zz(v):
+    v = np.asarray(v, dtype=np.int64) & 0xFFFFFFFF
+    s = v.astype(np.uint32).view(np.int32).astype(np.int64)
+    return ((s << 1) ^ (s >> 31)) & 0xFFFFFFFF
+
+
+def _bitlen(v):
+    return int(v).bit_length()
+
+
+def pin_pack_roundtrip_and_widths(L):
+    """unpack(pack(s)) == s byte for byte for quantizer streams of every kind
+    and size; each record's width is the bit length of the largest zigzag
+    value of the mode it names, that mode is the narrower one (plain on a
+    tie), and the outlier bitmap is present exactly for chunks with
+    outliers."""
+    rng = _rng(61)
+    streams = []
+    for dt in (np.float32, np.float64):
+        for n in (0, 1, 5, 1023, 1024, 1025, 3 * 1024 + 77):
+            x = synth.sines_1d(max(n, 1), 62 + n, dtype=dt)[:n]
+            if n:
+                x, _, _ = synth.inject_specials(x, max(1, n // 300), 63, 1e-3)
+            for q in ("abs", "rel", "noa"):
+                y = x if q != "rel" else synth.rel_variant(np.nan_to_num(x.astype(np.float64)), 64, dtype=dt)
+                streams.append((dt, y.size, O.quantize(q, y, 1e-3, L=L)))
+        base = synth.sines_1d(2500, 65, dtype=dt)
+        allsp, _, _ = synth.inject_specials(base, 2500, 66, 1e-3)
+        streams.append((dt, 2500, O.quantize("abs", allsp, 1e-3, L=L)))
+    # codes that use all 32 bits and wrap in delta mode
+    big = rng.integers(-(2 ** 31) + 1, 2 ** 31, 3000).astype(np.int32)
+    big[::97] = np.iinfo(np.int32).min
+    streams.append((np.float32, 3000, _lcq1_by_hand(big, outliers=np.arange(np.count_nonzero(big == np.iinfo(np.int32).min)))))
+    for dt, n, st in streams:
+        pk = O.pack(st, dt, n, L=L)
+        assert np.array_equal(O.unpack(pk, dt, n, L=L), st), (dt, n)
+        codes = parse(st, dt)["codes"].astype(np.int64)
+        C = (n + 1023) // 1024
+        ot = (64 + 8 * C + 15) // 16 * 16
+        pl = (ot + 8 * (C + 1) + 15) // 16 * 16
+        offs = pk[ot: ot + 8 * (C + 1)].view(np.uint64).astype(np.int64)
+        for c in range(C):
+            cc = codes[c * 1024: (c + 1) * 1024]
+            sent = cc == np.iinfo(np.int32).min
+            cv = np.where(sent, 0, cc)
+            wp = _bitlen(_zz(cv).max())
+            wd = _bitlen(_zz(cv - np.concatenate([[0], cv[:-1]])).max())
+            r = pl + offs[c]
+            w, mode, hb = int(pk[r]), int(pk[r + 1]), int(pk[r + 2])
+            assert (w, mode) == ((wd, 1) if wd < wp else (wp, 0)), (dt, n, c, w, mode, wp, wd)
+            assert hb == int(sent.any())
+            size = 16 + 128 * hb + (cc.size * w + 7) // 8
+            assert offs[c + 1] - offs[c] == (size + 15) // 16 * 16
+
+
+def pin_pack_errors(L):
+    st = O.quantize("abs", synth.sines_1d(3000, 67, dtype=np.float32), 1e-3, L=L)
+    pk = O.pack(st, np.float32, 3000, L=L)
+    C = 3
+    ot = (64 + 8 * C + 15) // 16 * 16
+    pl = (ot + 8 * (C + 1) + 15) // 16 * 16
+    for name, off, val in (("magic", 0, 0x58), ("n", 8, 0x01), ("width", pl, 40),
+                           ("offset", ot + 8, 0xFF)):
+        bad = pk.copy()
+        bad[off] = val if name != "n" else bad[off] ^ val
+        try:
+            O.unpack(bad, np.float32, 3000, L=L)
+        except O.OracleError as e:
+            assert e.status == O.ERR_STREAM, name
+        else:
+            raise AssertionError(f"accepted corrupted {name}")
+    try:
+        O.unpack(pk[:-1], np.float32, 3000, L=L)
+    except O.OracleError as e:
+        assert e.status == O.ERR_STREAM
+    else:
+        raise AssertionError("accepted truncated stream")
+
+
 PINS = [pin_mitchell_golden, pin_mitchell_powers_of_two, pin_mitchell_log2_error,
         pin_mitchell_log2_monotone, pin_mitchell_pow2_error, pin_params_abs,
         pin_params_rel, pin_params_noa, pin_arg_errors, pin_structure, pin_bounds,
         pin_specials, pin_abs_nearest_bin, pin_rel_nearest_bin, pin_bin_range,
         pin_roundtrip_sizes, pin_stream_errors, pin_noa_degenerate, pin_inline_format,
-        pin_ablation_abs_unchecked, pin_ablation_rel_libm]
+        pin_ablation_abs_unchecked, pin_ablation_rel_libm, pin_pack_golden,
+        pin_pack_roundtrip_and_widths, pin_pack_errors]

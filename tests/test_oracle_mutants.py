@@ -54,6 +54,14 @@ MUTANTS = {
     "rel_el": ("float el = round_down_f32(rel_low_double(eb));", "float el = round_down_f32(eb);"),
     # ABS step taken as e instead of 2e
     "abs_step": ("    p->stepf = e + e;", "    p->stepf = e;"),
+    # packing: zigzag with a logical shift (negative values mapped wrongly)
+    "pack_zigzag": ("static uint32_t zigzag32(uint32_t v) { return (v << 1) ^ (uint32_t)((int32_t)v >> 31); }",
+                    "static uint32_t zigzag32(uint32_t v) { return (v << 1) ^ (v >> 31); }"),
+    # packing: delta mode taken on a tie
+    "pack_tie": ("  *mode = wd < wp;", "  *mode = wd <= wp;"),
+    # packing: most significant bit of each byte first
+    "pack_bit_order": ("if ((z >> t) & 1u) bits[(j * w + t) / 8] |= (uint8_t)(1u << ((j * w + t) % 8));",
+                       "if ((z >> t) & 1u) bits[(j * w + t) / 8] |= (uint8_t)(0x80u >> ((j * w + t) % 8));"),
     # ablation: the unchecked ABS still runs the double-check
     "unchecked_checks": ("if (p->q != ORC_ABS_UNCHECKED && !(fabsf(x - rec) <= p->boundf)) return 1;",
                          "if (!(fabsf(x - rec) <= p->boundf)) return 1;"),
