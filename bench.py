@@ -12,6 +12,8 @@ produced by the library's HIP kernels through the C ABI.
 Also reported on the same JSON line:
   ops          per-kernel time and GB/s (HIP events around each main kernel)
   roofline     the dominant kernel against the 8 TB/s HBM peak
+  packing      the lossless packing stage after each quantizer: compression
+               ratio, pack / unpack time, byte-exact round trip
   ablation     section 6: ABS with vs without the double-check, REL with the
                section 3.2 approximations vs the device math library
   inline_layout the same fields in the in-line outlier layout (section 3.1):
@@ -229,6 +231,51 @@ def run_inline(args, x, xr, plain):
     torch.cuda.empty_cache()
     return {"stream_bytes": nb, "ops": dict(sorted(ops.items())),
             "decode_equals_list_layout": same}
+
+
+# ----------------------------------------------------------------- packing --
+def run_packing(args, x, xr):
+    """Lossless packing stage after each quantizer on the plain step's
+    fields: packed size (compression ratio against the float32 input and
+    against the LCQ1 stream), pack / unpack time (events around each call,
+    all of its kernels), and the unpacked stream equal to the original."""
+    import torch
+    import paper_2407_15037_amd as lcq
+    dev = torch.device("cuda:0")
+    eb = args.eb
+    n = x.size
+    reps = max(3, args.steps // 4)
+    res = {}
+    for q, arr in (("abs", x), ("noa", x), ("rel", xr)):
+        xt = torch.from_numpy(arr).to(dev)
+        st, nb = lcq.quantize(xt, q, eb)
+        size = int(nb.item())
+        pk = torch.empty(lcq.pack_max_bytes(torch.float32, n), dtype=torch.uint8, device=dev)
+        pnb = torch.zeros(1, dtype=torch.int64, device=dev)
+        ws = torch.empty(lcq.pack_workspace_bytes(torch.float32, n), dtype=torch.uint8, device=dev)
+        back = torch.empty(lcq.max_stream_bytes(torch.float32, n), dtype=torch.uint8, device=dev)
+        bnb = torch.zeros(1, dtype=torch.int64, device=dev)
+        tp, tu = [], []
+        for r in range(reps + 1):
+            e0, e1, e2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
+            e0.record()
+            lcq.pack(st, torch.float32, n, stream_bytes=size, out=pk, nbytes=pnb, ws=ws)
+            e1.record()
+            lcq.unpack(pk, torch.float32, n, out=back, nbytes=bnb, ws=ws)
+            e2.record()
+            torch.cuda.synchronize()
+            if r:
+                tp.append(e0.elapsed_time(e1) * 1e3)
+                tu.append(e1.elapsed_time(e2) * 1e3)
+        psize = int(pnb.item())
+        same = int(bnb.item()) == size and torch.equal(back[:size], st[:size])
+        res[q] = {"lcq1_bytes": size, "packed_bytes": psize,
+                  "ratio_vs_input": round(n * 4 / psize, 3), "ratio_vs_lcq1": round(size / psize, 3),
+                  "pack_us": round(sum(tp) / len(tp), 2), "unpack_us": round(sum(tu) / len(tu), 2),
+                  "unpacked_equals_stream": bool(same)}
+        del xt, st, pk, ws, back
+        torch.cuda.empty_cache()
+    return res
 
 
 # ---------------------------------------------------------------- ablation --
@@ -538,6 +585,7 @@ def main():
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-inline", action="store_true")
     ap.add_argument("--no-ablation", action="store_true")
+    ap.add_argument("--no-packing", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--fields", type=int, default=2000)
     ap.add_argument("--batch-reps", type=int, default=5)
@@ -603,6 +651,8 @@ def main():
     }
     if not args.no_inline:
         result["inline_layout"] = run_inline(args, x, xr, plain)
+    if not args.no_packing:
+        result["packing"] = run_packing(args, x, xr)
     abl_codes = None
     if not args.no_ablation:
         result["ablation"], abl_codes = run_ablation(args, x, xr, plain)

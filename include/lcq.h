@@ -140,6 +140,41 @@ lcq_status lcq_dequantize_ablation(lcq_ablation kind, lcq_dtype t,
                                    void *d_out, uint64_t n,
                                    void *d_ws, uint64_t ws_bytes, hipStream_t stream);
 
+/* ------------------------------------------------ lossless packing stage --
+ * A lossless back-end for LCQ1 streams (the paper passes the quantizer's
+ * output on to further lossless stages without naming them; this stage is
+ * this library's own).  Per chunk of 1024 codes, c'_j = code_j or 0 for an
+ * outlier sentinel, and z_j = zigzag(c'_j) (plain) or zigzag(c'_j - c'_{j-1})
+ * (delta, c'_{-1} = 0, mod 2^32), zigzag(v) = (v << 1) ^ (v >> 31); the mode
+ * with the smaller bit width w of the chunk's largest z is kept (plain on a
+ * tie) and z_j is stored in bits [j w, j w + w), least significant first.
+ *   [0,64)                   LCQ1 header with magic "LCQP"
+ *   [64, 64+8C)              the LCQ1 chunk table
+ *   ot = align16(64+8C)      u64 record offset per chunk, C+1 entries (the
+ *                            last is the payload size)
+ *   pl = align16(ot+8(C+1))  records, 16-byte aligned: u8 w, u8 mode (0
+ *                            plain, 1 delta), u8 has_bitmap, 13 zero bytes;
+ *                            if has_bitmap a 128-byte outlier bitmap (bit
+ *                            i%8 of byte i/8); ceil(len*w/8) bytes of bits;
+ *                            zeros to the next 16-byte boundary
+ *   oo = align16(pl+payload) the k raw outliers; size = oo + k*s
+ * lcq_pack reads an LCQ1 stream of n values (checked on the device, status
+ * in the first 8 bytes of d_ws, read with lcq_stream_status) and writes the
+ * packed stream and its size (device u64); packed_cap >=
+ * lcq_pack_max_bytes(t, n), ws_bytes >= lcq_pack_workspace_bytes(t, n).
+ * lcq_unpack restores the LCQ1 stream byte for byte (stream_cap >=
+ * lcq_max_stream_bytes(t, n) suffices; ws >= 8 bytes); every offset, width
+ * and record extent is checked on the device and a mismatch is recorded in
+ * the status word (output then unspecified, nothing written outside it). */
+uint64_t lcq_pack_max_bytes(lcq_dtype t, uint64_t n);        /* 0: bad dtype / n */
+uint64_t lcq_pack_workspace_bytes(lcq_dtype t, uint64_t n);  /* 0: bad dtype / n */
+lcq_status lcq_pack(lcq_dtype t, const void *d_stream, uint64_t stream_bytes, uint64_t n,
+                    void *d_packed, uint64_t packed_cap, uint64_t *d_packed_bytes,
+                    void *d_ws, uint64_t ws_bytes, hipStream_t stream);
+lcq_status lcq_unpack(lcq_dtype t, const void *d_packed, uint64_t packed_bytes, uint64_t n,
+                      void *d_stream, uint64_t stream_cap, uint64_t *d_stream_bytes,
+                      void *d_ws, uint64_t ws_bytes, hipStream_t stream);
+
 /* ---------------------------------------------- in-line outlier layout --
  * The paper's own layout (section 3.1): outliers stored in-line with the
  * bins.  One word of the field type's width per value -- its code (the same

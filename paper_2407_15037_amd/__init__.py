@@ -12,7 +12,8 @@ __all__ = ["ABS", "REL", "NOA", "F32", "F64", "LCQError", "lib", "max_stream_byt
            "workspace_bytes", "quantize", "dequantize", "stream_status", "profile_events",
            "set_lookback_spin", "tune_variants", "tune_set", "tune_get",
            "inline_stream_bytes", "inline_workspace_bytes", "quantize_inline",
-           "quantize_ablation", "dequantize_ablation", "ABL_ABS_UNCHECKED", "ABL_REL_LIBM", "dequantize_inline", "SO_PATH"]
+           "quantize_ablation", "dequantize_ablation", "ABL_ABS_UNCHECKED", "ABL_REL_LIBM",
+           "pack_max_bytes", "pack_workspace_bytes", "pack", "unpack", "dequantize_inline", "SO_PATH"]
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 SO_PATH = os.path.join(HERE, "liblcq.so")
@@ -52,6 +53,13 @@ _lib.lcq_quantize_ablation.argtypes = [_i32, _i32, _dbl, _vp, _u64, _vp, _u64, _
 _lib.lcq_quantize_ablation.restype = _i32
 _lib.lcq_dequantize_ablation.argtypes = [_i32, _i32, _vp, _u64, _vp, _u64, _vp, _u64, _vp]
 _lib.lcq_dequantize_ablation.restype = _i32
+_lib.lcq_pack_max_bytes.argtypes = [_i32, _u64]
+_lib.lcq_pack_max_bytes.restype = _u64
+_lib.lcq_pack_workspace_bytes.argtypes = [_i32, _u64]
+_lib.lcq_pack_workspace_bytes.restype = _u64
+for _name in ("lcq_pack", "lcq_unpack"):
+    getattr(_lib, _name).argtypes = [_i32, _vp, _u64, _u64, _vp, _u64, _vp, _vp, _u64, _vp]
+    getattr(_lib, _name).restype = _i32
 _lib.lcq_stream_status.argtypes = [_vp, _vp, ctypes.POINTER(ctypes.c_int32)]
 _lib.lcq_stream_status.restype = _i32
 _lib.lcq_status_string.argtypes = [_i32]
@@ -200,6 +208,50 @@ def dequantize_ablation(stream_buf, kind, dtype, n, *, stream_bytes=None, out=No
                                       n, _ptr(ws), ws.numel(), _stream_handle(stream))
     _check(st, "lcq_dequantize_ablation")
     return out
+
+
+def pack_max_bytes(dtype, n):
+    return int(_lib.lcq_pack_max_bytes(_dtype_code(dtype), n))
+
+
+def pack_workspace_bytes(dtype, n):
+    return int(_lib.lcq_pack_workspace_bytes(_dtype_code(dtype), n))
+
+
+def pack(stream_buf, dtype, n, *, stream_bytes=None, out=None, nbytes=None, ws=None, stream=None):
+    """Lossless packing stage: LCQ1 stream (uint8 CUDA tensor) -> packed
+    stream.  Returns (packed buffer, one-element int64 tensor with its size);
+    the input check's status lands in ws (read with stream_status)."""
+    import torch
+    dt = _dtype_code(dtype)
+    if out is None:
+        out = torch.empty(pack_max_bytes(dtype, n), dtype=torch.uint8, device=stream_buf.device)
+    if nbytes is None:
+        nbytes = torch.empty(1, dtype=torch.int64, device=stream_buf.device)
+    if ws is None:
+        ws = torch.empty(pack_workspace_bytes(dtype, n), dtype=torch.uint8, device=stream_buf.device)
+    sb = stream_buf.numel() if stream_bytes is None else int(stream_bytes)
+    st = _lib.lcq_pack(dt, _ptr(stream_buf), sb, n, _ptr(out), out.numel(), _ptr(nbytes),
+                       _ptr(ws), ws.numel(), _stream_handle(stream))
+    _check(st, "lcq_pack")
+    return out, nbytes
+
+
+def unpack(packed_buf, dtype, n, *, packed_bytes=None, out=None, nbytes=None, ws=None, stream=None):
+    """Inverse of pack(): (LCQ1 stream buffer, size tensor)."""
+    import torch
+    dt = _dtype_code(dtype)
+    if out is None:
+        out = torch.empty(max_stream_bytes(dtype, n), dtype=torch.uint8, device=packed_buf.device)
+    if nbytes is None:
+        nbytes = torch.empty(1, dtype=torch.int64, device=packed_buf.device)
+    if ws is None:
+        ws = torch.empty(64, dtype=torch.uint8, device=packed_buf.device)
+    pb = packed_buf.numel() if packed_bytes is None else int(packed_bytes)
+    st = _lib.lcq_unpack(dt, _ptr(packed_buf), pb, n, _ptr(out), out.numel(), _ptr(nbytes),
+                         _ptr(ws), ws.numel(), _stream_handle(stream))
+    _check(st, "lcq_unpack")
+    return out, nbytes
 
 
 def inline_stream_bytes(dtype, n):

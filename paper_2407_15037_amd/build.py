@@ -10,7 +10,8 @@ import subprocess
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 SO = os.path.join(HERE, "liblcq.so")
-SRCS = [os.path.join(HERE, "csrc", f) for f in ("lcq.hip", "lcq_batch.hip", "lcq_serve.hip")]
+SRCS = [os.path.join(HERE, "csrc", f) for f in ("lcq.hip", "lcq_batch.hip", "lcq_serve.hip",
+                                                       "lcq_pack.hip")]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [

@@ -1,0 +1,559 @@
+// lcq_pack.hip -- lossless packing stage for LCQ1 streams on gfx950.
+//
+// The paper hands the quantizer's output to further lossless stages of its
+// framework without naming them; this stage is defined here.  Per chunk of
+// 1024 codes (the stream format's chunk), with c'_j = code_j or 0 for an
+// outlier sentinel:
+//   plain mode  z_j = zigzag(c'_j)
+//   delta mode  z_j = zigzag(c'_j - c'_{j-1}), c'_{-1} = 0 (mod 2^32)
+// w = bit length of the chunk's largest z (0..32), the narrower mode kept
+// (plain on a tie); z_j occupies bits [j w, j w + w) of the chunk's record,
+// least significant bit first.  A chunk with outliers also carries a
+// 1024-bit outlier bitmap.  The LCQ1 chunk table and outliers are carried
+// over verbatim, so unpacking restores the LCQ1 stream byte for byte.
+//
+//   [0,64)                  LCQ1 header with magic "LCQP"
+//   [64, 64+8C)             LCQ1 chunk table
+//   ot = align16(64+8C)     u64 record offset per chunk (+1: payload size)
+//   pl = align16(ot+8(C+1)) records: 16-byte header (u8 w, u8 mode, u8
+//                           has_bitmap, 13 zero bytes), [128-byte bitmap],
+//                           packed bits, zeros to a 16-byte boundary
+//   oo = align16(pl+payload) the k raw outliers
+//
+// Kernels (one wavefront per chunk, the chunk-per-wavefront mapping):
+//   k_pack_plan   widths, modes and record sizes; one atomic add per
+//                 workgroup into its group's byte count
+//   k_pack_scan   one workgroup per group: record offsets, header, padding,
+//                 packed size
+//   k_pack_write  records (z staged in LDS, each lane assembles whole 32-bit
+//                 output words), chunk table, outliers
+//   k_unpack      per chunk: record checks, bit extraction, inverse zigzag,
+//                 wavefront prefix sum (delta mode), sentinels from the
+//                 bitmap; header, chunk table, outliers
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+#include <chrono>
+#include <cstring>
+
+#include "lcq.h"
+#include "lcq_chunk.hpp"
+#include "lcq_host.hpp"
+#include "lcq_math.hpp"
+#include "lcq_tile.hpp"
+
+using namespace lcq;
+
+namespace {
+
+constexpr uint32_t kMagicPacked = 0x5051434Cu;  // "LCQP"
+constexpr int kCW = 4;                           // codes per lane per sub-block
+constexpr int kCSub = (int)kChunk / (64 * kCW);  // 4 sub-blocks per chunk
+constexpr uint64_t kPackTile = kChunk * kWaves;  // codes per workgroup (4 chunks)
+
+__host__ __device__ inline uint64_t packed_table_offset(uint64_t C) { return align16(64 + 8 * C); }
+__host__ __device__ inline uint64_t packed_payload_offset(uint64_t C) {
+  return align16(packed_table_offset(C) + 8 * (C + 1));
+}
+__host__ __device__ inline uint64_t record_bytes(uint64_t len, unsigned w, unsigned hb) {
+  return 16 + (hb ? 128 : 0) + align16((len * w + 7) / 8);
+}
+
+__device__ __forceinline__ uint32_t zigzag(uint32_t v) {
+  return (v << 1) ^ (uint32_t)((int32_t)v >> 31);
+}
+__device__ __forceinline__ uint32_t unzigzag(uint32_t z) { return (z >> 1) ^ (0u - (z & 1u)); }
+__device__ __forceinline__ unsigned bitlen(uint32_t v) { return v ? 32u - (unsigned)__clz((int)v) : 0u; }
+
+__device__ __forceinline__ uint32_t wave_or(uint32_t v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v |= __shfl_xor(v, o, 64);
+  return v;
+}
+
+// The LCQ1 header of an input stream describes exactly this call.
+__device__ __forceinline__ bool lcq1_header_ok(const uint8_t *s, uint64_t bytes, int dtype,
+                                               uint64_t n, uint64_t &k) {
+  const uint64_t *hd = reinterpret_cast<const uint64_t *>(s);
+  const uint64_t h0 = hd[0];
+  k = hd[2];
+  const uint64_t sz = dtype == LCQ_F64 ? 8 : 4;
+  return (h0 & ~(0xFFull << 48)) == header_word0(dtype, 0) && ((h0 >> 48) & 0xFF) <= 2 &&
+         hd[1] == n && k <= n && outlier_offset(n) + k * sz <= bytes;
+}
+
+// One chunk's codes as c' (sentinels -> 0) and flags, lane's 16 positions.
+struct ChunkCodes {
+  uint32_t cv[kCSub][kCW];
+  unsigned flags;  // bit 4 j + e: outlier sentinel
+};
+
+__device__ __forceinline__ void load_chunk(const int32_t *codes, uint64_t n, uint64_t c, int lane,
+                                           ChunkCodes &cc) {
+  cc.flags = 0;
+#pragma unroll
+  for (int j = 0; j < kCSub; j++) {
+    const uint64_t i0 = chunk_value<kCW>(c, j, lane);
+    int32_t v[kCW];
+    load_codes<kCW>(codes, i0, n, v);
+#pragma unroll
+    for (int e = 0; e < kCW; e++) {
+      const bool sent = v[e] == kSent && i0 + e < n;
+      cc.cv[j][e] = sent ? 0u : (uint32_t)v[e];
+      if (sent) cc.flags |= 1u << (kCW * j + e);
+    }
+  }
+}
+
+// z values of a chunk in plain (DELTA false) or delta mode; 0 past n.
+template <bool DELTA>
+__device__ __forceinline__ void chunk_z(const ChunkCodes &cc, uint64_t n, uint64_t c, int lane,
+                                        uint32_t (&z)[kCSub][kCW]) {
+  uint32_t carry = 0;  // last c' of the previous sub-block
+#pragma unroll
+  for (int j = 0; j < kCSub; j++) {
+    const uint64_t i0 = chunk_value<kCW>(c, j, lane);
+    uint32_t prev = 0;
+    if constexpr (DELTA) {
+      const uint32_t up = __shfl_up(cc.cv[j][kCW - 1], 1, 64);
+      prev = lane == 0 ? carry : up;
+      carry = __shfl(cc.cv[j][kCW - 1], 63, 64);
+    }
+#pragma unroll
+    for (int e = 0; e < kCW; e++) {
+      const uint32_t d = DELTA ? cc.cv[j][e] - prev : cc.cv[j][e];
+      z[j][e] = i0 + e < n ? zigzag(d) : 0u;
+      prev = cc.cv[j][e];
+    }
+  }
+}
+
+// Width, mode and bitmap flag of one chunk (same on every lane).
+__device__ __forceinline__ void chunk_plan(const ChunkCodes &cc, uint64_t n, uint64_t c, int lane,
+                                           unsigned &w, unsigned &mode, unsigned &hb) {
+  uint32_t z[kCSub][kCW];
+  uint32_t op = 0, od = 0;
+  chunk_z<false>(cc, n, c, lane, z);
+#pragma unroll
+  for (int j = 0; j < kCSub; j++)
+#pragma unroll
+    for (int e = 0; e < kCW; e++) op |= z[j][e];
+  chunk_z<true>(cc, n, c, lane, z);
+#pragma unroll
+  for (int j = 0; j < kCSub; j++)
+#pragma unroll
+    for (int e = 0; e < kCW; e++) od |= z[j][e];
+  const unsigned wp = bitlen(wave_or(op)), wd = bitlen(wave_or(od));
+  mode = wd < wp ? 1u : 0u;
+  w = mode ? wd : wp;
+  hb = __ballot(cc.flags != 0) ? 1u : 0u;
+}
+
+struct PackArgs {
+  const uint8_t *in;      // LCQ1 stream
+  uint64_t in_bytes;
+  uint64_t n;
+  uint8_t *out;           // packed stream
+  uint64_t *out_bytes;
+  uint32_t *sizes;        // record bytes per chunk
+  uint32_t *meta;         // w | mode << 8 | hb << 16 per chunk
+  unsigned long long *group;
+  uint64_t tiles_per_group, chunks_per_group, ngroups;
+  unsigned long long *status;
+  uint64_t epoch;
+  int dtype;
+};
+
+__global__ __launch_bounds__(kBlock) void k_pack_plan(PackArgs a) {
+  __shared__ unsigned s_tot[kWaves];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const uint64_t n = a.n, nch = n_chunks(n);
+  uint64_t k;
+  if (!lcq1_header_ok(a.in, a.in_bytes, a.dtype, n, k)) return;  // uniform over the grid
+  const uint64_t c = (uint64_t)blockIdx.x * kWaves + wave;
+  unsigned size = 0;
+  if (c < nch) {
+    ChunkCodes cc;
+    load_chunk(reinterpret_cast<const int32_t *>(a.in + 64), n, c, lane, cc);
+    unsigned w, mode, hb;
+    chunk_plan(cc, n, c, lane, w, mode, hb);
+    const uint64_t len = min<uint64_t>(kChunk, n - c * kChunk);
+    size = (unsigned)record_bytes(len, w, hb);
+    if (lane == 0) {
+      a.sizes[c] = size;
+      a.meta[c] = w | (mode << 8) | (hb << 16);
+    }
+  }
+  if (lane == 0) s_tot[wave] = size;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    unsigned long long t = 0;
+#pragma unroll
+    for (int i = 0; i < kWaves; i++) t += s_tot[i];
+    if (t) atomicAdd(a.group + blockIdx.x / a.tiles_per_group, t);
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_pack_scan(PackArgs a) {
+  __shared__ unsigned long long s_red[kWaves];
+  __shared__ unsigned long long s_wt[kWaves];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const uint64_t n = a.n, nch = n_chunks(n);
+  const uint64_t g = blockIdx.x;
+  uint64_t k;
+  const bool ok = lcq1_header_ok(a.in, a.in_bytes, a.dtype, n, k);
+  if (g == 0 && tid == 0) report_status(a.status, a.epoch << 16, ok ? LCQ_OK : LCQ_ERR_STREAM);
+  if (!ok) return;
+  const uint64_t ot = packed_table_offset(nch), pl = packed_payload_offset(nch);
+  uint64_t *offs = reinterpret_cast<uint64_t *>(a.out + ot);
+
+  unsigned long long b = 0;
+  for (uint64_t i = tid; i < g; i += kBlock) b += a.group[i];
+  b = wave_sum(b);
+  if (lane == 0) s_red[wave] = b;
+  __syncthreads();
+  uint64_t run = 0;
+#pragma unroll
+  for (int w = 0; w < kWaves; w++) run += s_red[w];
+
+  const uint64_t c0 = g * a.chunks_per_group, c1 = min(c0 + a.chunks_per_group, nch);
+  for (uint64_t cb = c0; cb < c1; cb += kBlock) {
+    const uint64_t c = cb + tid;
+    const unsigned long long sz = c < c1 ? a.sizes[c] : 0ull;
+    unsigned long long incl = sz;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      const unsigned long long t = __shfl_up(incl, o, 64);
+      if (lane >= o) incl += t;
+    }
+    if (lane == 63) s_wt[wave] = incl;
+    __syncthreads();
+    uint64_t before = 0, total = 0;
+#pragma unroll
+    for (int w = 0; w < kWaves; w++) {
+      if (w < wave) before += s_wt[w];
+      total += s_wt[w];
+    }
+    if (c < c1) offs[c] = run + before + (incl - sz);
+    run += total;
+    __syncthreads();  // s_wt is rewritten by the next batch
+  }
+
+  if (g == a.ngroups - 1 && tid == 0) {
+    const uint64_t s = a.dtype == LCQ_F64 ? 8 : 4;
+    const uint64_t oo = align16(pl + run);
+    offs[nch] = run;
+    const uint64_t *hin = reinterpret_cast<const uint64_t *>(a.in);
+    uint64_t *hout = reinterpret_cast<uint64_t *>(a.out);
+    hout[0] = (hin[0] & ~0xFFFFFFFFull) | kMagicPacked;
+#pragma unroll
+    for (int i = 1; i < 8; i++) hout[i] = hin[i];
+    for (uint64_t x = 64 + 8 * nch; x < ot; x++) a.out[x] = 0;
+    for (uint64_t x = ot + 8 * (nch + 1); x < pl; x++) a.out[x] = 0;
+    for (uint64_t x = pl + run; x < oo; x++) a.out[x] = 0;
+    *a.out_bytes = oo + k * s;
+  }
+}
+
+// Records, chunk table and outliers.  z values are staged in LDS so each
+// lane can assemble whole 32-bit output words.
+__global__ __launch_bounds__(kBlock) void k_pack_write(PackArgs a) {
+  __shared__ uint32_t s_z[kWaves][kChunk];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const uint64_t n = a.n, nch = n_chunks(n);
+  uint64_t k;
+  if (!lcq1_header_ok(a.in, a.in_bytes, a.dtype, n, k)) return;  // uniform over the grid
+  const uint64_t ot = packed_table_offset(nch), pl = packed_payload_offset(nch);
+  const uint64_t c = (uint64_t)blockIdx.x * kWaves + wave;
+  const bool active = c < nch;  // uniform over the wavefront
+  unsigned w = 0, hb = 0;
+  uint64_t len = 0;
+  uint8_t *rec = nullptr;
+  if (active) {
+    const uint32_t m = a.meta[c];
+    w = m & 0xFF;
+    const unsigned mode = (m >> 8) & 1;
+    hb = (m >> 16) & 1;
+    len = min<uint64_t>(kChunk, n - c * kChunk);
+    rec = a.out + pl + reinterpret_cast<const uint64_t *>(a.out + ot)[c];
+    ChunkCodes cc;
+    load_chunk(reinterpret_cast<const int32_t *>(a.in + 64), n, c, lane, cc);
+    uint32_t z[kCSub][kCW];
+    if (mode) chunk_z<true>(cc, n, c, lane, z);
+    else chunk_z<false>(cc, n, c, lane, z);
+#pragma unroll
+    for (int j = 0; j < kCSub; j++)
+#pragma unroll
+      for (int e = 0; e < kCW; e++) s_z[wave][64 * kCW * j + kCW * lane + e] = z[j][e];
+    // record header (16 bytes) and the outlier bitmap
+    if (lane < 4) {
+      const uint32_t word = lane == 0 ? (w | (mode << 8) | (hb << 16)) : 0u;
+      reinterpret_cast<uint32_t *>(rec)[lane] = word;
+    }
+    if (hb) {
+#pragma unroll
+      for (int j = 0; j < kCSub; j++) {
+        const unsigned fw = gather_flag_word<kCW>((cc.flags >> (kCW * j)) & 0xFu, lane);
+        if ((lane & 7) == 0) reinterpret_cast<uint32_t *>(rec + 16)[8 * j + lane / 8] = fw;
+      }
+    }
+    if (lane == 0) {
+      const uint64_t *ct_in = reinterpret_cast<const uint64_t *>(a.in + chunk_table_offset(n));
+      reinterpret_cast<uint64_t *>(a.out + 64)[c] = ct_in[c];
+    }
+  }
+  __syncthreads();  // every wavefront's z values are in LDS
+  if (active) {
+    // packed word t holds stream bits [32 t, 32 t + 32); the rest of the
+    // record, up to its 16-byte end, is zero
+    uint32_t *pw = reinterpret_cast<uint32_t *>(rec + 16 + (hb ? 128 : 0));
+    const uint64_t nbits = len * w;
+    const unsigned nwords = (unsigned)(align16((nbits + 7) / 8) / 4);
+    for (unsigned t = lane; t < nwords; t += 64) {
+      uint64_t acc = 0;
+      const uint64_t b0 = 32ull * t;
+      if (w && b0 < nbits) {
+        const uint64_t j0 = b0 / w, j1 = min<uint64_t>((b0 + 31) / w, len - 1);
+        for (uint64_t j = j0; j <= j1; j++) {
+          const uint64_t v = s_z[wave][j];
+          const int64_t sh = (int64_t)(j * w) - (int64_t)b0;
+          acc |= sh >= 0 ? (v << sh) : (v >> (-sh));
+        }
+      }
+      pw[t] = (uint32_t)acc;
+    }
+  }
+  // outliers, grid-stride over the raw words
+  const uint64_t s = a.dtype == LCQ_F64 ? 8 : 4;
+  const uint64_t payload = reinterpret_cast<const uint64_t *>(a.out + ot)[nch];
+  const uint64_t oo = align16(pl + payload);
+  const uint64_t words = k * s / 4;
+  const uint32_t *src = reinterpret_cast<const uint32_t *>(a.in + outlier_offset(n));
+  uint32_t *dst = reinterpret_cast<uint32_t *>(a.out + oo);
+  for (uint64_t i = (uint64_t)blockIdx.x * kBlock + threadIdx.x; i < words;
+       i += (uint64_t)gridDim.x * kBlock)
+    dst[i] = src[i];
+}
+
+struct UnpackArgs {
+  const uint8_t *in;      // packed stream
+  uint64_t in_bytes;
+  uint64_t n;
+  uint8_t *out;           // LCQ1 stream
+  uint64_t out_cap;
+  uint64_t *out_bytes;
+  unsigned long long *status;
+  uint64_t epoch;
+  int dtype;
+};
+
+__global__ __launch_bounds__(kBlock) void k_unpack(UnpackArgs a) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const uint64_t n = a.n, nch = n_chunks(n);
+  const uint64_t s = a.dtype == LCQ_F64 ? 8 : 4;
+  const uint64_t ot = packed_table_offset(nch), pl = packed_payload_offset(nch);
+  const unsigned long long tag = (unsigned long long)(a.epoch << 16);
+  // header and table bounds (the host checked in_bytes >= pl)
+  const uint64_t *hd = reinterpret_cast<const uint64_t *>(a.in);
+  const uint64_t h0 = hd[0], k = hd[2];
+  const uint64_t *offs = reinterpret_cast<const uint64_t *>(a.in + ot);
+  const uint64_t payload = offs[nch];
+  const uint64_t want0 = (uint64_t)kMagicPacked | (1ull << 32) | ((uint64_t)a.dtype << 40) |
+                         ((uint64_t)kLog2Chunk << 56);
+  const bool bad = (h0 & ~(0xFFull << 48)) != want0 || ((h0 >> 48) & 0xFF) > 2 || hd[1] != n ||
+                   k > n || payload > a.in_bytes - pl ||
+                   align16(pl + payload) + k * s > a.in_bytes ||
+                   outlier_offset(n) + k * s > a.out_cap;
+  if (blockIdx.x == 0 && threadIdx.x == 0)
+    report_status(a.status, tag, bad ? LCQ_ERR_STREAM : LCQ_OK);
+  if (bad) return;
+  const uint64_t c = (uint64_t)blockIdx.x * kWaves + wave;
+  if (c < nch) {
+    const uint64_t off = offs[c], nxt = offs[c + 1];
+    const uint64_t len = min<uint64_t>(kChunk, n - c * kChunk);
+    bool ok = off <= payload && payload - off >= 16;
+    unsigned w = 0, mode = 0, hb = 0;
+    const uint8_t *rec = a.in + pl + (ok ? off : 0);
+    if (ok) {
+      const uint32_t h = reinterpret_cast<const uint32_t *>(rec)[0];
+      w = h & 0xFF;
+      mode = (h >> 8) & 0xFF;
+      hb = (h >> 16) & 0xFF;
+      ok = w <= 32 && mode <= 1 && hb <= 1 && payload - off >= record_bytes(len, w, hb) &&
+           nxt == off + record_bytes(len, w, hb);
+    }
+    if (!ok) {
+      if (lane == 0) report_status(a.status, tag, LCQ_ERR_STREAM);
+    } else {
+      const uint32_t *pw = reinterpret_cast<const uint32_t *>(rec + 16 + (hb ? 128 : 0));
+      const uint32_t mask = w == 32 ? 0xFFFFFFFFu : ((1u << w) - 1u);
+      const uint64_t nbits = len * w;
+      int32_t *codes = reinterpret_cast<int32_t *>(a.out + 64);
+      uint32_t carry = 0;
+#pragma unroll
+      for (int j = 0; j < kCSub; j++) {
+        const uint64_t i0 = chunk_value<kCW>(c, j, lane);
+        const uint64_t l0 = i0 - c * kChunk;  // position in the chunk
+        uint32_t v[kCW];
+#pragma unroll
+        for (int e = 0; e < kCW; e++) {
+          uint32_t z = 0;
+          const uint64_t b = (l0 + e) * w;
+          if (w && l0 + e < len) {
+            const uint64_t q = b >> 5;
+            const unsigned sh = (unsigned)(b & 31);
+            uint64_t pair = pw[q];
+            if (sh + w > 32 && 32 * (q + 1) < nbits) pair |= (uint64_t)pw[q + 1] << 32;
+            z = (uint32_t)(pair >> sh) & mask;
+          }
+          v[e] = unzigzag(z);
+        }
+        if (mode) {
+          // prefix sum over the chunk in value order (mod 2^32)
+#pragma unroll
+          for (int e = 1; e < kCW; e++) v[e] += v[e - 1];
+          uint32_t incl = v[kCW - 1];
+#pragma unroll
+          for (int o = 1; o < 64; o <<= 1) {
+            const uint32_t t = __shfl_up(incl, o, 64);
+            if (lane >= o) incl += t;
+          }
+          const uint32_t excl = incl - v[kCW - 1] + carry;
+#pragma unroll
+          for (int e = 0; e < kCW; e++) v[e] += excl;
+          carry += __shfl(incl, 63, 64);
+        }
+        unsigned fl = 0;
+        if (hb) fl = (rec[16 + l0 / 8] >> (l0 % 8)) & 0xFu;
+        int32_t out[kCW];
+#pragma unroll
+        for (int e = 0; e < kCW; e++) out[e] = ((fl >> e) & 1u) ? kSent : (int32_t)v[e];
+        store_codes<kCW>(codes, i0, n, out);
+      }
+      if (lane == 0) {
+        reinterpret_cast<uint64_t *>(a.out + chunk_table_offset(n))[c] =
+            reinterpret_cast<const uint64_t *>(a.in + 64)[c];
+      }
+    }
+  }
+  // header, padding, outliers
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    uint64_t *hout = reinterpret_cast<uint64_t *>(a.out);
+    hout[0] = (h0 & ~0xFFFFFFFFull) | kMagic;
+#pragma unroll
+    for (int i = 1; i < 8; i++) hout[i] = hd[i];
+    const uint64_t ct = chunk_table_offset(n), ce = ct + 8 * nch, oo = outlier_offset(n);
+    for (uint64_t x = 64 + 4 * n; x < ct; x++) a.out[x] = 0;
+    for (uint64_t x = ce; x < oo; x++) a.out[x] = 0;
+    *a.out_bytes = oo + k * s;
+  }
+  const uint64_t words = k * s / 4;
+  const uint32_t *src = reinterpret_cast<const uint32_t *>(a.in + align16(pl + payload));
+  uint32_t *dst = reinterpret_cast<uint32_t *>(a.out + outlier_offset(n));
+  for (uint64_t i = (uint64_t)blockIdx.x * kBlock + threadIdx.x; i < words;
+       i += (uint64_t)gridDim.x * kBlock)
+    dst[i] = src[i];
+}
+
+__global__ void k_clear_pk(uint64_t *p, uint64_t count) {
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count;
+       i += (uint64_t)gridDim.x * blockDim.x)
+    p[i] = 0;
+}
+
+// Workspace of lcq_pack: status word, group sums, record sizes, metadata.
+uint64_t pk_sizes_off() { return align16(256 + 8 * kMaxGroups); }
+uint64_t pk_meta_off(uint64_t C) { return align16(pk_sizes_off() + 4 * C); }
+
+lcq_status check_launch_pk() { return hipGetLastError() == hipSuccess ? LCQ_OK : LCQ_ERR_HIP; }
+
+// Call epochs tag the status word (as for the decoders); seeded from the
+// clock so a workspace left over from another process cannot match.
+std::atomic<uint64_t> g_pk_epoch{
+    ((uint64_t)std::chrono::steady_clock::now().time_since_epoch().count() ^ 0x5A5A5A5A5ull) &
+    0xFFFFFFFFFFFull};
+
+}  // namespace
+
+extern "C" {
+
+uint64_t lcq_pack_max_bytes(lcq_dtype t, uint64_t n) {
+  if ((t != LCQ_F32 && t != LCQ_F64) || n > LCQ_MAX_N) return 0;
+  const uint64_t s = t == LCQ_F64 ? 8 : 4, C = n_chunks(n);
+  return align16(packed_payload_offset(C) + C * record_bytes(kChunk, 32, 1)) + s * n;
+}
+
+uint64_t lcq_pack_workspace_bytes(lcq_dtype t, uint64_t n) {
+  if ((t != LCQ_F32 && t != LCQ_F64) || n > LCQ_MAX_N) return 0;
+  return pk_meta_off(n_chunks(n)) + 4 * n_chunks(n);
+}
+
+lcq_status lcq_pack(lcq_dtype t, const void *d_stream, uint64_t stream_bytes, uint64_t n,
+                    void *d_packed, uint64_t packed_cap, uint64_t *d_packed_bytes, void *d_ws,
+                    uint64_t ws_bytes, hipStream_t stream) {
+  if (t != LCQ_F32 && t != LCQ_F64) return LCQ_ERR_ARG;
+  if (n > LCQ_MAX_N) return LCQ_ERR_ARG;
+  if (!d_stream || !d_packed || !d_packed_bytes || !d_ws) return LCQ_ERR_ARG;
+  if (!aligned16(d_stream) || !aligned16(d_packed) || !aligned16(d_ws) ||
+      ((uintptr_t)d_packed_bytes & 7u))
+    return LCQ_ERR_ARG;
+  if (stream_bytes < outlier_offset(n)) return LCQ_ERR_STREAM;
+  if (packed_cap < lcq_pack_max_bytes(t, n)) return LCQ_ERR_CAPACITY;
+  if (ws_bytes < lcq_pack_workspace_bytes(t, n)) return LCQ_ERR_CAPACITY;
+  const uint64_t C = n_chunks(n);
+  const uint64_t ntiles = (C + kWaves - 1) / kWaves;
+  uint8_t *ws = static_cast<uint8_t *>(d_ws);
+  PackArgs a{};
+  a.in = static_cast<const uint8_t *>(d_stream);
+  a.in_bytes = stream_bytes;
+  a.n = n;
+  a.out = static_cast<uint8_t *>(d_packed);
+  a.out_bytes = d_packed_bytes;
+  a.sizes = reinterpret_cast<uint32_t *>(ws + pk_sizes_off());
+  a.meta = reinterpret_cast<uint32_t *>(ws + pk_meta_off(C));
+  a.group = reinterpret_cast<unsigned long long *>(ws + 256);
+  a.tiles_per_group = tiles_per_group(ntiles, kPackTile / kChunk);
+  a.chunks_per_group = a.tiles_per_group * (kPackTile / kChunk);
+  a.ngroups = std::max<uint64_t>(1, (ntiles + a.tiles_per_group - 1) / a.tiles_per_group);
+  a.status = reinterpret_cast<unsigned long long *>(ws);
+  a.epoch = g_pk_epoch.fetch_add(1) + 1;
+  a.dtype = (int)t;
+  const unsigned cg = (unsigned)std::min<uint64_t>((a.ngroups + kBlock - 1) / kBlock, 1024);
+  hipLaunchKernelGGL(k_clear_pk, dim3(cg), dim3(kBlock), 0, stream,
+                     reinterpret_cast<uint64_t *>(a.group), a.ngroups);
+  if (ntiles) hipLaunchKernelGGL(k_pack_plan, dim3((unsigned)ntiles), dim3(kBlock), 0, stream, a);
+  hipLaunchKernelGGL(k_pack_scan, dim3((unsigned)a.ngroups), dim3(kBlock), 0, stream, a);
+  if (ntiles) hipLaunchKernelGGL(k_pack_write, dim3((unsigned)ntiles), dim3(kBlock), 0, stream, a);
+  return check_launch_pk();
+}
+
+lcq_status lcq_unpack(lcq_dtype t, const void *d_packed, uint64_t packed_bytes, uint64_t n,
+                      void *d_stream, uint64_t stream_cap, uint64_t *d_stream_bytes, void *d_ws,
+                      uint64_t ws_bytes, hipStream_t stream) {
+  if (t != LCQ_F32 && t != LCQ_F64) return LCQ_ERR_ARG;
+  if (n > LCQ_MAX_N) return LCQ_ERR_ARG;
+  if (!d_packed || !d_stream || !d_stream_bytes || !d_ws) return LCQ_ERR_ARG;
+  if (!aligned16(d_packed) || !aligned16(d_stream) || !aligned16(d_ws) ||
+      ((uintptr_t)d_stream_bytes & 7u))
+    return LCQ_ERR_ARG;
+  if (ws_bytes < 8) return LCQ_ERR_CAPACITY;
+  const uint64_t C = n_chunks(n);
+  if (packed_bytes < packed_payload_offset(C)) return LCQ_ERR_STREAM;
+  if (stream_cap < outlier_offset(n)) return LCQ_ERR_CAPACITY;
+  UnpackArgs a{};
+  a.in = static_cast<const uint8_t *>(d_packed);
+  a.in_bytes = packed_bytes;
+  a.n = n;
+  a.out = static_cast<uint8_t *>(d_stream);
+  a.out_cap = stream_cap;
+  a.out_bytes = d_stream_bytes;
+  a.status = static_cast<unsigned long long *>(d_ws);
+  a.epoch = g_pk_epoch.fetch_add(1) + 1;
+  a.dtype = (int)t;
+  const uint64_t ntiles = std::max<uint64_t>(1, (C + kWaves - 1) / kWaves);
+  hipLaunchKernelGGL(k_unpack, dim3((unsigned)ntiles), dim3(kBlock), 0, stream, a);
+  return check_launch_pk();
+}
+
+}  // extern "C"
