@@ -1,8 +1,10 @@
-"""Parity at the single-field benchmark's full size: the 512^3 float32 GRF
-(and its lognormal variant for REL), eb = 1e-3.  The oracle finishes these
-in seconds, so whole streams and decodes are compared, under every
-quantize / dequantize launch variant the tuner can pick (the benchmark times
-whichever wins), and for the in-line layout."""
+"""Parity at the full single-field sizes: the 512^3 float32 GRF (and its
+lognormal variant for REL) at every bound of that workload, and the 384^3
+float64 GRF with a 2^20-value adversarial bin-border slice (ABS / NOA at
+1e-6, REL at 1e-4).  The oracle finishes these in seconds, so whole streams
+and decodes are compared -- at eb = 1e-3 under every quantize / dequantize
+launch variant the tuner can pick (the benchmark times whichever wins), and
+for the in-line layout."""
 import numpy as np
 import pytest
 
@@ -68,3 +70,45 @@ def test_fullsize_inline(fields, q):
     assert lcq.stream_status(ws) == 0
     ref = bits(O.dequantize_inline(st_o, np.float32, x.size))
     assert first_diff(bits(dec.cpu().numpy()), ref) is None
+
+
+def _compare_default(q, x, eb, label):
+    import torch
+    import paper_2407_15037_amd as lcq
+    announce("fullsize", label, q, x.dtype, x.size, eb)
+    st_o = O.quantize(q, x, eb)
+    xt = torch.from_numpy(x).cuda()
+    buf, nb = lcq.quantize(xt, q, eb)
+    size = int(nb.item())
+    diff = first_diff(buf[:size].cpu().numpy(), st_o)
+    assert diff is None, f"{label} {q} eb={eb}: stream {diff}"
+    ws = torch.zeros(64, dtype=torch.uint8, device="cuda")
+    dec = lcq.dequantize(buf, xt.dtype, x.size, stream_bytes=size, ws=ws)
+    assert lcq.stream_status(ws) == 0
+    diff = first_diff(bits(dec.cpu().numpy()), bits(O.dequantize(st_o, x.dtype, x.size)))
+    assert diff is None, f"{label} {q} eb={eb}: decode {diff}"
+    return st_o
+
+
+@pytest.mark.parametrize("q,eb", [("abs", 1e-2), ("abs", 1e-4), ("noa", 1e-2), ("noa", 1e-4),
+                                  ("rel", 1e-2)])
+def test_fullsize_other_bounds(fields, q, eb):
+    _compare_default(q, fields[q], eb, "grf512 f32")
+
+
+@pytest.fixture(scope="module")
+def fields64():
+    x, xr = synth.f64_grid_inputs()
+    return {"abs": x, "noa": x, "rel": xr}
+
+
+@pytest.mark.parametrize("q,eb", [("abs", 1e-6), ("noa", 1e-6), ("rel", 1e-4)])
+def test_fullsize_f64_grid_with_adversarial_slice(fields64, q, eb):
+    x = fields64[q]
+    st = _compare_default(q, x, eb, "grf384 f64")
+    k = int(st[16:24].view(np.uint64)[0])
+    # the bin-border slice sends values through the verify-and-fallback path
+    # (ABS; REL lower side) beyond the injected specials
+    nsp = synth.n_specials(x.size, 1e-4)
+    if q != "noa":
+        assert k > nsp, (q, k, nsp)
