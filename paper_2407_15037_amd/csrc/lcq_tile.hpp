@@ -502,7 +502,12 @@ __device__ void block_minmax(const T *in, uint64_t begin, uint64_t end, T &lo, T
   for (; i + (U - 1) * kBlock < ve; i += U * kBlock) {
     V v[U];
 #pragma unroll
-    for (int u = 0; u < U; u++) v[u] = vin[i + u * kBlock];
+    for (int u = 0; u < U; u++) {
+      // streamed once here: non-temporal loads
+      typedef T nv __attribute__((ext_vector_type(16 / sizeof(T))));
+      const nv t = __builtin_nontemporal_load(reinterpret_cast<const nv *>(vin + i + u * kBlock));
+      __builtin_memcpy(&v[u], &t, sizeof(V));
+    }
 #pragma unroll
     for (int u = 0; u < U; u++) {
       T x[W];
