@@ -286,8 +286,9 @@ def run_ablation(args, x, xr, plain):
     """The paper's two ablations (section 6) on the plain step's fields, same
     kernels and launch shape: ABS with vs without the double-check, and REL
     with the section 3.2 approximations vs the device math library's
-    log2 / exp2.  Event-timed like the plain ops; the unchecked ABS decode is
-    counted against the bound on the device."""
+    log2 / exp2, each pair timed interleaved (events around the per-value
+    kernels, as for the plain ops); the unchecked ABS decode is counted
+    against the bound on the device."""
     import numpy as np
     import torch
     import paper_2407_15037_amd as lcq
@@ -301,29 +302,44 @@ def run_ablation(args, x, xr, plain):
     nb = torch.zeros(1, dtype=torch.int64, device=dev)
     ws = torch.empty(lcq.workspace_bytes("rel", torch.float32, n), dtype=torch.uint8, device=dev)
     out = torch.empty(n, dtype=torch.float32, device=dev)
-    reps = max(3, args.steps // 2)
+    reps = max(5, args.steps // 2)
 
-    def timed(fn):
-        ts = []
-        for r in range(reps + 1):
-            e0 = torch.cuda.Event(enable_timing=True)
-            e1 = torch.cuda.Event(enable_timing=True)
-            e0.record(); e1.record()
-            lcq.profile_events(e0, e1)
-            fn()
-            lcq.profile_events(None, None)
-            torch.cuda.synchronize()
-            if r:
-                ts.append(e0.elapsed_time(e1) * 1e3)
-        return sum(ts) / len(ts)
+    def timed_once(fn):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(); e1.record()
+        lcq.profile_events(e0, e1)
+        fn()
+        lcq.profile_events(None, None)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) * 1e3
 
     res = {}
-    for kind, xt in (("abs_unchecked", xa), ("rel_libm", xl)):
-        tq = timed(lambda: lcq.quantize_ablation(xt, kind, eb, out=buf, nbytes=nb, ws=ws))
-        size = int(nb.item())
-        td = timed(lambda: lcq.dequantize_ablation(buf, kind, torch.float32, n, stream_bytes=size,
-                                                   out=out, ws=ws))
-        k = header_k(buf)
+    for kind, base_q, xt in (("abs_unchecked", "abs", xa), ("rel_libm", "rel", xl)):
+        # the guaranteed quantizer and its ablation, interleaved rep by rep
+        # so that both see the same clocks and memory state
+        tq = {base_q: [], kind: []}
+        td = {base_q: [], kind: []}
+        for r in range(reps + 1):
+            for which in (base_q, kind):
+                if which == base_q:
+                    tq_ = timed_once(lambda: lcq.quantize(xt, base_q, eb, out=buf, nbytes=nb, ws=ws))
+                else:
+                    tq_ = timed_once(lambda: lcq.quantize_ablation(xt, kind, eb, out=buf, nbytes=nb,
+                                                                    ws=ws))
+                size = int(nb.item())
+                if which == base_q:
+                    td_ = timed_once(lambda: lcq.dequantize(buf, torch.float32, n, stream_bytes=size,
+                                                            out=out, ws=ws))
+                else:
+                    td_ = timed_once(lambda: lcq.dequantize_ablation(buf, kind, torch.float32, n,
+                                                                     stream_bytes=size, out=out,
+                                                                     ws=ws))
+                if r:
+                    tq[which].append(tq_)
+                    td[which].append(td_)
+        avg = lambda v: sum(v) / len(v)
+        k = header_k(buf)  # the ablation's stream is the last one written
         fin = torch.isfinite(xt)
         if kind == "abs_unchecked":
             e = np.float32(eb)  # the float32 bound: largest float32 not above eb
@@ -332,22 +348,20 @@ def run_ablation(args, x, xr, plain):
             e = float(e)
             err = (xt.double() - out.double()).abs()
             viol = int(((err > e) & fin).sum().item())
-            base = plain["kern"]
             res["abs"] = {
-                "protected_quantize_us": round(base["quantize_abs"]["avg_us"], 2),
-                "unchecked_quantize_us": round(tq, 2),
-                "check_cost_pct": round(100.0 * (base["quantize_abs"]["avg_us"] - tq) / tq, 2),
-                "protected_dequantize_us": round(base["dequantize_abs"]["avg_us"], 2),
-                "unchecked_dequantize_us": round(td, 2),
+                "protected_quantize_us": round(avg(tq["abs"]), 2),
+                "unchecked_quantize_us": round(avg(tq[kind]), 2),
+                "check_cost_pct": round(100.0 * (avg(tq["abs"]) - avg(tq[kind])) / avg(tq[kind]), 2),
+                "protected_dequantize_us": round(avg(td["abs"]), 2),
+                "unchecked_dequantize_us": round(avg(td[kind]), 2),
                 "unchecked_outliers": k, "protected_outliers": plain["ks"]["abs"],
                 "unchecked_values_outside_bound": viol}
         else:
-            base = plain["kern"]
             res["rel"] = {
-                "mitchell_quantize_us": round(base["quantize_rel"]["avg_us"], 2),
-                "libm_quantize_us": round(tq, 2),
-                "mitchell_dequantize_us": round(base["dequantize_rel"]["avg_us"], 2),
-                "libm_dequantize_us": round(td, 2),
+                "mitchell_quantize_us": round(avg(tq["rel"]), 2),
+                "libm_quantize_us": round(avg(tq[kind]), 2),
+                "mitchell_dequantize_us": round(avg(td["rel"]), 2),
+                "libm_dequantize_us": round(avg(td[kind]), 2),
                 "mitchell_outliers": plain["ks"]["rel"], "libm_outliers": k}
             codes = buf[64: 64 + 4 * ABL_SAMPLE].view(torch.int32).cpu().numpy().copy()
     del xa, xl, buf, ws, out
