@@ -542,13 +542,18 @@ def run_serving(args):
         "queue_p99_ms": round(float(np.percentile(qwait, 99)), 4),
         "outputs_equal_alone": f"{ok}/{len(reqs)}",
     }
+    # the smallest payloads' expected streams go to the CPU leg, which checks
+    # them against the oracle
+    small = sorted(range(len(pool)), key=lambda i: pool[i]["spec"]["n"])[:16]
+    sample = [(pool[i]["spec"], pool[i]["x"].cpu().numpy(), pool[i]["stream"].cpu().numpy())
+              for i in small]
     del arena, pool, reqs
     torch.cuda.empty_cache()
-    return res
+    return res, sample
 
 
 # ------------------------------------------------------------ CPU baseline --
-def cpu_baseline_leg(x, xr, eb, plain, batch_sample, abl_codes=None):
+def cpu_baseline_leg(x, xr, eb, plain, batch_sample, abl_codes=None, serve_sample=()):
     """The CPU oracle, single thread, timed on the plain step's three fields
     (quantize + dequantize each); its streams also check the GPU's."""
     import numpy as np
@@ -569,6 +574,10 @@ def cpu_baseline_leg(x, xr, eb, plain, batch_sample, abl_codes=None):
     bparity = 0
     for sp, xv, gs in batch_sample:
         bparity += int(np.array_equal(oracle.quantize(sp["q"], xv, sp["eb"]), gs))
+    if serve_sample:
+        ok = sum(int(np.array_equal(oracle.quantize(sp["q"], xv, sp["eb"]), gs))
+                 for sp, xv, gs in serve_sample)
+        parity["serving_pool_sample"] = f"{ok}/{len(serve_sample)}"
     if abl_codes is not None:
         # REL-libm ablation: the host library's codes for the first values of
         # the field vs the GPU's (REL codes depend on the value alone)
@@ -673,10 +682,11 @@ def main():
     sample = []
     if not args.no_batched:
         result["batched"], sample = run_batched(args)
+    serve_sample = []
     if not args.no_serving:
-        result["serving"] = run_serving(args)
+        result["serving"], serve_sample = run_serving(args)
     if not args.no_cpu_baseline:
-        base, parity, bpar = cpu_baseline_leg(x, xr, args.eb, plain, sample, abl_codes)
+        base, parity, bpar = cpu_baseline_leg(x, xr, args.eb, plain, sample, abl_codes, serve_sample)
         result["cpu_baseline"] = base
         result["parity_vs_oracle"] = {"plain": parity, "batched_sample": bpar}
     print(json.dumps(result), flush=True)
