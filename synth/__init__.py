@@ -104,9 +104,9 @@ def plain_step_inputs(N=512, eb=1e-3, seed=1, rel_seed=11, frac=1e-4):
 def f64_grid_inputs(N=384, abs_eb=1e-6, rel_eb=1e-4, seed=2, rel_seed=12, frac=1e-4,
                     adversarial=1 << 20, adv_seed=22):
     """The float64 single-field workload: an N^3 Gaussian random field with
-    a fraction `frac` of special values and its last `adversarial` values
-    replaced by ABS bin-border values for abs_eb; the REL variant likewise
-    with REL bin-border values for rel_eb."""
+    a fraction `frac` of special values and the `adversarial` contiguous
+    values from n/2 on replaced by ABS bin-border values for abs_eb; the REL
+    variant likewise with REL bin-border values for rel_eb."""
     g = grf_3d(N, seed, dtype=np.float64)
     nsp = n_specials(g.size, frac)
     x, _, _ = inject_specials(g.copy(), nsp, seed + 1000, abs_eb)
@@ -114,8 +114,9 @@ def f64_grid_inputs(N=384, abs_eb=1e-6, rel_eb=1e-4, seed=2, rel_seed=12, frac=1
     del g
     xr, _, _ = inject_specials(xr, nsp, rel_seed + 1000, rel_eb)
     if adversarial:
-        x[-adversarial:] = adversarial_abs(adversarial, abs_eb, adv_seed, np.float64)
-        xr[-adversarial:] = adversarial_rel(adversarial, rel_eb, adv_seed + 1, np.float64)
+        h = x.size // 2
+        x[h: h + adversarial] = adversarial_abs(adversarial, abs_eb, adv_seed, np.float64)
+        xr[h: h + adversarial] = adversarial_rel(adversarial, rel_eb, adv_seed + 1, np.float64)
     return x, xr
 
 
