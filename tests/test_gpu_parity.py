@@ -237,3 +237,18 @@ def test_status_word_ignores_workspace_contents():
                 else:
                     lcq.dequantize(buf, torch.float32, x.size, ws=ws)
                 assert lcq.stream_status(ws) == (3 if broken else 0)
+
+
+@pytest.mark.parametrize("q", ["abs", "noa", "rel"])
+def test_parity_sines_2_20(q):
+    """The small 1-D case at its full size: 2^20 float32 values from the sum
+    of 8 sines plus noise, 0.1 % special values (NaN, +-INF, +-0, denormals,
+    half-bin neighbours, bins beyond 2^30), eb = 1e-3; streams and decodes
+    compared whole."""
+    n = 1 << 20
+    x = synth.sines_1d(n, 1, dtype=np.float32)
+    x, _, _ = synth.inject_specials(x, synth.n_specials(n, 1e-3), 2, 1e-3)
+    if q == "rel":
+        x = synth.rel_variant(np.nan_to_num(x.astype(np.float64)), 3, dtype=np.float32)
+        x, _, _ = synth.inject_specials(x, synth.n_specials(n, 1e-3), 4, 1e-3)
+    _parity(q, x, 1e-3, "sines 2^20")
