@@ -619,6 +619,14 @@ __device__ __forceinline__ void store_flag_word(uint8_t *flags, uint64_t b, uint
   }
 }
 
+// Vector types for non-temporal 128-bit accesses (every stream here is
+// touched once).
+template <typename T> struct NtVec;
+template <> struct NtVec<float> { typedef float type __attribute__((ext_vector_type(4))); };
+template <> struct NtVec<double> { typedef double type __attribute__((ext_vector_type(2))); };
+typedef uint32_t nt_u4 __attribute__((ext_vector_type(4)));
+typedef uint64_t nt_u2 __attribute__((ext_vector_type(2)));
+
 // Quantize one tile in the in-line layout: a pure map, no scan.
 template <typename T, int Q, int SLOTS>
 __device__ void quant_tile_inline(const QField<T> &f, uint64_t tile) {
@@ -639,7 +647,9 @@ __device__ void quant_tile_inline(const QField<T> &f, uint64_t tile) {
   for (int j = 0; j < SLOTS; j++) {
     const uint64_t i0 = base + ((uint64_t)j * kBlock + tid) * W;
     if (i0 + W <= n) {
-      v[j] = *reinterpret_cast<const V *>(f.in + i0);
+      const typename NtVec<T>::type t =
+          __builtin_nontemporal_load(reinterpret_cast<const typename NtVec<T>::type *>(f.in + i0));
+      __builtin_memcpy(&v[j], &t, sizeof(V));
     } else {
       T tmp[W];
 #pragma unroll
@@ -664,9 +674,11 @@ __device__ void quant_tile_inline(const QField<T> &f, uint64_t tile) {
     }
     if (i0 + W <= n) {
       if constexpr (sizeof(T) == 4) {
-        *reinterpret_cast<uint4 *>(words + i0) = make_uint4(w[0], w[1], w[2], w[3]);
+        const nt_u4 o = {(uint32_t)w[0], (uint32_t)w[1], (uint32_t)w[2], (uint32_t)w[3]};
+        __builtin_nontemporal_store(o, reinterpret_cast<nt_u4 *>(words + i0));
       } else {
-        *reinterpret_cast<ulonglong2 *>(words + i0) = make_ulonglong2(w[0], w[1]);
+        const nt_u2 o = {(uint64_t)w[0], (uint64_t)w[1]};
+        __builtin_nontemporal_store(o, reinterpret_cast<nt_u2 *>(words + i0));
       }
     } else {
 #pragma unroll
@@ -705,10 +717,10 @@ __device__ void dequant_tile_inline(const uint8_t *stream, uint64_t n, T step, b
     U w[W];
     if (i0 + W <= n) {
       if constexpr (sizeof(T) == 4) {
-        const uint4 q4 = *reinterpret_cast<const uint4 *>(words + i0);
+        const nt_u4 q4 = __builtin_nontemporal_load(reinterpret_cast<const nt_u4 *>(words + i0));
         w[0] = q4.x; w[1] = q4.y; w[2] = q4.z; w[3] = q4.w;
       } else {
-        const ulonglong2 q2 = *reinterpret_cast<const ulonglong2 *>(words + i0);
+        const nt_u2 q2 = __builtin_nontemporal_load(reinterpret_cast<const nt_u2 *>(words + i0));
         w[0] = q2.x; w[1] = q2.y;
       }
     } else {
@@ -722,9 +734,9 @@ __device__ void dequant_tile_inline(const uint8_t *stream, uint64_t n, T step, b
     for (int e = 0; e < W; e++)
       y[e] = ((m >> e) & 1u) ? from_bits(w[e]) : decode<T>((int32_t)(uint32_t)w[e], step, rel);
     if (i0 + W <= n) {
-      V o;
+      typename NtVec<T>::type o;
       __builtin_memcpy(&o, y, sizeof(V));
-      *reinterpret_cast<V *>(out + i0) = o;
+      __builtin_nontemporal_store(o, reinterpret_cast<typename NtVec<T>::type *>(out + i0));
     } else {
 #pragma unroll
       for (int e = 0; e < W; e++)
