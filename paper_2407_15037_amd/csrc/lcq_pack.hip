@@ -368,14 +368,19 @@ __global__ __launch_bounds__(kBlock) void k_unpack(UnpackArgs a) {
   if (blockIdx.x == 0 && threadIdx.x == 0)
     report_status(a.status, tag, bad ? LCQ_ERR_STREAM : LCQ_OK);
   if (bad) return;
+  __shared__ uint32_t s_w[kWaves][kChunk];  // the record's packed words
   const uint64_t c = (uint64_t)blockIdx.x * kWaves + wave;
-  if (c < nch) {
+  const bool act = c < nch;  // uniform over the wavefront
+  bool ok = false;
+  unsigned w = 0, mode = 0, hb = 0;
+  uint64_t len = 0;
+  const uint8_t *rec = a.in + pl;
+  if (act) {
     const uint64_t off = offs[c], nxt = offs[c + 1];
-    const uint64_t len = min<uint64_t>(kChunk, n - c * kChunk);
-    bool ok = off <= payload && payload - off >= 16;
-    unsigned w = 0, mode = 0, hb = 0;
-    const uint8_t *rec = a.in + pl + (ok ? off : 0);
+    len = min<uint64_t>(kChunk, n - c * kChunk);
+    ok = off <= payload && payload - off >= 16;
     if (ok) {
+      rec = a.in + pl + off;
       const uint32_t h = reinterpret_cast<const uint32_t *>(rec)[0];
       w = h & 0xFF;
       mode = (h >> 8) & 0xFF;
@@ -383,58 +388,69 @@ __global__ __launch_bounds__(kBlock) void k_unpack(UnpackArgs a) {
       ok = w <= 32 && mode <= 1 && hb <= 1 && payload - off >= record_bytes(len, w, hb) &&
            nxt == off + record_bytes(len, w, hb);
     }
-    if (!ok) {
-      if (lane == 0) report_status(a.status, tag, LCQ_ERR_STREAM);
-    } else {
-      const uint32_t *pw = reinterpret_cast<const uint32_t *>(rec + 16 + (hb ? 128 : 0));
-      const uint32_t mask = w == 32 ? 0xFFFFFFFFu : ((1u << w) - 1u);
-      const uint64_t nbits = len * w;
-      int32_t *codes = reinterpret_cast<int32_t *>(a.out + 64);
-      uint32_t carry = 0;
+    if (!ok && lane == 0) report_status(a.status, tag, LCQ_ERR_STREAM);
+  }
+  // stage the record's packed words with 128-bit loads (the packed area is
+  // a whole number of 16-byte units inside the record)
+  const uint64_t nbits = ok ? len * w : 0;
+  const unsigned nwords = (unsigned)((nbits + 31) / 32);
+  if (ok) {
+    const nt_u4 *pw4 = reinterpret_cast<const nt_u4 *>(rec + 16 + (hb ? 128 : 0));
+    for (unsigned t = lane; 4 * t < nwords; t += 64) {
+      const nt_u4 v = __builtin_nontemporal_load(pw4 + t);
+      s_w[wave][4 * t] = v.x;
+      s_w[wave][4 * t + 1] = v.y;
+      s_w[wave][4 * t + 2] = v.z;
+      s_w[wave][4 * t + 3] = v.w;
+    }
+  }
+  __syncthreads();
+  if (ok) {
+    const uint32_t mask = w == 32 ? 0xFFFFFFFFu : ((1u << w) - 1u);
+    int32_t *codes = reinterpret_cast<int32_t *>(a.out + 64);
+    uint32_t carry = 0;
 #pragma unroll
-      for (int j = 0; j < kCSub; j++) {
-        const uint64_t i0 = chunk_value<kCW>(c, j, lane);
-        const uint64_t l0 = i0 - c * kChunk;  // position in the chunk
-        uint32_t v[kCW];
+    for (int j = 0; j < kCSub; j++) {
+      const uint64_t i0 = chunk_value<kCW>(c, j, lane);
+      const uint64_t l0 = i0 - c * kChunk;  // position in the chunk
+      uint32_t v[kCW];
 #pragma unroll
-        for (int e = 0; e < kCW; e++) {
-          uint32_t z = 0;
+      for (int e = 0; e < kCW; e++) {
+        uint32_t z = 0;
+        if (w && l0 + e < len) {
           const uint64_t b = (l0 + e) * w;
-          if (w && l0 + e < len) {
-            const uint64_t q = b >> 5;
-            const unsigned sh = (unsigned)(b & 31);
-            uint64_t pair = pw[q];
-            if (sh + w > 32 && 32 * (q + 1) < nbits) pair |= (uint64_t)pw[q + 1] << 32;
-            z = (uint32_t)(pair >> sh) & mask;
-          }
-          v[e] = unzigzag(z);
+          const unsigned q = (unsigned)(b >> 5), sh = (unsigned)(b & 31);
+          uint64_t pair = s_w[wave][q];
+          if (sh + w > 32 && q + 1 < nwords) pair |= (uint64_t)s_w[wave][q + 1] << 32;
+          z = (uint32_t)(pair >> sh) & mask;
         }
-        if (mode) {
-          // prefix sum over the chunk in value order (mod 2^32)
+        v[e] = unzigzag(z);
+      }
+      if (mode) {
+        // prefix sum over the chunk in value order (mod 2^32)
 #pragma unroll
-          for (int e = 1; e < kCW; e++) v[e] += v[e - 1];
-          uint32_t incl = v[kCW - 1];
+        for (int e = 1; e < kCW; e++) v[e] += v[e - 1];
+        uint32_t incl = v[kCW - 1];
 #pragma unroll
-          for (int o = 1; o < 64; o <<= 1) {
-            const uint32_t t = __shfl_up(incl, o, 64);
-            if (lane >= o) incl += t;
-          }
-          const uint32_t excl = incl - v[kCW - 1] + carry;
-#pragma unroll
-          for (int e = 0; e < kCW; e++) v[e] += excl;
-          carry += __shfl(incl, 63, 64);
+        for (int o = 1; o < 64; o <<= 1) {
+          const uint32_t t = __shfl_up(incl, o, 64);
+          if (lane >= o) incl += t;
         }
-        unsigned fl = 0;
-        if (hb) fl = (rec[16 + l0 / 8] >> (l0 % 8)) & 0xFu;
-        int32_t out[kCW];
+        const uint32_t excl = incl - v[kCW - 1] + carry;
 #pragma unroll
-        for (int e = 0; e < kCW; e++) out[e] = ((fl >> e) & 1u) ? kSent : (int32_t)v[e];
-        store_codes<kCW>(codes, i0, n, out);
+        for (int e = 0; e < kCW; e++) v[e] += excl;
+        carry += __shfl(incl, 63, 64);
       }
-      if (lane == 0) {
-        reinterpret_cast<uint64_t *>(a.out + chunk_table_offset(n))[c] =
-            reinterpret_cast<const uint64_t *>(a.in + 64)[c];
-      }
+      unsigned fl = 0;
+      if (hb) fl = (rec[16 + l0 / 8] >> (l0 % 8)) & 0xFu;
+      int32_t out[kCW];
+#pragma unroll
+      for (int e = 0; e < kCW; e++) out[e] = ((fl >> e) & 1u) ? kSent : (int32_t)v[e];
+      store_codes<kCW>(codes, i0, n, out);
+    }
+    if (lane == 0) {
+      reinterpret_cast<uint64_t *>(a.out + chunk_table_offset(n))[c] =
+          reinterpret_cast<const uint64_t *>(a.in + 64)[c];
     }
   }
   // header, padding, outliers
