@@ -542,6 +542,19 @@ def run_serving(args):
         "queue_p99_ms": round(float(np.percentile(qwait, 99)), 4),
         "outputs_equal_alone": f"{ok}/{len(reqs)}",
     }
+    # saturation: the first requests of the same mix all arriving at once
+    # (closed queue), so the loop admits them as fast as the budget and the
+    # streams allow; every output still compared with the request alone
+    m = min(len(reqs), args.saturation_requests)
+    sat = [dict(r, arrival_ns=0) for r in reqs[:m]]
+    sat_bytes = sum(r["n"] * (8 if r["dtype"] == torch.float64 else 4) if r["op"] == "quantize"
+                    else r["in_bytes"] for r in sat)
+    log(f"serving saturation: {m} requests at once")
+    rs = serve.run(sat, n_streams=args.streams, arena=arena)
+    span = (rs["done_ns"].max() - rs["admit_ns"].min()) / 1e9
+    res["saturated"] = {
+        "requests": m, "GBs": round(sat_bytes / span / 1e9, 1),
+        "outputs_equal_alone": f"{int(np.sum((rs['status'] == 0) & (rs['mismatched'] == 0)))}/{m}"}
     # the smallest payloads' expected streams go to the CPU leg, which checks
     # them against the oracle
     small = sorted(range(len(pool)), key=lambda i: pool[i]["spec"]["n"])[:16]
@@ -617,6 +630,7 @@ def main():
     ap.add_argument("--serve-seconds", type=float, default=60.0)
     ap.add_argument("--budget-gb", type=float, default=64.0)
     ap.add_argument("--streams", type=int, default=8)
+    ap.add_argument("--saturation-requests", type=int, default=20000)
     ap.add_argument("--calib-copy", action="store_true",
                     help="first run three 512 MiB device-to-device copies (a plain copy "
                          "kernel of known size, to scale hardware byte counters)")
