@@ -636,9 +636,8 @@ def main():
                          "kernel of known size, to scale hardware byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build measures one GPU; the quantizer path has no "
-                          "multi-GPU form here (DESIGN.md describes how it would shard)",
-                          "n_gpus": args.gpus}))
+        print(json.dumps({"error": "one GPU only: the quantizer path has no multi-GPU form "
+                          "(sharding is described, not implemented)", "n_gpus": args.gpus}))
         sys.exit(2)
 
     import torch
