@@ -13,7 +13,7 @@ __all__ = ["ABS", "REL", "NOA", "F32", "F64", "LCQError", "lib", "max_stream_byt
            "set_lookback_spin", "tune_variants", "tune_set", "tune_get",
            "inline_stream_bytes", "inline_workspace_bytes", "quantize_inline",
            "quantize_ablation", "dequantize_ablation", "ABL_ABS_UNCHECKED", "ABL_REL_LIBM",
-           "pack_max_bytes", "pack_workspace_bytes", "pack", "unpack", "dequantize_inline", "SO_PATH"]
+           "pack_max_bytes", "pack_workspace_bytes", "pack", "unpack", "compress", "decompress", "dequantize_inline", "SO_PATH"]
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 SO_PATH = os.path.join(HERE, "liblcq.so")
@@ -252,6 +252,27 @@ def unpack(packed_buf, dtype, n, *, packed_bytes=None, out=None, nbytes=None, ws
                          _ptr(ws), ws.numel(), _stream_handle(stream))
     _check(st, "lcq_unpack")
     return out, nbytes
+
+
+def compress(x, q, eb, *, stream=None):
+    """Quantize then pack: the guaranteed quantizer followed by the lossless
+    packing stage.  Returns the packed stream as a uint8 CUDA tensor of
+    exactly its size (one host synchronisation to read that size)."""
+    buf, nb = quantize(x, q, eb, stream=stream)
+    pk, pnb = pack(buf, x.dtype, x.numel(), stream=stream)
+    return pk[: int(pnb.item())]
+
+
+def decompress(packed, dtype, n, *, stream=None):
+    """Unpack then dequantize a compress() result; raises LCQError if either
+    stage finds the stream inconsistent."""
+    import torch
+    ws = torch.zeros(64, dtype=torch.uint8, device=packed.device)
+    st, nb = unpack(packed, dtype, n, ws=ws, stream=stream)
+    _check(stream_status(ws, stream), "lcq_unpack")
+    out = dequantize(st, dtype, n, ws=ws, stream=stream)
+    _check(stream_status(ws, stream), "lcq_dequantize")
+    return out
 
 
 def inline_stream_bytes(dtype, n):

@@ -112,3 +112,38 @@ def test_fullsize_f64_grid_with_adversarial_slice(fields64, q, eb):
     nsp = synth.n_specials(x.size, 1e-4)
     if q != "noa":
         assert k > nsp, (q, k, nsp)
+
+
+def test_fullsize_abs_unchecked_ablation(fields):
+    """The section 6 ablation without the double-check is deterministic IEEE
+    arithmetic too: its full-size stream and decode equal the oracle's."""
+    import torch
+    import paper_2407_15037_amd as lcq
+    x = fields["abs"]
+    announce("fullsize ablation abs_unchecked", x.size)
+    st_o = O.quantize("abs_unchecked", x, EB)
+    xt = torch.from_numpy(x).cuda()
+    buf, nb = lcq.quantize_ablation(xt, "abs_unchecked", EB)
+    size = int(nb.item())
+    assert first_diff(buf[:size].cpu().numpy(), st_o) is None
+    dec = lcq.dequantize_ablation(buf, "abs_unchecked", torch.float32, x.size, stream_bytes=size)
+    assert first_diff(bits(dec.cpu().numpy()), bits(O.dequantize(st_o, np.float32, x.size))) is None
+
+
+@pytest.mark.parametrize("q", ["abs", "noa", "rel"])
+def test_fullsize_packing_stage(fields, q):
+    """Packed bytes of the full-size streams equal the oracle's, and the
+    GPU unpack restores each stream byte for byte."""
+    import torch
+    import paper_2407_15037_amd as lcq
+    x = fields[q]
+    announce("fullsize packing", q, x.size)
+    st_o = O.quantize(q, x, EB)
+    pk_o = O.pack(st_o, np.float32, x.size)
+    buf = torch.from_numpy(st_o).cuda()
+    pk, pnb = lcq.pack(buf, torch.float32, x.size)
+    psize = int(pnb.item())
+    assert first_diff(pk[:psize].cpu().numpy(), pk_o) is None
+    back, bnb = lcq.unpack(pk, torch.float32, x.size, packed_bytes=psize)
+    assert int(bnb.item()) == st_o.size
+    assert torch.equal(back[: st_o.size], buf)

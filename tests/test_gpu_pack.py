@@ -102,3 +102,21 @@ def test_pack_of_gpu_stream_and_errors():
     announce("pack corrupt input")
     _, status = _gpu_pack(bad, np.float32, n)
     assert status == 3
+
+
+def test_compress_decompress_pipeline():
+    """quantize + pack and unpack + dequantize through the one-call helpers:
+    the decode equals the oracle's decode of its own stream."""
+    import torch
+    import paper_2407_15037_amd as lcq
+    for dt in DTYPES:
+        x = synth.sines_1d(50000, 900, dtype=dt)
+        x, _, _ = synth.inject_specials(x, 60, 901, 1e-4)
+        for q in ("abs", "noa", "rel"):
+            y = x if q != "rel" else synth.rel_variant(np.nan_to_num(x.astype(np.float64)), 902, dtype=dt)
+            announce("compress pipeline", np.dtype(dt).name, q)
+            pk = lcq.compress(torch.from_numpy(y).cuda(), q, 1e-4)
+            assert first_diff(pk.cpu().numpy(), O.pack(O.quantize(q, y, 1e-4), dt, y.size)) is None
+            dec = lcq.decompress(pk, _tdt(dt), y.size).cpu().numpy()
+            ref = O.dequantize(O.quantize(q, y, 1e-4), dt, y.size)
+            assert np.array_equal(dec.view(np.uint8), ref.view(np.uint8))
