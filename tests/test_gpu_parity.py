@@ -252,3 +252,15 @@ def test_parity_sines_2_20(q):
         x = synth.rel_variant(np.nan_to_num(x.astype(np.float64)), 3, dtype=np.float32)
         x, _, _ = synth.inject_specials(x, synth.n_specials(n, 1e-3), 4, 1e-3)
     _parity(q, x, 1e-3, "sines 2^20")
+
+
+@pytest.mark.parametrize("q,eb", [("abs", 1e-3), ("abs", 1e-12), ("noa", 1e-6), ("rel", 1e-3),
+                                  ("rel", 1e-9)])
+def test_parity_random_float64_bit_patterns(q, eb):
+    """2^22 float64 values with uniformly random bit patterns (every
+    exponent, NaN payloads, INF, denormals, values whose bin leaves the
+    range): the float64 counterpart of the exhaustive float32 sweep."""
+    rng = np.random.default_rng(int(-np.log10(eb)) * 10 + len(q))
+    u = rng.integers(0, np.iinfo(np.uint64).max, 1 << 22, dtype=np.uint64, endpoint=True)
+    x = u.view(np.float64)
+    _parity(q, x, eb, "random f64 bits")
