@@ -598,7 +598,17 @@ def cpu_baseline_leg(x, xr, eb, plain, batch_sample, abl_codes=None, serve_sampl
         oc = st[64: 64 + 4 * abl_codes.size].view(np.int32)
         parity["rel_libm_codes_differing_cpu_vs_gpu"] = (
             f"{int(np.count_nonzero(oc != abl_codes))} of {abl_codes.size}")
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
     base = {"value": round(3 * n * 4 / tsum / 1e9, 4), "unit": "GB/s", "cores": 1, "kind": "oracle",
+            "host": f"{model}, {os.cpu_count()} logical CPUs visible",
             "sample": f"the plain step's three fields ({n} float32 values each): one "
                       "single-threaded oracle quantize + dequantize per field"}
     return base, parity, f"{bparity}/{len(batch_sample)}"
@@ -674,6 +684,15 @@ def main():
                    "n": plain["n"], "eb": args.eb, "quantizers": ["abs", "noa", "rel"]},
         "ops": {k: {"us": round(v["avg_us"], 2), "input_GBs": round(v["gbs_input"], 1),
                     "alg_GBs": round(v["gbs_hbm"], 1)} for k, v in sorted(kern.items())},
+        "input_GBs": {
+            # input bytes of the three fields over the summed per-op times
+            # (NOA quantize as a whole operation, range pass included)
+            "quantize": round(3 * plain["n"] * 4 / (1e-6 * (kern["quantize_abs"]["avg_us"] +
+                                                          plain["noa_whole_us"] +
+                                                          kern["quantize_rel"]["avg_us"])) / 1e9, 1),
+            "dequantize": round(3 * plain["n"] * 4 / (1e-6 * sum(
+                kern[f"dequantize_{q}"]["avg_us"] for q in ("abs", "noa", "rel"))) / 1e9, 1),
+            "combined_step": round(plain["value"], 1)},
         "quantize_noa_whole_op_us": round(plain["noa_whole_us"], 2),
         "outlier_fraction": {q: plain["ks"][q] / plain["n"] for q in plain["ks"]},
         "stream_bytes": plain["sizes"],
