@@ -295,8 +295,10 @@ lcq_status lcq_serve(const lcq_server_config *cfg, const lcq_request *req, uint3
  * kernel variants; all produce the same bytes.  Variants 0-5: one
  * workgroup-wide tile per workgroup (loads in flight per thread x rounds;
  * quantize finds its outlier offset by a decoupled look-back over earlier
- * tiles).  Variants 6-8 (6 is the default): one wavefront per 1024-value
- * chunk; quantize runs two kernels, a streaming pass that writes codes,
+ * tiles).  Variants 6-10 (6 is the default): one wavefront per 1024-value
+ * chunk, 1, 2 or 4 chunks per wavefront, loaded together (6-8) or software
+ * pipelined (9, 10: the next chunk's loads in flight while one is
+ * processed); quantize runs two kernels, a streaming pass that writes codes,
  * per-chunk outlier counts and staged outliers, then a scan pass that
  * writes the chunk table, the outliers and the header.  op 0 = quantize,
  * 1 = dequantize.  Process-wide; the tuner

@@ -386,6 +386,8 @@ void launch_quantize_variant(int v, const PlainQ &a, const StageQ &sq, hipStream
     case 6: return launch_quantize<T, Q, 6>(a, sq, s);
     case 7: return launch_quantize<T, Q, 7>(a, sq, s);
     case 8: return launch_quantize<T, Q, 8>(a, sq, s);
+    case 9: return launch_quantize<T, Q, 9>(a, sq, s);
+    case 10: return launch_quantize<T, Q, 10>(a, sq, s);
     default: return launch_quantize<T, Q, 0>(a, sq, s);
   }
 }
@@ -413,6 +415,8 @@ void launch_dequantize_variant(int v, uint64_t ntiles, const PlainD &a, hipStrea
     case 6: return launch_dequantize<T, 6>(ntiles, a, s);
     case 7: return launch_dequantize<T, 7>(ntiles, a, s);
     case 8: return launch_dequantize<T, 8>(ntiles, a, s);
+    case 9: return launch_dequantize<T, 9>(ntiles, a, s);
+    case 10: return launch_dequantize<T, 10>(ntiles, a, s);
     default: return launch_dequantize<T, 0>(ntiles, a, s);
   }
 }

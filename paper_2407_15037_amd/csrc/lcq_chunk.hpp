@@ -165,65 +165,123 @@ template <typename T> struct StageField {
   FieldParams<T> p;
 };
 
-// Pass 1 for the CPW * kWaves chunks of workgroup `tile`; PF chunks per
-// wavefront are loaded before any is encoded.
-template <typename T, int Q, int CPW, int PF>
-__device__ void quant_chunks(const StageField<T> &f, uint64_t tile) {
-  static_assert(CPW % PF == 0, "whole prefetch groups");
+// The 16 values per lane of chunk c (zeros past n).
+template <typename T>
+__device__ __forceinline__ void load_chunk(const T *in, uint64_t n, uint64_t c, int lane,
+                                           T (&x)[ChunkShape<T>::NSUB][ChunkShape<T>::W]) {
   constexpr int W = ChunkShape<T>::W, NSUB = ChunkShape<T>::NSUB;
-  constexpr unsigned kLaneMask = (1u << W) - 1;
-  __shared__ unsigned s_cnt[kWaves];
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+#pragma unroll
+  for (int j = 0; j < NSUB; j++) load_vals<T, W>(in, chunk_value<W>(c, j, lane), n, x[j]);
+}
+
+// Number of set bits of the wavefront mask b in lanes below this one, plus
+// acc.
+__device__ __forceinline__ unsigned lanes_below(uint64_t b, unsigned acc) {
+  return __builtin_amdgcn_mbcnt_hi((unsigned)(b >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)b, acc));
+}
+
+// Wavefront mask of the lanes whose value e of sub-block j lies below n,
+// for a chunk with `left` values from its first one on (all lanes when the
+// chunk is full).  Uniform: scalar arithmetic only.
+template <int W>
+__device__ __forceinline__ uint64_t valid_lanes(uint64_t left, int j, int e) {
+  if (left >= kChunk) return ~0ull;
+  const int64_t t = (int64_t)left - (int64_t)(64 * W * j + e);  // values from lane 0's
+  if (t <= 0) return 0;
+  const uint64_t lanes = ((uint64_t)t + W - 1) / W;
+  return lanes >= 64 ? ~0ull : ((1ull << lanes) - 1);
+}
+
+// Pass 1 for chunk c held in x (c is uniform over the wavefront): codes,
+// staged outliers and the chunk's count; returns the count.  Sub-block by
+// sub-block: each value's outlier flag is one wavefront mask, and a
+// sub-block with outliers puts them into the wavefront's LDS row `srow` at
+// their ranks (running rank = outliers of earlier sub-blocks + set bits of
+// lower lanes); the first kStageCap then leave in one contiguous store.
+template <typename T, int Q>
+__device__ __forceinline__ unsigned encode_chunk(const StageField<T> &f, uint64_t c, int lane,
+                                                 const T (&x)[ChunkShape<T>::NSUB][ChunkShape<T>::W],
+                                                 typename FT<T>::U *srow) {
+  constexpr int W = ChunkShape<T>::W, NSUB = ChunkShape<T>::NSUB;
   const uint64_t n = f.n;
-  const uint64_t nch = n_chunks(n);
-  const uint64_t lt = __lanemask_lt();
-  unsigned wsum = 0;
+  const uint64_t left = n - c * kChunk;
+  const bool full = left >= kChunk;
+  unsigned cnt = 0;
 #pragma unroll
-  for (int r0 = 0; r0 < CPW; r0 += PF) {
-    T x[PF][NSUB][W];
+  for (int j = 0; j < NSUB; j++) {
+    const uint64_t i0 = chunk_value<W>(c, j, lane);
+    int32_t code[W];
+    uint64_t b[W], any = 0;
 #pragma unroll
-    for (int p = 0; p < PF; p++) {
-      const uint64_t c = (tile * CPW + r0 + p) * kWaves + wave;
-      if (c < nch) {
+    for (int e = 0; e < W; e++) {
+      code[e] = encode<T, Q>(x[j][e], f.p);
+      b[e] = __ballot(code[e] == kSent) & valid_lanes<W>(left, j, e);
+      any |= b[e];
+    }
+    store_codes<W>(f.codes, i0, n, code);
+    if (any) {  // uniform
+      unsigned r = cnt;
 #pragma unroll
-        for (int j = 0; j < NSUB; j++) load_vals<T, W>(f.in, chunk_value<W>(c, j, lane), n, x[p][j]);
+      for (int e = 0; e < W; e++) {
+        r = lanes_below(b[e], r);
+        cnt += (unsigned)__popcll(b[e]);
+      }
+#pragma unroll
+      for (int e = 0; e < W; e++) {
+        const bool mine = full ? code[e] == kSent : ((b[e] >> lane) & 1u) != 0;
+        if (mine) {
+          if (r < (unsigned)kStageCap) srow[r] = to_bits(x[j][e]);
+          r++;
+        }
       }
     }
+  }
+  // LDS accesses of one wavefront complete in issue order: the row written
+  // above is whole for the reads below
+  __builtin_amdgcn_wave_barrier();
+  if ((unsigned)lane < min(cnt, (unsigned)kStageCap)) f.stage[c * kStageCap + lane] = srow[lane];
+  __builtin_amdgcn_wave_barrier();
+  if (lane == 0) f.counts[c] = cnt;
+  return cnt;
+}
+
+// Pass 1 for the CPW * kWaves chunks of workgroup `tile`.  PF > 0: PF
+// chunks per wavefront are loaded before any is encoded.  PF = 0: software
+// pipelined, the next chunk's loads are in flight while one is encoded.
+template <typename T, int Q, int CPW, int PF>
+__device__ void quant_chunks(const StageField<T> &f, uint64_t tile) {
+  static_assert(PF == 0 || CPW % PF == 0, "whole prefetch groups");
+  constexpr int W = ChunkShape<T>::W, NSUB = ChunkShape<T>::NSUB;
+  __shared__ unsigned s_cnt[kWaves];
+  __shared__ typename FT<T>::U s_stage[kWaves][kStageCap];  // one row per wavefront
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // uniform: chunk logic is scalar
+  const uint64_t nch = n_chunks(f.n);
+  unsigned wsum = 0;
+  if constexpr (PF == 0) {
+    T x[2][NSUB][W];
+    const uint64_t c0 = tile * CPW * kWaves + wave;
+    if (c0 < nch) load_chunk<T>(f.in, f.n, c0, lane, x[0]);
 #pragma unroll
-    for (int p = 0; p < PF; p++) {
-      const uint64_t c = (tile * CPW + r0 + p) * kWaves + wave;
-      if (c >= nch) continue;  // uniform over the wavefront
-      unsigned om = 0;
+    for (int r = 0; r < CPW; r++) {
+      const uint64_t c = c0 + (uint64_t)r * kWaves;
+      if (r + 1 < CPW && c + kWaves < nch) load_chunk<T>(f.in, f.n, c + kWaves, lane, x[(r + 1) & 1]);
+      if (c < nch) wsum += encode_chunk<T, Q>(f, c, lane, x[r & 1], s_stage[wave]);  // uniform
+    }
+  } else {
 #pragma unroll
-      for (int j = 0; j < NSUB; j++) {
-        const uint64_t i0 = chunk_value<W>(c, j, lane);
-        int32_t code[W];
+    for (int r0 = 0; r0 < CPW; r0 += PF) {
+      T x[PF][NSUB][W];
 #pragma unroll
-        for (int e = 0; e < W; e++) {
-          code[e] = encode<T, Q>(x[p][j][e], f.p);
-          if (code[e] == kSent && i0 + e < n) om |= 1u << (W * j + e);
-        }
-        store_codes<W>(f.codes, i0, n, code);
+      for (int p = 0; p < PF; p++) {
+        const uint64_t c = (tile * CPW + r0 + p) * kWaves + wave;
+        if (c < nch) load_chunk<T>(f.in, f.n, c, lane, x[p]);
       }
-      unsigned cnt = 0;
-      if (__ballot(om != 0)) {
 #pragma unroll
-        for (int j = 0; j < NSUB; j++) {
-          unsigned pre;
-          const unsigned tot = sub_ranks<W>((om >> (W * j)) & kLaneMask, lt, pre);
-          unsigned r = cnt + pre;
-#pragma unroll
-          for (int e = 0; e < W; e++) {
-            if ((om >> (W * j + e)) & 1u) {
-              if (r < (unsigned)kStageCap) f.stage[c * kStageCap + r] = to_bits(x[p][j][e]);
-              r++;
-            }
-          }
-          cnt += tot;
-        }
+      for (int p = 0; p < PF; p++) {
+        const uint64_t c = (tile * CPW + r0 + p) * kWaves + wave;
+        if (c < nch) wsum += encode_chunk<T, Q>(f, c, lane, x[p], s_stage[wave]);  // uniform
       }
-      if (lane == 0) f.counts[c] = cnt;
-      wsum += cnt;
     }
   }
   if (lane == 0) s_cnt[wave] = wsum;
@@ -334,20 +392,36 @@ __device__ void quant_finish(const FinishField<T> &f, uint64_t g) {
     s_P[tid] = before + (incl - cnt);  // batch-relative first outlier of each chunk
     s_c[tid] = cnt;                    // (read after the barrier below)
     const int m = (int)min<uint64_t>((uint64_t)kBlock, c1 - cb);
-    // staged outliers: thread t moves its own chunk's staged row (up to
-    // kStageCap words, all loads issued before the first store)
-    if (c < c1 && cnt != 0 && cnt <= (unsigned)kStageCap) {
-      const U *row = f.stage + c * kStageCap;
-      U v[kStageCap];
+    // the barrier makes s_P and s_c whole, and says whether any chunk of the
+    // batch has more outliers than were staged
+    const bool over = __syncthreads_or(cnt > (unsigned)kStageCap);
+    // staged outliers: half a wavefront per chunk, word r of a row moved by
+    // lane r of the half (one row read and one contiguous run written per
+    // instruction); the loads of a round are all issued before its stores
+    {
+      constexpr int kHalves = kBlock / kStageCap, kRound = 8;
+      static_assert(kStageCap == 32, "a staged row is one half wavefront");
+      const int h = tid / kStageCap, r = tid % kStageCap;
+      for (int i0 = h; i0 < m; i0 += kHalves * kRound) {
+        U v[kRound];
+        uint64_t dst[kRound];
+        bool mv[kRound];
 #pragma unroll
-      for (int r = 0; r < kStageCap; r++) v[r] = (unsigned)r < cnt ? row[r] : (U)0;
+        for (int u = 0; u < kRound; u++) {
+          const int i = i0 + u * kHalves;
+          const unsigned ci = i < m ? s_c[i] : 0u;
+          mv[u] = ci <= (unsigned)kStageCap && (unsigned)r < ci;
+          dst[u] = mv[u] ? run + s_P[i] + (unsigned)r : 0;
+          if (mv[u]) v[u] = f.stage[(cb + (uint64_t)i) * kStageCap + r];
+        }
 #pragma unroll
-      for (int r = 0; r < kStageCap; r++)
-        if ((unsigned)r < cnt) outl[P + r] = v[r];
+        for (int u = 0; u < kRound; u++)
+          if (mv[u]) outl[dst[u]] = v[u];
+      }
     }
     // chunks with more outliers than were staged (rare): rescanned by a
     // wavefront each; the batch skips this when it has none
-    if (__syncthreads_or(cnt > (unsigned)kStageCap)) {
+    if (over) {
       for (int i = wave; i < m; i += kWaves) {
         if (s_c[i] > (unsigned)kStageCap) rescan_chunk<T>(f, cb + (uint64_t)i, run + s_P[i], lane);
       }
@@ -381,73 +455,102 @@ __device__ void quant_finish(const FinishField<T> &f, uint64_t g) {
 }
 
 // ---------------------------------------------------------- dequantize ---
-// Decode the CPW * kWaves chunks of workgroup `tile`, PF chunks per
-// wavefront loaded at a time (LIBM: the library-exp2 REL ablation).
-template <typename T, int CPW, int PF, bool LIBM = false>
-__device__ void dequant_chunks(const DField<T> &f, uint64_t tile) {
-  static_assert(CPW % PF == 0, "whole prefetch groups");
+// The 16 codes per lane of chunk c (zeros past n).
+template <int W, int NSUB>
+__device__ __forceinline__ void load_chunk_codes(const int32_t *codes, uint64_t n, uint64_t c,
+                                                 int lane, int32_t (&cc)[NSUB][W]) {
+#pragma unroll
+  for (int j = 0; j < NSUB; j++) load_codes<W>(codes, chunk_value<W>(c, j, lane), n, cc[j]);
+}
+
+// Decode chunk c from its codes cc: gather its outliers, check its
+// chunk-table entry, store its values (LIBM: the library-exp2 REL ablation).
+template <typename T, bool LIBM>
+__device__ __forceinline__ void decode_chunk(const DField<T> &f, uint64_t c, int lane, uint64_t lt,
+                                             const int32_t (&cc)[ChunkShape<T>::NSUB][ChunkShape<T>::W]) {
   using U = typename FT<T>::U;
   constexpr int W = ChunkShape<T>::W, NSUB = ChunkShape<T>::NSUB;
   constexpr unsigned kLaneMask = (1u << W) - 1;
+  const uint64_t n = f.n;
+  const uint64_t nch = n_chunks(n);
+  const uint64_t *chunk_tab = reinterpret_cast<const uint64_t *>(f.stream + chunk_table_offset(n));
+  const U *outl = reinterpret_cast<const U *>(f.stream + outlier_offset(n));
+  const uint64_t cur = chunk_tab[c];
+  const uint64_t nxt = (c + 1 < nch) ? chunk_tab[c + 1] : f.k;
+  unsigned om = 0;
+  T y[NSUB][W];
+#pragma unroll
+  for (int j = 0; j < NSUB; j++) {
+    const uint64_t i0 = chunk_value<W>(c, j, lane);
+#pragma unroll
+    for (int e = 0; e < W; e++) {
+      const bool sent = cc[j][e] == kSent;
+      y[j][e] = sent ? (T)0 : decode<T, LIBM>(cc[j][e], f.step, f.rel);
+      if (sent && i0 + e < n) om |= 1u << (W * j + e);
+    }
+  }
+  uint64_t cnt = 0;
+  if (__ballot(om != 0)) {
+#pragma unroll
+    for (int j = 0; j < NSUB; j++) {
+      unsigned pre;
+      const unsigned tot = sub_ranks<W>((om >> (W * j)) & kLaneMask, lt, pre);
+      uint64_t r = cur + cnt + pre;
+#pragma unroll
+      for (int e = 0; e < W; e++) {
+        if ((om >> (W * j + e)) & 1u) {
+          // ranks are checked against the outlier count: never read past it
+          y[j][e] = (r < f.k) ? from_bits(outl[r]) : (T)0;
+          r++;
+        }
+      }
+      cnt += tot;
+    }
+  }
+  // the chunk-table entry must count exactly the sentinels before it
+  if (lane == 0 && (cur > f.k || nxt - cur != cnt || (c == 0 && cur != 0)))
+    report_status(f.status, f.tag, LCQ_ERR_STREAM);
+#pragma unroll
+  for (int j = 0; j < NSUB; j++) store_vals<T, W>(f.out, chunk_value<W>(c, j, lane), n, y[j]);
+}
+
+// Decode the CPW * kWaves chunks of workgroup `tile`.  PF > 0: PF chunks per
+// wavefront loaded at a time.  PF = 0: software pipelined, the next chunk's
+// codes are in flight while one is decoded.
+template <typename T, int CPW, int PF, bool LIBM = false>
+__device__ void dequant_chunks(const DField<T> &f, uint64_t tile) {
+  static_assert(PF == 0 || CPW % PF == 0, "whole prefetch groups");
+  constexpr int W = ChunkShape<T>::W, NSUB = ChunkShape<T>::NSUB;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const uint64_t n = f.n;
   const uint64_t nch = n_chunks(n);
   const int32_t *codes = reinterpret_cast<const int32_t *>(f.stream + 64);
-  const uint64_t *chunk_tab = reinterpret_cast<const uint64_t *>(f.stream + chunk_table_offset(n));
-  const U *outl = reinterpret_cast<const U *>(f.stream + outlier_offset(n));
   const uint64_t lt = __lanemask_lt();
+  if constexpr (PF == 0) {
+    int32_t cc[2][NSUB][W];
+    const uint64_t c0 = tile * CPW * kWaves + wave;
+    if (c0 < nch) load_chunk_codes<W, NSUB>(codes, n, c0, lane, cc[0]);
 #pragma unroll
-  for (int r0 = 0; r0 < CPW; r0 += PF) {
-    int32_t cc[PF][NSUB][W];
-#pragma unroll
-    for (int p = 0; p < PF; p++) {
-      const uint64_t c = (tile * CPW + r0 + p) * kWaves + wave;
-      if (c < nch) {
-#pragma unroll
-        for (int j = 0; j < NSUB; j++) load_codes<W>(codes, chunk_value<W>(c, j, lane), n, cc[p][j]);
-      }
+    for (int r = 0; r < CPW; r++) {
+      const uint64_t c = c0 + (uint64_t)r * kWaves;
+      if (r + 1 < CPW && c + kWaves < nch)
+        load_chunk_codes<W, NSUB>(codes, n, c + kWaves, lane, cc[(r + 1) & 1]);
+      if (c < nch) decode_chunk<T, LIBM>(f, c, lane, lt, cc[r & 1]);  // uniform
     }
+  } else {
 #pragma unroll
-    for (int p = 0; p < PF; p++) {
-      const uint64_t c = (tile * CPW + r0 + p) * kWaves + wave;
-      if (c >= nch) continue;  // uniform over the wavefront
-      const uint64_t cur = chunk_tab[c];
-      const uint64_t nxt = (c + 1 < nch) ? chunk_tab[c + 1] : f.k;
-      unsigned om = 0;
-      T y[NSUB][W];
+    for (int r0 = 0; r0 < CPW; r0 += PF) {
+      int32_t cc[PF][NSUB][W];
 #pragma unroll
-      for (int j = 0; j < NSUB; j++) {
-        const uint64_t i0 = chunk_value<W>(c, j, lane);
-#pragma unroll
-        for (int e = 0; e < W; e++) {
-          const bool sent = cc[p][j][e] == kSent;
-          y[j][e] = sent ? (T)0 : decode<T, LIBM>(cc[p][j][e], f.step, f.rel);
-          if (sent && i0 + e < n) om |= 1u << (W * j + e);
-        }
+      for (int p = 0; p < PF; p++) {
+        const uint64_t c = (tile * CPW + r0 + p) * kWaves + wave;
+        if (c < nch) load_chunk_codes<W, NSUB>(codes, n, c, lane, cc[p]);
       }
-      uint64_t cnt = 0;
-      if (__ballot(om != 0)) {
 #pragma unroll
-        for (int j = 0; j < NSUB; j++) {
-          unsigned pre;
-          const unsigned tot = sub_ranks<W>((om >> (W * j)) & kLaneMask, lt, pre);
-          uint64_t r = cur + cnt + pre;
-#pragma unroll
-          for (int e = 0; e < W; e++) {
-            if ((om >> (W * j + e)) & 1u) {
-              // ranks are checked against the outlier count: never read past it
-              y[j][e] = (r < f.k) ? from_bits(outl[r]) : (T)0;
-              r++;
-            }
-          }
-          cnt += tot;
-        }
+      for (int p = 0; p < PF; p++) {
+        const uint64_t c = (tile * CPW + r0 + p) * kWaves + wave;
+        if (c < nch) decode_chunk<T, LIBM>(f, c, lane, lt, cc[p]);  // uniform
       }
-      // the chunk-table entry must count exactly the sentinels before it
-      if (lane == 0 && (cur > f.k || nxt - cur != cnt || (c == 0 && cur != 0)))
-        report_status(f.status, f.tag, LCQ_ERR_STREAM);
-#pragma unroll
-      for (int j = 0; j < NSUB; j++) store_vals<T, W>(f.out, chunk_value<W>(c, j, lane), n, y[j]);
     }
   }
 }

@@ -81,6 +81,35 @@ template <typename T> LCQ_HD T pow2approx(T y) {
   return from_bits((U)(((U)k << F::kMant) | (to_bits(g) & F::kFracMask)));
 }
 
+// Device forms of the two approximations, value for value the same as
+// log2approx / pow2approx above (the sign bit of log2approx_dev's argument
+// is ignored too), in fewer instructions for float32:
+// - log2: E - 128 is the exponent byte E with its top bit flipped, read as
+//   a signed byte (one xor and one signed bit-field extract);
+// - pow2: t is finite here (a finite bin times a finite step), so the clamp
+//   is one median-of-three; for t >= 0, t - (k - 1) = fract(t) + 1 exactly
+//   when t >= 1 (both sides exact) and with the same single rounding of
+//   t + 1 when t < 1 (k = 0).
+template <typename T> __device__ __forceinline__ T log2approx_dev(T a) {
+  if constexpr (sizeof(T) == 4) {
+    const uint32_t u = to_bits(a);
+    const int e = (int)((u ^ 0x40000000u) << 1) >> 24;  // E - 128
+    return from_bits((uint32_t)(0x3F800000u | (u & 0x007FFFFFu))) + (float)e;
+  } else {
+    return log2approx(a);
+  }
+}
+template <typename T> __device__ __forceinline__ T pow2approx_dev(T y) {
+  if constexpr (sizeof(T) == 4) {
+    const float t = __builtin_amdgcn_fmed3f(y + 127.0f, 0.0f, 255.0f);
+    const int k = (int)t;
+    const float g = __builtin_amdgcn_fractf(t) + 1.0f;
+    return from_bits((uint32_t)(((uint32_t)k << 23) | (to_bits(g) & 0x007FFFFFu)));
+  } else {
+    return pow2approx(y);
+  }
+}
+
 // Parameters of one field in the field's type.
 template <typename T> struct FieldParams {
   T step;   // bin width
@@ -102,35 +131,46 @@ LCQ_HD double lib_log2(double x) { return log2(x); }
 LCQ_HD float lib_exp2(float x) { return exp2f(x); }
 LCQ_HD double lib_exp2(double x) { return exp2(x); }
 
+// Whether x may be quantized at all (sections 2.2 and 3.1): INF, NaN and
+// denormals are stored losslessly, and for REL zeros too.  One class test:
+// bits 3 and 8 of its mask are the negative and positive normals, bits 5
+// and 6 the negative and positive zeros.
+template <typename T, int Q> __device__ __forceinline__ bool quantizable(T x) {
+  constexpr int kNormal = (1 << 3) | (1 << 8), kZero = (1 << 5) | (1 << 6);
+  constexpr int m = is_rel_q<Q>() ? kNormal : (kNormal | kZero);
+  if constexpr (sizeof(T) == 4) return __builtin_amdgcn_classf(x, m);
+  else return __builtin_amdgcn_class(x, m);
+}
+
 // One value -> its int32 code, or kSent if it must be stored losslessly.
 // Evaluates every step for every lane (no data-dependent branches) and only
 // converts the bin to int where it is in range.
-template <typename T, int Q> LCQ_HD int32_t encode(T x, const FieldParams<T> &p) {
+template <typename T, int Q> __device__ __forceinline__ int32_t encode(T x, const FieldParams<T> &p) {
   using F = FT<T>;
   using U = typename F::U;
   const U u = to_bits(x);
-  const U E = (u >> F::kMant) & F::kExpMask;
-  const U frac = u & F::kFracMask;
-  // section 2.2 / 3.1: INF, NaN and denormals (REL: also zeros) are lossless
-  bool ok = (E != F::kExpMask) && (E != 0 || (!is_rel_q<Q>() && frac == 0));
+  bool ok = quantizable<T, Q>(x);
   if (Q == kNOA) ok = ok && !p.lossless_all;
 
   if constexpr (is_rel_q<Q>()) {
     const T a = from_bits((U)(u & ~F::kSign));
-    const T q = rint_t((Q == kREL_LIBM ? lib_log2(a) : log2approx(a)) * p.inv);
+    // (the approximate log2 reads only the exponent and fraction fields)
+    const T q = rint_t((Q == kREL_LIBM ? lib_log2(a) : log2approx_dev(x)) * p.inv);
     // section 3.3: both range tests, on the float, before any conversion
     ok = ok && (q > (T)-kMaxBin) && (q < (T)kMaxBin);
     // qb is integral and inside (-2^30, 2^30), so (T)(int)qb == qb exactly
     const T qb = ok ? q : (T)0;
     const int32_t b = (int32_t)qb;
-    const T rec = Q == kREL_LIBM ? lib_exp2(qb * p.step) : pow2approx(qb * p.step);
+    const T rec = Q == kREL_LIBM ? lib_exp2(qb * p.step) : pow2approx_dev(qb * p.step);
     // section 3.1 double-check against both sides of the section 2.1.2 range
     // |rec - a| equals (a - rec) when rec < a: round-to-nearest is
     // symmetric under negation, so one subtraction serves both sides
     const bool up = rec >= a;
     const T diff = abs_t(rec - a);
-    const T lim = (up ? p.bound : p.low) * a;
-    ok = ok && (diff < lim);
+    // el <= eh, so passing the lower side's test implies passing the upper
+    // side's: one select-free form of (up ? diff < eh a : diff < el a)
+    const bool ok_up = diff < p.bound * a, ok_low = diff < p.low * a;
+    ok = ok & (ok_low | (up & ok_up));
     const uint32_t code = ((uint32_t)b << 1) | (uint32_t)(u >> (sizeof(T) * 8 - 1));
     return ok ? (int32_t)code : kSent;
   } else {
@@ -146,13 +186,14 @@ template <typename T, int Q> LCQ_HD int32_t encode(T x, const FieldParams<T> &p)
 
 // One non-sentinel code -> its value (the decoder side of encode; LIBM: the
 // library-exp2 ablation).
-template <typename T, bool LIBM = false> LCQ_HD T decode(int32_t c, T step, bool rel) {
+template <typename T, bool LIBM = false>
+__device__ __forceinline__ T decode(int32_t c, T step, bool rel) {
   using F = FT<T>;
   using U = typename F::U;
   if (rel) {
     const U sgn = (U)(c & 1);
     const int32_t b = c >> 1;  // arithmetic shift: c = 2b + sign
-    const T a = LIBM ? lib_exp2((T)b * step) : pow2approx((T)b * step);
+    const T a = LIBM ? lib_exp2((T)b * step) : pow2approx_dev((T)b * step);
     return from_bits((U)(to_bits(a) | (sgn << (sizeof(T) * 8 - 1))));
   }
   return (T)c * step;
