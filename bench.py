@@ -182,6 +182,79 @@ def run_plain(args, x, xr):
                 gpu_streams=gpu_streams, gpu_decodes=gpu_decodes)
 
 
+# ----------------------------------------------------------------- float64 --
+def run_f64(args):
+    """The float64 single-field workload (384^3 GRF with its bin-border slice;
+    ABS / NOA at 1e-6, REL at 1e-4): per-operation times of the per-value
+    kernels, events on the launch stream as in the float32 step."""
+    import numpy as np
+    import torch
+    import synth
+    import paper_2407_15037_amd as lcq
+    t0 = time.time()
+    x, xr = synth.f64_grid_inputs()
+    log(f"float64 inputs 384^3 generated in {time.time() - t0:.1f}s")
+    dev = torch.device("cuda:0")
+    ebs = {"abs": 1e-6, "noa": 1e-6, "rel": 1e-4}
+    order_q = ["abs", "noa", "rel"]
+    n, s = x.size, 8
+    dx = {"abs": torch.from_numpy(x).to(dev)}
+    dx["noa"] = dx["abs"]
+    dx["rel"] = torch.from_numpy(xr).to(dev)
+    cap = lcq.max_stream_bytes(torch.float64, n)
+    bufs = {q: torch.empty(cap, dtype=torch.uint8, device=dev) for q in order_q}
+    nbs = {q: torch.zeros(1, dtype=torch.int64, device=dev) for q in order_q}
+    ws = {q: torch.empty(lcq.workspace_bytes(q, torch.float64, n), dtype=torch.uint8, device=dev)
+          for q in order_q}
+    outs = {q: torch.empty(n, dtype=torch.float64, device=dev) for q in order_q}
+    ev = {}
+    for rep in range(args.warmup + args.steps):
+        for kind in ("q", "d"):
+            for q in order_q:
+                if rep >= args.warmup:
+                    e0 = torch.cuda.Event(enable_timing=True)
+                    e1 = torch.cuda.Event(enable_timing=True)
+                    e0.record(); e1.record()
+                    lcq.profile_events(e0, e1)
+                    ev.setdefault((kind, q), []).append((e0, e1))
+                if kind == "q":
+                    lcq.quantize(dx[q], q, ebs[q], out=bufs[q], nbytes=nbs[q], ws=ws[q])
+                else:
+                    lcq.dequantize(bufs[q], torch.float64, n, out=outs[q], ws=ws[q])
+            lcq.profile_events(None, None)
+    torch.cuda.synchronize()
+    ks = {q: header_k(bufs[q]) for q in order_q}
+    ops = {}
+    for (kind, q), pairs in sorted(ev.items()):
+        us = 1e3 * sum(a.elapsed_time(b) for a, b in pairs) / len(pairs)
+        nbytes = (alg_bytes_quant if kind == "q" else alg_bytes_dequant)(n, s, ks[q])
+        ops[f"{'quantize' if kind == 'q' else 'dequantize'}_{q}"] = {
+            "us": round(us, 2), "input_GBs": round(n * s / (us * 1e-6) / 1e9, 1),
+            "alg_GBs": round(nbytes / (us * 1e-6) / 1e9, 1),
+            "frac_of_peak": round(nbytes / (us * 1e-6) / 1e9 / HBM_PEAK_GBS, 4)}
+    # every decoded value within its bound (specials bit-exact) on the GPU
+    ok = {}
+    for q in order_q:
+        a, b = dx[q], outs[q]
+        fin = torch.isfinite(a) & ~((a != 0) & (a.abs() < 2.2250738585072014e-308))
+        if q == "rel":
+            good = (b - a).abs() <= ebs[q] * a.abs()
+        else:
+            bound = float(bufs[q][40:48].cpu().numpy().view(np.float64)[0])
+            good = (b - a).abs() <= bound
+        same_bits = a.view(torch.int64) == b.view(torch.int64)
+        ok[q] = bool(torch.where(fin, good | same_bits, same_bits).all().item())
+    res = {"workload": "grf384^3 float64, 0.01% specials, 2^20-value bin-border slice at n/2; "
+                       "ABS/NOA eb=1e-6, REL eb=1e-4 on the lognormal variant",
+           "n": n, "ops": ops,
+           "outlier_fraction": {q: ks[q] / n for q in order_q},
+           "stream_bytes": {q: int(nbs[q].item()) for q in order_q},
+           "decodes_within_bound": ok}
+    del dx, bufs, ws, outs
+    torch.cuda.empty_cache()
+    return res
+
+
 # ----------------------------------------------------------------- in-line --
 def run_inline(args, x, xr, plain):
     """The same three fields in the in-line layout (one word per value plus a
@@ -632,6 +705,7 @@ def main():
     ap.add_argument("--no-inline", action="store_true")
     ap.add_argument("--no-ablation", action="store_true")
     ap.add_argument("--no-packing", action="store_true")
+    ap.add_argument("--no-f64", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--fields", type=int, default=2000)
     ap.add_argument("--batch-reps", type=int, default=5)
@@ -704,6 +778,18 @@ def main():
                      "alg_bytes_per_launch": dom["alg_bytes"],
                      "avg_launch_us": round(dom["avg_us"], 2)},
     }
+    # each quantizer's quantize + dequantize pair on one field: algorithmic
+    # bytes of both over their summed times (NOA: whole quantize operation,
+    # its range pass's read of the field included)
+    pair = {}
+    for q in ("abs", "noa", "rel"):
+        kq, kd = kern[f"quantize_{q}"], kern[f"dequantize_{q}"]
+        tq = plain["noa_whole_us"] if q == "noa" else kq["avg_us"]
+        nb = kq["alg_bytes"] + kd["alg_bytes"] + (plain["n"] * 4 if q == "noa" else 0)
+        pair[q] = round(nb / ((tq + kd["avg_us"]) * 1e-6) / 1e9 / HBM_PEAK_GBS, 4)
+    result["quantize_dequantize_pair_frac_of_peak"] = pair
+    if not args.no_f64:
+        result["float64_grid"] = run_f64(args)
     if not args.no_inline:
         result["inline_layout"] = run_inline(args, x, xr, plain)
     if not args.no_packing:

@@ -19,7 +19,8 @@
 //           (the chunk table), copy of staged outliers to their final,
 //           input-ordered place, header and size.  A chunk with more than
 //           kStageCap outliers has its codes rescanned and its raw bits
-//           read from the input.
+//           read from the input, by a workgroup chosen so that runs of
+//           such chunks spread over all of them.
 // Dequantize gathers each outlier's bits before the single store of its
 // values and checks every chunk-table entry against the counted sentinels.
 #pragma once
@@ -310,33 +311,50 @@ template <typename T> struct FinishField {
 };
 
 // Outliers of chunk c from its codes and the input (a chunk with more
-// outliers than were staged), written from index P on.  One wavefront.
+// outliers than were staged), written from index P on.  One wavefront; all
+// code and value loads of the chunk are issued before the first rank.
 template <typename T>
 __device__ void rescan_chunk(const FinishField<T> &f, uint64_t c, uint64_t P, int lane) {
   using U = typename FT<T>::U;
   constexpr int W = ChunkShape<T>::W, NSUB = ChunkShape<T>::NSUB;
   const int32_t *codes = reinterpret_cast<const int32_t *>(f.stream + 64);
   U *outl = reinterpret_cast<U *>(f.stream + outlier_offset(f.n));
-  const U *inb = reinterpret_cast<const U *>(f.in);
-  const uint64_t lt = __lanemask_lt();
+  int32_t cc[NSUB][W];
+  T x[NSUB][W];
+#pragma unroll
+  for (int j = 0; j < NSUB; j++) load_codes<W>(codes, chunk_value<W>(c, j, lane), f.n, cc[j]);
+  load_chunk<T>(f.in, f.n, c, lane, x);
+  const uint64_t left = f.n - c * kChunk;
   uint64_t run = P;
 #pragma unroll
   for (int j = 0; j < NSUB; j++) {
-    const uint64_t i0 = chunk_value<W>(c, j, lane);
-    int32_t cc[W];
-    load_codes<W>(codes, i0, f.n, cc);
-    unsigned fl = 0;
+    uint64_t b[W];
+    uint64_t r = run;
+#pragma unroll
+    for (int e = 0; e < W; e++) {
+      b[e] = __ballot(cc[j][e] == kSent) & valid_lanes<W>(left, j, e);
+      r = lanes_below(b[e], (unsigned)0) + r;
+      run += (uint64_t)__popcll(b[e]);
+    }
 #pragma unroll
     for (int e = 0; e < W; e++)
-      if (cc[e] == kSent && i0 + e < f.n) fl |= 1u << e;
-    unsigned pre;
-    const unsigned tot = sub_ranks<W>(fl, lt, pre);
-    uint64_t r = run + pre;
-#pragma unroll
-    for (int e = 0; e < W; e++)
-      if ((fl >> e) & 1u) outl[r++] = inb[i0 + e];
-    run += tot;
+      if ((b[e] >> lane) & 1u) outl[r++] = to_bits(x[j][e]);
   }
+}
+
+static_assert(LCQ_MAX_N / kChunk <= 0xFFFFFFFFull, "chunk indices fit 32 bits");
+
+// Index of chunk c's first outlier, from the pass-1 group sums and chunk
+// counts alone (so any workgroup can find it before the chunk table is
+// written).  One wavefront; uniform result.
+template <typename T>
+__device__ uint64_t chunk_first_outlier(const FinishField<T> &f, uint64_t c, int lane) {
+  // chunk and group indices fit 32 bits (n <= LCQ_MAX_N = 2^38)
+  const uint64_t gc = (uint32_t)c / (uint32_t)f.chunks_per_group;
+  unsigned long long s = 0;
+  for (uint64_t i = (uint64_t)lane; i < gc; i += 64) s += f.group[i];
+  for (uint64_t i = gc * f.chunks_per_group + (uint64_t)lane; i < c; i += 64) s += f.counts[i];
+  return wave_sum(s);
 }
 
 // Pass 2 for group g: chunk-table entries of its chunks, their outliers,
@@ -356,8 +374,11 @@ __device__ void quant_finish(const FinishField<T> &f, uint64_t g) {
 
   const uint64_t c0 = g * f.chunks_per_group;
   const uint64_t c1 = min(c0 + f.chunks_per_group, nch);
-  // the first batch's count is loaded before the earlier groups are summed
+  // the first batch's count (and the first count of the rescan duty below)
+  // is loaded before the earlier groups are summed
   unsigned cnt_next = c0 + tid < c1 ? f.counts[c0 + tid] : 0u;
+  const uint64_t cd0 = g + (uint64_t)tid * f.ngroups;
+  const unsigned duty0 = cd0 < nch ? f.counts[cd0] : 0u;
 
   // outliers of all earlier groups
   unsigned long long b = 0;
@@ -392,14 +413,12 @@ __device__ void quant_finish(const FinishField<T> &f, uint64_t g) {
     s_P[tid] = before + (incl - cnt);  // batch-relative first outlier of each chunk
     s_c[tid] = cnt;                    // (read after the barrier below)
     const int m = (int)min<uint64_t>((uint64_t)kBlock, c1 - cb);
-    // the barrier makes s_P and s_c whole, and says whether any chunk of the
-    // batch has more outliers than were staged
-    const bool over = __syncthreads_or(cnt > (unsigned)kStageCap);
+    __syncthreads();  // s_P and s_c whole
     // staged outliers: half a wavefront per chunk, word r of a row moved by
     // lane r of the half (one row read and one contiguous run written per
     // instruction); the loads of a round are all issued before its stores
     {
-      constexpr int kHalves = kBlock / kStageCap, kRound = 8;
+      constexpr int kHalves = kBlock / kStageCap, kRound = 16;
       static_assert(kStageCap == 32, "a staged row is one half wavefront");
       const int h = tid / kStageCap, r = tid % kStageCap;
       for (int i0 = h; i0 < m; i0 += kHalves * kRound) {
@@ -419,15 +438,36 @@ __device__ void quant_finish(const FinishField<T> &f, uint64_t g) {
           if (mv[u]) outl[dst[u]] = v[u];
       }
     }
-    // chunks with more outliers than were staged (rare): rescanned by a
-    // wavefront each; the batch skips this when it has none
-    if (over) {
-      for (int i = wave; i < m; i += kWaves) {
-        if (s_c[i] > (unsigned)kStageCap) rescan_chunk<T>(f, cb + (uint64_t)i, run + s_P[i], lane);
-      }
-    }
     run += total;
     __syncthreads();  // s_wt, s_P, s_c are rewritten by the next batch
+  }
+
+  // Chunks with more outliers than were staged are rescanned from their
+  // codes and input, and not by their own group: workgroup g takes chunks
+  // g, g + ngroups, g + 2 ngroups, ... so that runs of such chunks (a
+  // stretch of hard data) spread over every workgroup instead of queueing
+  // behind one.  One wavefront per such chunk.
+  for (uint64_t t0 = 0; g + t0 * f.ngroups < nch; t0 += kBlock) {
+    const uint64_t c = g + (t0 + (uint64_t)tid) * f.ngroups;
+    const unsigned cn = t0 == 0 ? duty0 : (c < nch ? f.counts[c] : 0u);
+    const bool ov = cn > (unsigned)kStageCap;
+    if (!__syncthreads_or(ov)) continue;
+    const uint64_t wb = __ballot(ov);
+    if (lane == 0) s_wt[wave] = (unsigned)__popcll(wb);
+    __syncthreads();
+    unsigned base = 0, nov = 0;
+#pragma unroll
+    for (int w = 0; w < kWaves; w++) {
+      if (w < wave) base += s_wt[w];
+      nov += s_wt[w];
+    }
+    if (ov) s_P[base + lanes_below(wb, 0u)] = c;  // compact list of this batch's chunks
+    __syncthreads();
+    for (unsigned i = (unsigned)wave; i < nov; i += kWaves) {
+      const uint64_t cv = s_P[i];
+      rescan_chunk<T>(f, cv, chunk_first_outlier<T>(f, cv, lane), lane);
+    }
+    __syncthreads();  // s_wt and s_P are rewritten by the next batch
   }
 
   if (g == f.ngroups - 1 && tid == 0) {
