@@ -264,3 +264,28 @@ def test_parity_random_float64_bit_patterns(q, eb):
     u = rng.integers(0, np.iinfo(np.uint64).max, 1 << 22, dtype=np.uint64, endpoint=True)
     x = u.view(np.float64)
     _parity(q, x, eb, "random f64 bits")
+
+
+@pytest.mark.parametrize("dt", DTYPES, ids=["f32", "f64"])
+@pytest.mark.parametrize("q,eb", [("abs", 1e-3), ("noa", 1e-3), ("rel", 1e-3)])
+@pytest.mark.parametrize("nchunks", [40, 300, 1203])
+def test_parity_overflow_runs(dt, q, eb, nchunks):
+    """Runs of chunks with more outliers than a chunk stages (NaN every other
+    value, or random bit patterns) in a smooth field: a run across a group
+    boundary, a run of random bits, and a ragged last chunk full of NaNs.
+    Such chunks are rescanned by workgroups other than their own group's, at
+    offsets found from the pass-1 sums; the stream must still equal the
+    oracle's."""
+    n = nchunks * 1024 - 333
+    x = _field(dt, n, 900 + nchunks, eb, q)
+    rng = np.random.default_rng(nchunks)
+    a, b = 60 * 1024, min(75 * 1024, n)
+    x[a:b:2] = np.nan
+    if nchunks > 200:
+        ub = np.uint64 if dt == np.float64 else np.uint32
+        lo, hi = 200 * 1024, 264 * 1024
+        x[lo:hi] = rng.integers(0, np.iinfo(ub).max, hi - lo, dtype=ub, endpoint=True).view(dt)
+    x[(nchunks - 1) * 1024:] = np.nan
+    st, _ = _parity(q, x, eb, f"overflow runs {nchunks} chunks")
+    k = int(st[16:24].view(np.uint64)[0])
+    assert k >= (n - (nchunks - 1) * 1024) + (b - a) // 2, (k, n)
