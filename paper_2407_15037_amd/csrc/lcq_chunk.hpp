@@ -237,11 +237,12 @@ __device__ __forceinline__ unsigned encode_chunk(const StageField<T> &f, uint64_
       }
     }
   }
-  // LDS accesses of one wavefront complete in issue order: the row written
-  // above is whole for the reads below
-  __builtin_amdgcn_wave_barrier();
+  // other lanes' LDS writes above, then this lane's read: a wavefront-scope
+  // fence orders them (LDS accesses of one wavefront complete in issue
+  // order, so it costs no wait)
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
   if ((unsigned)lane < min(cnt, (unsigned)kStageCap)) f.stage[c * kStageCap + lane] = srow[lane];
-  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");  // before the next chunk's writes
   if (lane == 0) f.counts[c] = cnt;
   return cnt;
 }
