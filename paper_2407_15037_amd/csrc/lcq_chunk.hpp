@@ -353,8 +353,24 @@ __device__ uint64_t chunk_first_outlier(const FinishField<T> &f, uint64_t c, int
   // chunk and group indices fit 32 bits (n <= LCQ_MAX_N = 2^38)
   const uint64_t gc = (uint32_t)c / (uint32_t)f.chunks_per_group;
   unsigned long long s = 0;
-  for (uint64_t i = (uint64_t)lane; i < gc; i += 64) s += f.group[i];
-  for (uint64_t i = gc * f.chunks_per_group + (uint64_t)lane; i < c; i += 64) s += f.counts[i];
+  // eight loads per lane in flight per round (unconditional loads at a
+  // clamped index, masked afterwards)
+  for (uint64_t i0 = (uint64_t)lane; i0 < gc; i0 += 64 * 8) {
+#pragma unroll
+    for (int k = 0; k < 8; k++) {
+      const uint64_t i = i0 + 64 * (uint64_t)k;
+      const unsigned long long v = f.group[i < gc ? i : 0];
+      s += i < gc ? v : 0ull;
+    }
+  }
+  for (uint64_t i0 = gc * f.chunks_per_group + (uint64_t)lane; i0 < c; i0 += 64 * 8) {
+#pragma unroll
+    for (int k = 0; k < 8; k++) {
+      const uint64_t i = i0 + 64 * (uint64_t)k;
+      const unsigned v = f.counts[i < c ? i : 0];
+      s += i < c ? v : 0u;
+    }
+  }
   return wave_sum(s);
 }
 
@@ -381,9 +397,16 @@ __device__ void quant_finish(const FinishField<T> &f, uint64_t g) {
   const uint64_t cd0 = g + (uint64_t)tid * f.ngroups;
   const unsigned duty0 = cd0 < nch ? f.counts[cd0] : 0u;
 
-  // outliers of all earlier groups
+  // outliers of all earlier groups: every load issued before the first add
+  // (unconditional loads at a clamped index, masked afterwards)
+  static_assert(kMaxGroups % kBlock == 0, "whole rounds of group sums");
   unsigned long long b = 0;
-  for (uint64_t i = tid; i < g; i += kBlock) b += f.group[i];
+#pragma unroll
+  for (int k = 0; k < (int)(kMaxGroups / kBlock); k++) {
+    const uint64_t i = (uint64_t)tid + (uint64_t)k * kBlock;
+    const unsigned long long v = f.group[i < g ? i : 0];
+    b += i < g ? v : 0ull;
+  }
   b = wave_sum(b);
   if (lane == 0) s_red[wave] = b;
   __syncthreads();
