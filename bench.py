@@ -57,24 +57,28 @@ def kernel_source_digest():
 TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "hbm_traffic_grf512_f32.md")
 
 
-def measured_traffic(op, grid, eb):
+def measured_traffic(op, grid, eb, variants):
     """HBM bytes per launch of `op` from the committed rocprofv3 FETCH_SIZE /
-    WRITE_SIZE summary of this workload, or None if the workload differs or
-    the kernels changed since the counters were taken."""
+    WRITE_SIZE summary of this workload, or None if the workload differs,
+    the launch variants timed (quantize, dequantize) are not the ones the
+    counters were taken with, or the kernels changed since."""
     if grid != 512 or eb != 1e-3 or not os.path.exists(TRAFFIC_PROFILE):
         return None
-    digest, table = None, {}
+    digest, table, counted = None, {}, None
     with open(TRAFFIC_PROFILE) as fh:
         for line in fh:
             if line.startswith("kernel-source-sha256:"):
                 digest = line.split(":", 1)[1].strip()
+            if counted is None and "--variants " in line:
+                v = line.split("--variants ", 1)[1].split()[0]
+                counted = tuple(int(x) for x in v.split(","))
             cells = [c.strip() for c in line.strip().strip("|").split("|")]
             if len(cells) >= 4 and cells[0] and not cells[0].startswith(("op", "-", "`")):
                 try:
                     table[cells[0]] = float(cells[3])
                 except ValueError:
                     pass
-    if digest != kernel_source_digest():
+    if digest != kernel_source_digest() or counted != tuple(variants):
         return None
     return table.get(op)
 
@@ -725,6 +729,7 @@ def main():
         sys.exit(2)
 
     import torch
+    import paper_2407_15037_amd as lcq
     if args.calib_copy:
         src = torch.ones(128 << 20, dtype=torch.float32, device="cuda")
         dst = torch.empty_like(src)
@@ -735,7 +740,6 @@ def main():
         log("calibration copies: 3 x 512 MiB read + 512 MiB written")
     tuned = None
     if args.variants:
-        import paper_2407_15037_amd as lcq
         qv, dv = (int(v) for v in args.variants.split(","))
         lcq.tune_set("quantize", torch.float32, qv)
         lcq.tune_set("dequantize", torch.float32, dv)
@@ -774,7 +778,9 @@ def main():
         "roofline": {"kernel": dom_name, "bound": "hbm", "achieved": round(dom["gbs_hbm"], 1),
                      "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(dom["gbs_hbm"] / HBM_PEAK_GBS, 4),
-                     "traffic": measured_traffic(dom_name, args.grid, args.eb),
+                     "traffic": measured_traffic(dom_name, args.grid, args.eb,
+                                                 (lcq.tune_get("quantize", torch.float32),
+                                                  lcq.tune_get("dequantize", torch.float32))),
                      "alg_bytes_per_launch": dom["alg_bytes"],
                      "avg_launch_us": round(dom["avg_us"], 2)},
     }
