@@ -5,7 +5,7 @@ every decoded value must satisfy its bound (special values bit-exact), and
 the GPU stream of every 2^28-value chunk must equal the CPU oracle's (compared
 by digest, oracle chunks run in a process pool).
 
-Opt-in: runs only with LCQ_EXHAUSTIVE=1 (about 10 minutes on one MI355X machine
+Opt-in: runs only with LCQ_EXHAUSTIVE=1 (about 5 minutes on one MI355X machine
 with 16 host cores); the default GPU suite skips it.
 """
 import hashlib
