@@ -214,6 +214,16 @@ def _cases():
     for dt in (np.float32, np.float64):
         for q, eb in (("abs", 1e-3), ("noa", 1e-4), ("rel", 1e-2), ("rel", 1e-3)):
             n = 3 * 1024 + 517
+            if q == "noa":
+                # specials that keep the field's range (its bins are real),
+                # border values at the field's own eb * R
+                x = synth.with_specials(synth.sines_1d(n, 5, dtype=dt), "noa",
+                                        max(19, n // 1000), 105, eb)
+                lo, hi = synth.finite_range(x)
+                adv = synth.adversarial_noa(4000, synth.noa_half_bin(x, eb), lo, hi, 8, dt)
+                x = np.concatenate([x, adv]).astype(dt)
+                out.append((dt, q, eb, x))
+                continue
             x = _config0_like(dt, n, 5, eb)
             if q == "rel":
                 x = synth.rel_variant(x.astype(np.float64), 6, dtype=dt)

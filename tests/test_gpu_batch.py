@@ -27,7 +27,7 @@ def _fields(seed, nf, max_n):
         off = int(rng.integers(0, src.size))
         x = np.take(src, np.arange(off, off + n) % src.size).astype(dt)
         if n:
-            x, _, _ = synth.inject_specials(x, max(1, n // 5000), seed + 7 * i, eb)
+            x = synth.with_specials(x, q, max(1, n // 5000), seed + 7 * i, eb)
         out.append(dict(x_np=x, q=q, eb=eb))
     return out
 

@@ -4,13 +4,22 @@ float64 GRF with a 2^20-value adversarial bin-border slice (ABS / NOA at
 1e-6, REL at 1e-4).  The oracle finishes these in seconds, so whole streams
 and decodes are compared -- at eb = 1e-3 under every quantize / dequantize
 launch variant the tuner can pick (the benchmark times whichever wins), and
-for the in-line layout."""
+for the in-line layout.
+
+NOA fields carry special values that keep the base field's range (section
+2.1.3: the bound scales with it), so their bins are the field's real bins:
+each NOA test checks that the stream's bound is the field's eb * R (at most
+4 ulps below it: RD(eb), hi - lo and the product are each rounded and then
+stepped down once) and that most codes are bins other than 0."""
+from fractions import Fraction
+
 import numpy as np
 import pytest
 
 import oracle as O
 import synth
 from gpu_util import announce, bits, first_diff
+from streamcheck import SENT, parse
 
 pytestmark = pytest.mark.gpu
 
@@ -19,8 +28,30 @@ EB = 1e-3
 
 @pytest.fixture(scope="module")
 def fields():
-    x, xr = synth.plain_step_inputs(512, EB)
-    return {"abs": x, "noa": x, "rel": xr}
+    x, xn, xr = synth.plain_step_inputs(512, EB)
+    return {"abs": x, "noa": xn, "rel": xr}
+
+
+@pytest.fixture(scope="module")
+def grf512():
+    """The base grid of the float32 workload (no specials)."""
+    return synth.grf_3d(512, 1, dtype=np.float64).astype(np.float32)
+
+
+def assert_real_noa_range(st, x, eb, min_nonzero):
+    """The NOA stream's bound is eb * R of x's finite values (exactly not
+    above, at most 4 ulps below) and at least min_nonzero of the codes are
+    bins other than 0."""
+    P = parse(st, x.dtype)
+    lo, hi = synth.finite_range(x)
+    exact = Fraction(eb) * (Fraction(hi) - Fraction(lo))
+    ebr = P["hdr"]["bound"]
+    ulp = Fraction(float(np.spacing(ebr)))
+    assert Fraction(float(ebr)) <= exact, (ebr, float(exact))
+    assert exact - Fraction(float(ebr)) <= 4 * ulp, (ebr, float(exact))
+    codes = P["codes"]
+    nz = np.count_nonzero((codes != 0) & (codes != SENT))
+    assert nz >= min_nonzero * x.size, (nz, x.size)
 
 
 @pytest.mark.parametrize("q", ["abs", "noa", "rel"])
@@ -53,6 +84,8 @@ def test_fullsize_every_variant(fields, q):
     finally:
         lcq.tune_set("quantize", torch.float32, saved[0])
         lcq.tune_set("dequantize", torch.float32, saved[1])
+    if q == "noa":
+        assert_real_noa_range(st_o, x, EB, 0.9)
 
 
 @pytest.mark.parametrize("q", ["abs", "noa", "rel"])
@@ -90,16 +123,32 @@ def _compare_default(q, x, eb, label):
     return st_o
 
 
-@pytest.mark.parametrize("q,eb", [("abs", 1e-2), ("abs", 1e-4), ("noa", 1e-2), ("noa", 1e-4),
-                                  ("rel", 1e-2)])
+@pytest.mark.parametrize("q,eb", [("abs", 1e-2), ("abs", 1e-4), ("rel", 1e-2)])
 def test_fullsize_other_bounds(fields, q, eb):
     _compare_default(q, fields[q], eb, "grf512 f32")
 
 
+@pytest.mark.parametrize("eb,min_nonzero", [(1e-2, 0.85), (1e-4, 0.99)])
+def test_fullsize_noa_other_bounds(grf512, eb, min_nonzero):
+    """NOA at the workload's other bounds, each on the base grid with its
+    own range-keeping specials (half-bin neighbours at that eb * R)."""
+    x = synth.plain_noa_field(grf512, eb)
+    st = _compare_default("noa", x, eb, "grf512 f32")
+    assert_real_noa_range(st, x, eb, min_nonzero)
+
+
+def test_fullsize_noa_huge_range_edge(fields):
+    """Edge case: the ABS field's specials include +-FLT_MAX, which stretch
+    NOA's range to the whole type; the bound saturates and nearly every
+    value lands in bin 0, but the bytes are still the oracle's."""
+    st = _compare_default("noa", fields["abs"], EB, "grf512 f32 huge range")
+    assert parse(st, np.float32)["hdr"]["bound"] > 1e35
+
+
 @pytest.fixture(scope="module")
 def fields64():
-    x, xr = synth.f64_grid_inputs()
-    return {"abs": x, "noa": x, "rel": xr}
+    x, xn, xr = synth.f64_grid_inputs()
+    return {"abs": x, "noa": xn, "rel": xr}
 
 
 @pytest.mark.parametrize("q,eb", [("abs", 1e-6), ("noa", 1e-6), ("rel", 1e-4)])
@@ -108,10 +157,12 @@ def test_fullsize_f64_grid_with_adversarial_slice(fields64, q, eb):
     st = _compare_default(q, x, eb, "grf384 f64")
     k = int(st[16:24].view(np.uint64)[0])
     # the bin-border slice sends values through the verify-and-fallback path
-    # (ABS; REL lower side) beyond the injected specials
+    # (ABS and NOA: its values sit at the bin borders of eb, resp. of the
+    # field's own eb * R; REL: the lower side) beyond the injected specials
     nsp = synth.n_specials(x.size, 1e-4)
-    if q != "noa":
-        assert k > nsp, (q, k, nsp)
+    assert k > nsp + 10000, (q, k, nsp)
+    if q == "noa":
+        assert_real_noa_range(st, x, eb, 0.99)
 
 
 def test_fullsize_abs_unchecked_ablation(fields):

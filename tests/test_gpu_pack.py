@@ -76,7 +76,7 @@ def test_pack_equals_oracle_and_roundtrips(case):
 def test_pack_of_gpu_stream_and_errors():
     import torch
     import paper_2407_15037_amd as lcq
-    x, _ = synth.plain_step_inputs(64, 1e-3)
+    x, _, _ = synth.plain_step_inputs(64, 1e-3)
     n = x.size
     announce("pack gpu stream", n)
     buf, nb = lcq.quantize(torch.from_numpy(x).cuda(), "abs", 1e-3)

@@ -29,6 +29,8 @@ def _parity(q, x, eb, label=""):
 
 def _field(dt, n, seed, eb, q):
     x = synth.sines_1d(n, seed, dtype=dt)
+    if q == "noa":  # specials that keep the range, half-bin values at eb * R
+        return synth.with_specials(x, "noa", max(19, n // 1000), seed + 1, eb)
     x, _, _ = synth.inject_specials(x, max(19, n // 1000), seed + 1, eb)
     if q == "rel":
         x = synth.rel_variant(np.nan_to_num(x.astype(np.float64)), seed + 2, dtype=dt)
@@ -43,9 +45,33 @@ def test_parity_mixed(dt, q, eb):
     # several tiles plus a ragged tail, specials, bin-border adversarial values
     n = 5 * 4096 + 777
     x = _field(dt, n, 11, eb, q)
-    adv = synth.adversarial_rel(3000, eb, 12, dt) if q == "rel" else synth.adversarial_abs(3000, eb, 12, dt)
+    if q == "rel":
+        adv = synth.adversarial_rel(3000, eb, 12, dt)
+    elif q == "noa":  # bin borders of the field's own range, which they keep
+        lo, hi = synth.finite_range(x)
+        adv = synth.adversarial_noa(3000, synth.noa_half_bin(x, eb), lo, hi, 12, dt)
+    else:
+        adv = synth.adversarial_abs(3000, eb, 12, dt)
     x = np.concatenate([x, adv]).astype(dt)
-    _parity(q, x, eb)
+    st, _ = _parity(q, x, eb)
+    if q == "noa":
+        # a real range: most codes are bins other than 0, and the border
+        # values send some through the lossless fallback
+        codes = parse(st, dt)["codes"]
+        assert np.count_nonzero((codes != 0) & (codes != SENT)) > x.size // 2
+        assert parse(st, dt)["hdr"]["k"] > max(19, n // 1000)
+
+
+@pytest.mark.parametrize("dt", DTYPES, ids=["f32", "f64"])
+def test_parity_noa_huge_range_edge(dt):
+    """Edge case: finite specials up to +-max stretch NOA's range to the
+    whole type, so the bound saturates and nearly every value lands in bin
+    0; still the oracle's bytes."""
+    n = 5 * 4096 + 777
+    x = synth.sines_1d(n, 13, dtype=dt)
+    x, _, _ = synth.inject_specials(x, max(19, n // 1000), 14, 1e-4)
+    st, _ = _parity("noa", x, 1e-4, "huge range")
+    assert parse(st, dt)["hdr"]["bound"] > np.finfo(dt).max / 1e9
 
 
 @pytest.mark.parametrize("dt", DTYPES, ids=["f32", "f64"])
@@ -243,11 +269,14 @@ def test_status_word_ignores_workspace_contents():
 def test_parity_sines_2_20(q):
     """The small 1-D case at its full size: 2^20 float32 values from the sum
     of 8 sines plus noise, 0.1 % special values (NaN, +-INF, +-0, denormals,
-    half-bin neighbours, bins beyond 2^30), eb = 1e-3; streams and decodes
-    compared whole."""
+    half-bin neighbours, bins beyond 2^30; for NOA only the classes that keep
+    the range), eb = 1e-3; streams and decodes compared whole."""
     n = 1 << 20
     x = synth.sines_1d(n, 1, dtype=np.float32)
-    x, _, _ = synth.inject_specials(x, synth.n_specials(n, 1e-3), 2, 1e-3)
+    if q == "noa":  # the range-keeping mix, half-bin neighbours at eb * R
+        x = synth.with_specials(x, "noa", synth.n_specials(n, 1e-3), 2, 1e-3)
+    else:
+        x, _, _ = synth.inject_specials(x, synth.n_specials(n, 1e-3), 2, 1e-3)
     if q == "rel":
         x = synth.rel_variant(np.nan_to_num(x.astype(np.float64)), 3, dtype=np.float32)
         x, _, _ = synth.inject_specials(x, synth.n_specials(n, 1e-3), 4, 1e-3)
