@@ -59,6 +59,13 @@ def _bind(L):
     L.orc_quantize.restype = i32
     L.orc_dequantize.argtypes = [i32, vp, u64, vp, u64]
     L.orc_dequantize.restype = i32
+    L.orc_quantize_mt.argtypes = [i32, i32, ctypes.c_double, vp, u64, vp, u64,
+                                  ctypes.POINTER(u64), i32]
+    L.orc_quantize_mt.restype = i32
+    L.orc_dequantize_mt.argtypes = [i32, vp, u64, vp, u64, i32]
+    L.orc_dequantize_mt.restype = i32
+    L.orc_threads_used.argtypes = [i32]
+    L.orc_threads_used.restype = i32
     L.orc_inline_stream_bytes.argtypes = [i32, u64]
     L.orc_inline_stream_bytes.restype = u64
     L.orc_quantize_inline.argtypes = [i32, i32, ctypes.c_double, vp, u64, vp, u64, ctypes.POINTER(u64)]
@@ -108,6 +115,40 @@ def quantize(q, x, eb, L=None):
     if st != OK:
         raise OracleError(st, "orc_quantize")
     return buf[: nbytes.value].copy()
+
+
+def quantize_mt(q, x, eb, threads=0, L=None):
+    """quantize() split over `threads` threads at chunk boundaries (0: one
+    per online CPU); the same bytes."""
+    L = L or lib()
+    x = np.ascontiguousarray(x)
+    dt = _dt(x)
+    cap = int(L.orc_max_stream_bytes(dt, x.size))
+    buf = np.empty(cap, dtype=np.uint8)
+    nbytes = ctypes.c_uint64(0)
+    st = L.orc_quantize_mt(_q(q), dt, float(eb), x.ctypes.data, x.size,
+                           buf.ctypes.data, cap, ctypes.byref(nbytes), int(threads))
+    if st != OK:
+        raise OracleError(st, "orc_quantize_mt")
+    return buf[: nbytes.value]
+
+
+def dequantize_mt(stream, dtype, n, threads=0, L=None):
+    """dequantize() split over `threads` threads (0: one per online CPU)."""
+    L = L or lib()
+    stream = np.ascontiguousarray(stream, dtype=np.uint8)
+    out = np.empty(n, dtype=dtype)
+    st = L.orc_dequantize_mt(_dt(out), stream.ctypes.data, stream.size, out.ctypes.data, n,
+                             int(threads))
+    if st != OK:
+        raise OracleError(st, "orc_dequantize_mt")
+    return out
+
+
+def threads_used(threads=0, L=None):
+    """Thread count a `threads` argument of the *_mt calls resolves to."""
+    L = L or lib()
+    return int(L.orc_threads_used(int(threads)))
 
 
 def dequantize(stream, dtype, n, L=None):

@@ -19,7 +19,7 @@ CFLAGS = [
 def build(extra_flags=(), out=SO, quiet=False):
     """Compile lcq_oracle.c with gcc; returns the path of the shared object."""
     cmd = ["gcc", *CFLAGS, *extra_flags, os.path.join(HERE, "lcq_oracle.c"),
-           "-o", out, "-lm"]
+           "-o", out, "-lm", "-lpthread"]
     res = subprocess.run(cmd, capture_output=True, text=True)
     if res.returncode != 0:
         raise RuntimeError("oracle build failed:\n" + " ".join(cmd) + "\n" + res.stderr)

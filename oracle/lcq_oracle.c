@@ -204,7 +204,9 @@ static void noa_range_f64(const double *x, uint64_t n, double *lo, double *hi) {
   *lo = l; *hi = h;
 }
 
-static int derive_f32(int q, double eb, const float *x, uint64_t n, params_t *p) {
+/* Parameters of a float32 field; NOA takes its range (lo, hi) from the
+ * caller. */
+static int derive_f32_range(int q, double eb, float lo, float hi, params_t *p) {
   memset(p, 0, sizeof *p);
   p->q = q;
   if (q == ORC_ABS || q == ORC_ABS_UNCHECKED) {
@@ -230,8 +232,6 @@ static int derive_f32(int q, double eb, const float *x, uint64_t n, params_t *p)
   } else {
     /* sec. 2.1.3: bound eb * R with R = max - min; each rounded step is
      * followed by one step down so that ebR <= eb * R holds exactly. */
-    float lo, hi;
-    noa_range_f32(x, n, &lo, &hi);
     float r = hi - lo;
     if (r == INFINITY) r = 3.40282346638528859812e+38f;
     if (r > 0.0f) r = nextafterf(r, 0.0f);
@@ -254,7 +254,7 @@ static int derive_f32(int q, double eb, const float *x, uint64_t n, params_t *p)
   return ORC_OK;
 }
 
-static int derive_f64(int q, double eb, const double *x, uint64_t n, params_t *p) {
+static int derive_f64_range(int q, double eb, double lo, double hi, params_t *p) {
   memset(p, 0, sizeof *p);
   p->q = q;
   if (q == ORC_ABS || q == ORC_ABS_UNCHECKED) {
@@ -272,8 +272,6 @@ static int derive_f64(int q, double eb, const double *x, uint64_t n, params_t *p
     p->step = lam + lam;
     p->inv = 1.0 / p->step;
   } else {
-    double lo, hi;
-    noa_range_f64(x, n, &lo, &hi);
     double r = hi - lo;
     if (r == INFINITY) r = 1.79769313486231570815e+308;
     if (r > 0.0) r = nextafter(r, 0.0);
@@ -294,6 +292,19 @@ static int derive_f64(int q, double eb, const double *x, uint64_t n, params_t *p
     }
   }
   return ORC_OK;
+}
+
+/* Parameters of a field; NOA first reduces the field's range. */
+static int derive_f32(int q, double eb, const float *x, uint64_t n, params_t *p) {
+  float lo = 0.0f, hi = 0.0f;
+  if (q == ORC_NOA) noa_range_f32(x, n, &lo, &hi);
+  return derive_f32_range(q, eb, lo, hi, p);
+}
+
+static int derive_f64(int q, double eb, const double *x, uint64_t n, params_t *p) {
+  double lo = 0.0, hi = 0.0;
+  if (q == ORC_NOA) noa_range_f64(x, n, &lo, &hi);
+  return derive_f64_range(q, eb, lo, hi, p);
 }
 
 static int is_rel(int q) { return q == ORC_REL || q == ORC_REL_LIBM; }
@@ -830,5 +841,317 @@ int orc_unpack(int dtype, const void *packed, uint64_t bytes, uint64_t n, void *
     }
   }
   *out_bytes = out_offset(n) + s * k;
+  return ORC_OK;
+}
+
+/* ------------------------------------------- chunk-parallel wrapper ------
+ * The same quantize / dequantize, with the values split into contiguous
+ * ranges of whole CHUNKs, one per thread.  Every per-value step is the one
+ * above (encode_f32 / encode_f64, decode_f32 / decode_f64); only the order
+ * in which independent values are visited changes, and the few quantities
+ * that depend on earlier values are put together serially:
+ *   quantize    pass 1 (threads): codes of the range, its outlier count;
+ *               serial: exclusive prefix of the counts;
+ *               pass 2 (threads): chunk-table entries and raw outlier bits
+ *               of the range, from its codes, at its prefix;
+ *               serial: padding and header.
+ *               NOA: the range's finite min / max per thread, combined
+ *               (min / max of finite values, -0 read as +0, do not depend
+ *               on the order), then the parameters as for one thread.
+ *   dequantize  threads: sentinels per range and each chunk-table entry
+ *               against the range's running count; serial: the first entry
+ *               of every range against the prefix of the counts and the
+ *               total against the header's count (together exactly the
+ *               checks of the single-threaded walk); threads: decode.
+ * Output bytes and error statuses equal the single-threaded calls'. */
+#include <pthread.h>
+#include <unistd.h>
+
+#define ORC_MAX_THREADS 256
+
+typedef struct {
+  int dtype;
+  const params_t *p;
+  const uint8_t *in;
+  uint8_t *S;
+  uint64_t n, b, e; /* values [b, e) */
+  uint64_t k;       /* pass 1: outliers of the range; pass 2: first index */
+  float lo32, hi32;
+  double lo64, hi64;
+  int fp_ok;
+} qrange_t;
+
+static void *q_range_minmax(void *arg) {
+  qrange_t *r = (qrange_t *)arg;
+  r->fp_ok = fpenv_ok();
+  if (r->dtype == ORC_F32) noa_range_f32((const float *)r->in + r->b, r->e - r->b, &r->lo32, &r->hi32);
+  else noa_range_f64((const double *)r->in + r->b, r->e - r->b, &r->lo64, &r->hi64);
+  return NULL;
+}
+
+static void *q_range_pass1(void *arg) {
+  qrange_t *r = (qrange_t *)arg;
+  r->fp_ok = fpenv_ok();
+  const uint64_t s = r->dtype == ORC_F64 ? 8 : 4;
+  uint64_t k = 0;
+  for (uint64_t i = r->b; i < r->e; i++) {
+    int32_t code = 0;
+    int outlier;
+    if (r->dtype == ORC_F32) {
+      float x;
+      memcpy(&x, r->in + 4 * i, 4);
+      outlier = encode_f32(r->p, x, &code);
+    } else {
+      double x;
+      memcpy(&x, r->in + 8 * i, 8);
+      outlier = encode_f64(r->p, x, &code);
+    }
+    if (outlier) {
+      code = SENT;
+      k++;
+    }
+    memcpy(r->S + 64 + 4 * i, &code, 4);
+  }
+  (void)s;
+  r->k = k;
+  return NULL;
+}
+
+static void *q_range_pass2(void *arg) {
+  qrange_t *r = (qrange_t *)arg;
+  const uint64_t s = r->dtype == ORC_F64 ? 8 : 4;
+  const uint64_t ct = ct_offset(r->n), out = out_offset(r->n);
+  uint64_t k = r->k;
+  for (uint64_t i = r->b; i < r->e; i++) {
+    if (i % CHUNK == 0) put_u64(r->S + ct + 8 * (i / CHUNK), k);
+    int32_t code;
+    memcpy(&code, r->S + 64 + 4 * i, 4);
+    if (code == SENT) {
+      memcpy(r->S + out + s * k, r->in + s * i, s);
+      k++;
+    }
+  }
+  return NULL;
+}
+
+static int orc_threads(int nthreads) {
+  if (nthreads <= 0) {
+    long c = sysconf(_SC_NPROCESSORS_ONLN);
+    nthreads = c > 0 ? (int)c : 1;
+  }
+  return nthreads > ORC_MAX_THREADS ? ORC_MAX_THREADS : nthreads;
+}
+
+/* Split [0, n) into at most `want` ranges of whole chunks; returns the
+ * number of ranges and fills b[] / e[]. */
+static int split_chunks(uint64_t n, int want, uint64_t *b, uint64_t *e) {
+  const uint64_t C = n_chunks(n);
+  uint64_t parts = (uint64_t)want < C ? (uint64_t)want : C;
+  if (parts == 0) parts = 1;
+  for (uint64_t t = 0; t < parts; t++) {
+    const uint64_t c0 = C * t / parts, c1 = C * (t + 1) / parts;
+    b[t] = c0 * CHUNK < n ? c0 * CHUNK : n;
+    e[t] = c1 * CHUNK < n ? c1 * CHUNK : n;
+  }
+  return (int)parts;
+}
+
+/* Runs fn over ranges[0..m) on m threads (the calling thread takes the
+ * last); returns 0 if every thread started. */
+static int run_ranges(void *(*fn)(void *), void *ranges, size_t stride, int m) {
+  pthread_t th[ORC_MAX_THREADS];
+  int started = 0, ok = 1;
+  for (int t = 0; t < m - 1; t++) {
+    if (pthread_create(&th[t], NULL, fn, (uint8_t *)ranges + stride * (size_t)t) != 0) {
+      ok = 0;
+      break;
+    }
+    started++;
+  }
+  if (ok) fn((uint8_t *)ranges + stride * (size_t)(m - 1));
+  for (int t = 0; t < started; t++) pthread_join(th[t], NULL);
+  return ok ? 0 : -1;
+}
+
+int orc_threads_used(int nthreads) { return orc_threads(nthreads); }
+
+int orc_quantize_mt(int q, int dtype, double eb, const void *in, uint64_t n,
+                    void *stream, uint64_t cap, uint64_t *stream_bytes, int nthreads) {
+  if (!fpenv_ok()) return ORC_ERR_FPENV;
+  int st = check_args(q, dtype, eb);
+  if (st) return st;
+  if (!stream || !stream_bytes || (n > 0 && !in)) return ORC_ERR_ARG;
+  if (n > (1ull << 38)) return ORC_ERR_ARG;
+  if (cap < orc_max_stream_bytes(dtype, n)) return ORC_ERR_CAPACITY;
+
+  const uint64_t s = dtype == ORC_F64 ? 8 : 4;
+  uint8_t *S = (uint8_t *)stream;
+  const uint64_t ct = ct_offset(n), out = out_offset(n);
+  uint64_t b[ORC_MAX_THREADS], e[ORC_MAX_THREADS];
+  const int m = split_chunks(n, orc_threads(nthreads), b, e);
+  qrange_t R[ORC_MAX_THREADS];
+  memset(R, 0, sizeof R);
+  for (int t = 0; t < m; t++) {
+    R[t].dtype = dtype;
+    R[t].in = (const uint8_t *)in;
+    R[t].S = S;
+    R[t].n = n;
+    R[t].b = b[t];
+    R[t].e = e[t];
+  }
+
+  params_t p;
+  if (q == ORC_NOA) {
+    if (run_ranges(q_range_minmax, R, sizeof R[0], m)) return ORC_ERR_ARG;
+    if (dtype == ORC_F32) {
+      float lo = INFINITY, hi = -INFINITY;
+      for (int t = 0; t < m; t++) {
+        if (R[t].lo32 < lo) lo = R[t].lo32;
+        if (R[t].hi32 > hi) hi = R[t].hi32;
+      }
+      derive_f32_range(q, eb, lo, hi, &p);
+    } else {
+      double lo = INFINITY, hi = -INFINITY;
+      for (int t = 0; t < m; t++) {
+        if (R[t].lo64 < lo) lo = R[t].lo64;
+        if (R[t].hi64 > hi) hi = R[t].hi64;
+      }
+      derive_f64_range(q, eb, lo, hi, &p);
+    }
+  } else if (dtype == ORC_F32) {
+    derive_f32_range(q, eb, 0.0f, 0.0f, &p);
+  } else {
+    derive_f64_range(q, eb, 0.0, 0.0, &p);
+  }
+  for (int t = 0; t < m; t++) R[t].p = &p;
+
+  if (run_ranges(q_range_pass1, R, sizeof R[0], m)) return ORC_ERR_ARG;
+  for (int t = 0; t < m; t++)
+    if (!R[t].fp_ok) return ORC_ERR_FPENV;
+  uint64_t k = 0;
+  for (int t = 0; t < m; t++) {
+    const uint64_t kt = R[t].k;
+    R[t].k = k;
+    k += kt;
+  }
+  if (run_ranges(q_range_pass2, R, sizeof R[0], m)) return ORC_ERR_ARG;
+
+  memset(S + 64 + 4 * n, 0, ct - (64 + 4 * n));
+  memset(S + ct + 8 * n_chunks(n), 0, out - (ct + 8 * n_chunks(n)));
+  orc_params o;
+  export_params(dtype, &p, &o);
+  memset(S, 0, 64);
+  put_u32(S + 0, MAGIC);
+  S[4] = 1;
+  S[5] = (uint8_t)dtype;
+  S[6] = (uint8_t)q;
+  S[7] = (uint8_t)LOG2_CHUNK;
+  put_u64(S + 8, n);
+  put_u64(S + 16, k);
+  memcpy(S + 24, &eb, 8);
+  put_u64(S + 32, o.step);
+  put_u64(S + 40, o.bound);
+  put_u64(S + 48, o.aux0);
+  put_u64(S + 56, o.aux1);
+  *stream_bytes = out + s * k;
+  return ORC_OK;
+}
+
+typedef struct {
+  int dtype, q;
+  const uint8_t *S;
+  uint8_t *out;
+  uint64_t n, b, e, k, stepbits;
+  uint64_t sent;   /* sentinels in [b, e) */
+  int table_ok;    /* every chunk entry in the range matches its own walk */
+  int fp_ok;
+} drange_t;
+
+static void *d_range_check(void *arg) {
+  drange_t *r = (drange_t *)arg;
+  const uint64_t ct = ct_offset(r->n);
+  const uint64_t base = r->b < r->e ? get_u64(r->S + ct + 8 * (r->b / CHUNK)) : 0;
+  uint64_t cnt = 0;
+  int ok = 1;
+  for (uint64_t i = r->b; i < r->e; i++) {
+    if (i % CHUNK == 0 && get_u64(r->S + ct + 8 * (i / CHUNK)) - base != cnt) ok = 0;
+    int32_t c;
+    memcpy(&c, r->S + 64 + 4 * i, 4);
+    cnt += c == SENT;
+  }
+  r->sent = cnt;
+  r->table_ok = ok;
+  return NULL;
+}
+
+static void *d_range_decode(void *arg) {
+  drange_t *r = (drange_t *)arg;
+  r->fp_ok = fpenv_ok();
+  const uint64_t s = r->dtype == ORC_F64 ? 8 : 4;
+  const uint64_t ct = ct_offset(r->n), out = out_offset(r->n);
+  uint64_t cursor = r->b < r->e ? get_u64(r->S + ct + 8 * (r->b / CHUNK)) : 0;
+  for (uint64_t i = r->b; i < r->e; i++) {
+    int32_t c;
+    memcpy(&c, r->S + 64 + 4 * i, 4);
+    uint8_t *dst = r->out + s * i;
+    if (c == SENT) {
+      memcpy(dst, r->S + out + s * cursor, s);
+      cursor++;
+    } else if (r->dtype == ORC_F32) {
+      float v = decode_f32(r->q, from32((uint32_t)r->stepbits), c);
+      memcpy(dst, &v, 4);
+    } else {
+      double v = decode_f64(r->q, from64(r->stepbits), c);
+      memcpy(dst, &v, 8);
+    }
+  }
+  return NULL;
+}
+
+int orc_dequantize_mt(int dtype, const void *stream, uint64_t bytes, void *out_v, uint64_t n,
+                      int nthreads) {
+  if (!fpenv_ok()) return ORC_ERR_FPENV;
+  if (dtype != ORC_F32 && dtype != ORC_F64) return ORC_ERR_ARG;
+  if (!stream || (n > 0 && !out_v)) return ORC_ERR_ARG;
+  if (bytes < 64) return ORC_ERR_STREAM;
+  const uint8_t *S = (const uint8_t *)stream;
+  const uint64_t s = dtype == ORC_F64 ? 8 : 4;
+  if (get_u32(S) != MAGIC || S[4] != 1 || S[5] != dtype || S[6] > ORC_REL_LIBM ||
+      S[7] != LOG2_CHUNK)
+    return ORC_ERR_STREAM;
+  if (get_u64(S + 8) != n) return ORC_ERR_STREAM;
+  const uint64_t k = get_u64(S + 16);
+  if (k > n || bytes < out_offset(n) + s * k) return ORC_ERR_STREAM;
+
+  uint64_t b[ORC_MAX_THREADS], e[ORC_MAX_THREADS];
+  const int m = split_chunks(n, orc_threads(nthreads), b, e);
+  drange_t R[ORC_MAX_THREADS];
+  memset(R, 0, sizeof R);
+  for (int t = 0; t < m; t++) {
+    R[t].dtype = dtype;
+    R[t].q = S[6];
+    R[t].S = S;
+    R[t].out = (uint8_t *)out_v;
+    R[t].n = n;
+    R[t].b = b[t];
+    R[t].e = e[t];
+    R[t].k = k;
+    R[t].stepbits = get_u64(S + 32);
+  }
+  if (run_ranges(d_range_check, R, sizeof R[0], m)) return ORC_ERR_ARG;
+  /* the walk's checks: every chunk entry equals the sentinels before it,
+   * and all sentinels together equal the outlier count */
+  const uint64_t ctab = ct_offset(n);
+  uint64_t before = 0;
+  for (int t = 0; t < m; t++) {
+    if (!R[t].table_ok) return ORC_ERR_STREAM;
+    if (R[t].b < R[t].e && get_u64(S + ctab + 8 * (R[t].b / CHUNK)) != before)
+      return ORC_ERR_STREAM;
+    before += R[t].sent;
+  }
+  if (before != k) return ORC_ERR_STREAM;
+  if (run_ranges(d_range_decode, R, sizeof R[0], m)) return ORC_ERR_ARG;
+  for (int t = 0; t < m; t++)
+    if (!R[t].fp_ok) return ORC_ERR_FPENV;
   return ORC_OK;
 }

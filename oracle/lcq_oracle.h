@@ -4,8 +4,9 @@
  * Error Bound in Lossy Quantizers", CoDaC'24).
  *
  * TEST INFRASTRUCTURE ONLY.  This library is a plain, slow, single-threaded
- * C implementation that the tests, the smoke check and the benchmark's CPU
- * baseline compare the HIP library against.  The product path never links,
+ * C implementation (plus a chunk-parallel wrapper of the same steps) that
+ * the tests, the smoke check and the benchmark's CPU baseline compare the
+ * HIP library against.  The product path never links,
  * loads or calls it.  It shares no code, header or constant with the HIP
  * library: both are written independently from the same definitions.
  *
@@ -13,7 +14,7 @@
  * (they are a file format, so they must agree byte for byte).
  *
  * Every function is synchronous, uses host pointers only and allocates
- * nothing.  It refuses to run (ORC_ERR_FPENV) unless the x87/SSE control
+ * nothing (the chunk-parallel wrapper starts threads).  It refuses to run (ORC_ERR_FPENV) unless the x87/SSE control
  * state is round-to-nearest with flush-to-zero and denormals-are-zero off,
  * so that every float operation is the IEEE-754 one the paper relies on
  * (section 3.2).
@@ -66,6 +67,18 @@ int orc_quantize(int q, int dtype, double eb, const void *in, uint64_t n,
  * same format) into out[0..n). */
 int orc_dequantize(int dtype, const void *stream, uint64_t bytes, void *out,
                    uint64_t n);
+
+/* Chunk-parallel wrapper: the same computation as orc_quantize /
+ * orc_dequantize, with the values split at CHUNK boundaries over nthreads
+ * threads (<= 0: one per online CPU, at most 256); output bytes and status
+ * codes equal the single-threaded calls'.  orc_threads_used reports the
+ * thread count a given nthreads resolves to (ranges never outnumber the
+ * chunks, so a small field may use fewer). */
+int orc_quantize_mt(int q, int dtype, double eb, const void *in, uint64_t n,
+                    void *stream, uint64_t cap, uint64_t *stream_bytes, int nthreads);
+int orc_dequantize_mt(int dtype, const void *stream, uint64_t bytes, void *out,
+                      uint64_t n, int nthreads);
+int orc_threads_used(int nthreads);
 
 /* The two approximations of section 3.2, element-wise over arrays, exposed
  * so the tests can pin them. */
