@@ -217,8 +217,10 @@ typedef struct {
   void *d_stream;            /* quantize output / dequantize input            */
   uint64_t stream_cap;       /* >= lcq_max_stream_bytes(t, n)                 */
   uint64_t *d_stream_bytes;  /* receives the stream size (device u64)         */
-  void *d_out;               /* dequantize output, n values (may be null if   */
-                             /* the plan is only used to quantize)            */
+  void *d_out;               /* dequantize output, n values; may be null if   */
+                             /* the plan is only used to quantize (then       */
+                             /* lcq_batch_dequantize returns LCQ_ERR_ARG and  */
+                             /* launches nothing)                             */
 } lcq_field;
 
 typedef struct lcq_batch_plan lcq_batch_plan;
@@ -240,7 +242,9 @@ lcq_status lcq_batch_plan_create(const lcq_field *f, uint32_t nf, const char *tu
                                  void *d_ws, uint64_t ws_bytes, hipStream_t stream,
                                  lcq_batch_plan **out);
 
-/* Quantize / dequantize every field of the plan: one hipGraphLaunch on s. */
+/* Quantize / dequantize every field of the plan: one hipGraphLaunch on s.
+ * lcq_batch_dequantize returns LCQ_ERR_ARG, before any launch, for a plan
+ * with a field of n > 0 values whose d_out is null. */
 lcq_status lcq_batch_quantize(lcq_batch_plan *p, hipStream_t s);
 lcq_status lcq_batch_dequantize(lcq_batch_plan *p, hipStream_t s);
 
@@ -256,7 +260,10 @@ void lcq_batch_plan_destroy(lcq_batch_plan *p);
  * n_streams HIP streams is free and its output and workspace fit in the
  * device arena; admitted requests run concurrently; completions free their
  * slot and memory at once.  Every output is compared on the device with the
- * caller's expected bytes.  Blocking; host-side single loop.
+ * caller's expected bytes.  Blocking; host-side single loop.  Ordering: the
+ * call first waits for all work already queued on the device (any stream),
+ * so inputs, expected bytes and the arena may come from pending work; it
+ * returns after every request's work has finished.
  */
 typedef struct {
   int32_t op;             /* 0 = quantize, 1 = dequantize                      */

@@ -112,6 +112,19 @@ def _stream_handle(stream):
     return ctypes.c_void_p(stream.cuda_stream)
 
 
+def _empty(numel, dtype, device, stream, zero=False):
+    """A buffer a call on `stream` uses.  It is allocated on that stream, so
+    torch's caching allocator cannot hand its memory to work on another
+    stream while the call's kernels may still run (a temporary dropped when
+    the wrapper returns is only reused by later work on the same stream)."""
+    import torch
+    make = torch.zeros if zero else torch.empty
+    if stream is None:
+        return make(numel, dtype=dtype, device=device)
+    with torch.cuda.stream(stream):
+        return make(numel, dtype=dtype, device=device)
+
+
 def max_stream_bytes(dtype, n):
     return int(_lib.lcq_max_stream_bytes(_dtype_code(dtype), n))
 
@@ -137,12 +150,11 @@ def quantize(x, q, eb, *, out=None, nbytes=None, ws=None, stream=None):
     n = x.numel()
     cap = int(_lib.lcq_max_stream_bytes(dt, n))
     if out is None:
-        out = torch.empty(cap, dtype=torch.uint8, device=x.device)
+        out = _empty(cap, torch.uint8, x.device, stream)
     if nbytes is None:
-        nbytes = torch.empty(1, dtype=torch.int64, device=x.device)
+        nbytes = _empty(1, torch.int64, x.device, stream)
     if ws is None:
-        ws = torch.empty(int(_lib.lcq_workspace_bytes(_q(q), dt, n)), dtype=torch.uint8,
-                         device=x.device)
+        ws = _empty(int(_lib.lcq_workspace_bytes(_q(q), dt, n)), torch.uint8, x.device, stream)
     st = _lib.lcq_quantize(_q(q), dt, float(eb), _ptr(x) if n else None, n, _ptr(out),
                            out.numel(), _ptr(nbytes), _ptr(ws), ws.numel(),
                            _stream_handle(stream))
@@ -156,9 +168,9 @@ def dequantize(stream_buf, dtype, n, *, stream_bytes=None, out=None, ws=None, st
     import torch
     dt = _dtype_code(dtype)
     if out is None:
-        out = torch.empty(n, dtype=dtype, device=stream_buf.device)
+        out = _empty(n, dtype, stream_buf.device, stream)
     if ws is None:
-        ws = torch.empty(64, dtype=torch.uint8, device=stream_buf.device)
+        ws = _empty(64, torch.uint8, stream_buf.device, stream)
     sb = stream_buf.numel() if stream_bytes is None else int(stream_bytes)
     st = _lib.lcq_dequantize(dt, _ptr(stream_buf), sb, _ptr(out) if n else None, n, _ptr(ws),
                              ws.numel(), _stream_handle(stream))
@@ -180,13 +192,12 @@ def quantize_ablation(x, kind, eb, *, out=None, nbytes=None, ws=None, stream=Non
     n = x.numel()
     k = _abl(kind)
     if out is None:
-        out = torch.empty(int(_lib.lcq_max_stream_bytes(dt, n)), dtype=torch.uint8, device=x.device)
+        out = _empty(int(_lib.lcq_max_stream_bytes(dt, n)), torch.uint8, x.device, stream)
     if nbytes is None:
-        nbytes = torch.empty(1, dtype=torch.int64, device=x.device)
+        nbytes = _empty(1, torch.int64, x.device, stream)
     if ws is None:
         base = ABS if k == ABL_ABS_UNCHECKED else REL
-        ws = torch.empty(int(_lib.lcq_workspace_bytes(base, dt, n)), dtype=torch.uint8,
-                         device=x.device)
+        ws = _empty(int(_lib.lcq_workspace_bytes(base, dt, n)), torch.uint8, x.device, stream)
     st = _lib.lcq_quantize_ablation(k, dt, float(eb), _ptr(x) if n else None, n, _ptr(out),
                                     out.numel(), _ptr(nbytes), _ptr(ws), ws.numel(),
                                     _stream_handle(stream))
@@ -200,9 +211,9 @@ def dequantize_ablation(stream_buf, kind, dtype, n, *, stream_bytes=None, out=No
     import torch
     dt = _dtype_code(dtype)
     if out is None:
-        out = torch.empty(n, dtype=dtype, device=stream_buf.device)
+        out = _empty(n, dtype, stream_buf.device, stream)
     if ws is None:
-        ws = torch.empty(64, dtype=torch.uint8, device=stream_buf.device)
+        ws = _empty(64, torch.uint8, stream_buf.device, stream)
     sb = stream_buf.numel() if stream_bytes is None else int(stream_bytes)
     st = _lib.lcq_dequantize_ablation(_abl(kind), dt, _ptr(stream_buf), sb, _ptr(out) if n else None,
                                       n, _ptr(ws), ws.numel(), _stream_handle(stream))
@@ -225,11 +236,11 @@ def pack(stream_buf, dtype, n, *, stream_bytes=None, out=None, nbytes=None, ws=N
     import torch
     dt = _dtype_code(dtype)
     if out is None:
-        out = torch.empty(pack_max_bytes(dtype, n), dtype=torch.uint8, device=stream_buf.device)
+        out = _empty(pack_max_bytes(dtype, n), torch.uint8, stream_buf.device, stream)
     if nbytes is None:
-        nbytes = torch.empty(1, dtype=torch.int64, device=stream_buf.device)
+        nbytes = _empty(1, torch.int64, stream_buf.device, stream)
     if ws is None:
-        ws = torch.empty(pack_workspace_bytes(dtype, n), dtype=torch.uint8, device=stream_buf.device)
+        ws = _empty(pack_workspace_bytes(dtype, n), torch.uint8, stream_buf.device, stream)
     sb = stream_buf.numel() if stream_bytes is None else int(stream_bytes)
     st = _lib.lcq_pack(dt, _ptr(stream_buf), sb, n, _ptr(out), out.numel(), _ptr(nbytes),
                        _ptr(ws), ws.numel(), _stream_handle(stream))
@@ -242,11 +253,11 @@ def unpack(packed_buf, dtype, n, *, packed_bytes=None, out=None, nbytes=None, ws
     import torch
     dt = _dtype_code(dtype)
     if out is None:
-        out = torch.empty(max_stream_bytes(dtype, n), dtype=torch.uint8, device=packed_buf.device)
+        out = _empty(max_stream_bytes(dtype, n), torch.uint8, packed_buf.device, stream)
     if nbytes is None:
-        nbytes = torch.empty(1, dtype=torch.int64, device=packed_buf.device)
+        nbytes = _empty(1, torch.int64, packed_buf.device, stream)
     if ws is None:
-        ws = torch.empty(64, dtype=torch.uint8, device=packed_buf.device)
+        ws = _empty(64, torch.uint8, packed_buf.device, stream)
     pb = packed_buf.numel() if packed_bytes is None else int(packed_bytes)
     st = _lib.lcq_unpack(dt, _ptr(packed_buf), pb, n, _ptr(out), out.numel(), _ptr(nbytes),
                          _ptr(ws), ws.numel(), _stream_handle(stream))
@@ -267,7 +278,7 @@ def decompress(packed, dtype, n, *, stream=None):
     """Unpack then dequantize a compress() result; raises LCQError if either
     stage finds the stream inconsistent."""
     import torch
-    ws = torch.zeros(64, dtype=torch.uint8, device=packed.device)
+    ws = _empty(64, torch.uint8, packed.device, stream, zero=True)
     st, nb = unpack(packed, dtype, n, ws=ws, stream=stream)
     _check(stream_status(ws, stream), "lcq_unpack")
     out = dequantize(st, dtype, n, ws=ws, stream=stream)
@@ -293,11 +304,9 @@ def quantize_inline(x, q, eb, *, out=None, ws=None, stream=None):
     dt = _dtype_code(x.dtype)
     n = x.numel()
     if out is None:
-        out = torch.empty(int(_lib.lcq_inline_stream_bytes(dt, n)), dtype=torch.uint8,
-                          device=x.device)
+        out = _empty(int(_lib.lcq_inline_stream_bytes(dt, n)), torch.uint8, x.device, stream)
     if ws is None:
-        ws = torch.empty(int(_lib.lcq_inline_workspace_bytes(_q(q))), dtype=torch.uint8,
-                         device=x.device)
+        ws = _empty(int(_lib.lcq_inline_workspace_bytes(_q(q))), torch.uint8, x.device, stream)
     st = _lib.lcq_quantize_inline(_q(q), dt, float(eb), _ptr(x) if n else None, n, _ptr(out),
                                   out.numel(), _ptr(ws), ws.numel(), _stream_handle(stream))
     _check(st, "lcq_quantize_inline")
@@ -310,9 +319,9 @@ def dequantize_inline(stream_buf, dtype, n, *, out=None, ws=None, stream=None):
     import torch
     dt = _dtype_code(dtype)
     if out is None:
-        out = torch.empty(n, dtype=dtype, device=stream_buf.device)
+        out = _empty(n, dtype, stream_buf.device, stream)
     if ws is None:
-        ws = torch.empty(64, dtype=torch.uint8, device=stream_buf.device)
+        ws = _empty(64, torch.uint8, stream_buf.device, stream)
     st = _lib.lcq_dequantize_inline(dt, _ptr(stream_buf), stream_buf.numel(),
                                     _ptr(out) if n else None, n, _ptr(ws), ws.numel(),
                                     _stream_handle(stream))

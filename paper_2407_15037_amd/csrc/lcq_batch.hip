@@ -498,6 +498,7 @@ lcq_status launch_batch_quantize(int bv, const BatchQArgs *a, unsigned grid, hip
 struct lcq_batch_plan {
   int variant;
   uint32_t nf;
+  bool can_decode;  // every field with values has a decode buffer
   uint8_t *ws;
   Layout L;
   Counts c;
@@ -625,6 +626,9 @@ lcq_status lcq_batch_plan_create(const lcq_field *f, uint32_t nf, const char *tu
   if (!p) return LCQ_ERR_ARG;
   p->variant = bv;
   p->nf = nf;
+  p->can_decode = true;
+  for (uint32_t i = 0; i < nf; i++)
+    if (f[i].n && !f[i].d_out) p->can_decode = false;
   p->ws = ws;
   p->L = L;
   p->c = c;
@@ -700,7 +704,7 @@ lcq_status lcq_batch_quantize(lcq_batch_plan *p, hipStream_t s) {
 }
 
 lcq_status lcq_batch_dequantize(lcq_batch_plan *p, hipStream_t s) {
-  if (!p) return LCQ_ERR_ARG;
+  if (!p || !p->can_decode) return LCQ_ERR_ARG;
   return hipGraphLaunch(p->ed, s) == hipSuccess ? LCQ_OK : LCQ_ERR_HIP;
 }
 

@@ -125,6 +125,10 @@ extern "C" lcq_status lcq_serve(const lcq_server_config *cfg, const lcq_request 
     // the compare must stay inside the output buffer
     if (R.op == 0 && R.d_expect && R.expect_bytes > lcq_max_stream_bytes(R.t, R.n)) return LCQ_ERR_ARG;
   }
+  // inputs, expected bytes and arena memory may still be produced (or, for
+  // recycled memory, read) by work queued on other streams; the request
+  // streams below do not order after them, so wait for it all first
+  if (hipDeviceSynchronize() != hipSuccess) return LCQ_ERR_HIP;
   const uint32_t S = cfg->n_streams;
   std::vector<hipStream_t> streams(S, nullptr);
   std::vector<hipEvent_t> events(S, nullptr);
