@@ -551,6 +551,7 @@ int orc_dequantize(int dtype, const void *stream, uint64_t bytes, void *out_v,
       memcpy(dst, &v, 8);
     }
   }
+  /* ASAN-CONTROL: dequantize output end */
   if (cursor != k) return ORC_ERR_STREAM;
   return ORC_OK;
 }
