@@ -87,6 +87,30 @@ lcq_status lcq_quantize(lcq_quantizer q, lcq_dtype t, double eb,
                         uint64_t *d_stream_bytes,
                         void *d_ws, uint64_t ws_bytes, hipStream_t stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): as
+ * lcq_quantize, but the workspace is a fixed array of
+ * LCQ_NOALLOC_SCRATCH_BYTES inside the library, one per GPU, reserved when
+ * the library's code is loaded on that GPU and held until the process ends.
+ * The caller passes the input, the stream buffer and the size word as for
+ * lcq_quantize.  The call allocates nothing; its first call on a device
+ * looks the array's address up once.
+ *  - LCQ_ERR_CAPACITY when lcq_workspace_bytes(q, t, n) exceeds
+ *    LCQ_NOALLOC_SCRATCH_BYTES (float32: up to about 2.6e8 values, float64:
+ *    about 1.3e8), checked on the host before anything is launched;
+ *    LCQ_ERR_HIP if the array's address cannot be found.  Other errors as
+ *    for lcq_quantize.
+ *  - Every call on one GPU shares that GPU's array: calls that overlap on
+ *    one GPU (different streams, or host threads without ordering) race and
+ *    give undefined streams.  Calls ordered on one stream are safe; each
+ *    clears the state it needs, so the previous call's leftovers are
+ *    harmless. */
+#define LCQ_NOALLOC_SCRATCH_BYTES (32ull << 20)
+lcq_status lcq_quantize_noalloc(lcq_quantizer q, lcq_dtype t, double eb,
+                                const void *d_in, uint64_t n,
+                                void *d_stream, uint64_t stream_cap,
+                                uint64_t *d_stream_bytes, hipStream_t stream);
+
 /* Decode a stream into d_out[0..n) of type t (the decoder has no
  * double-check, section 6).  stream_bytes is the number of valid bytes at
  * d_stream; the host checks that the codes and chunk table of n values fit.

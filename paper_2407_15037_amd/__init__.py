@@ -9,7 +9,7 @@ import ctypes
 import os
 
 __all__ = ["ABS", "REL", "NOA", "F32", "F64", "LCQError", "lib", "max_stream_bytes",
-           "workspace_bytes", "quantize", "dequantize", "stream_status", "profile_events",
+           "workspace_bytes", "quantize", "quantize_noalloc", "NOALLOC_SCRATCH_BYTES", "dequantize", "stream_status", "profile_events",
            "set_lookback_spin", "tune_variants", "tune_set", "tune_get",
            "inline_stream_bytes", "inline_workspace_bytes", "quantize_inline",
            "quantize_ablation", "dequantize_ablation", "ABL_ABS_UNCHECKED", "ABL_REL_LIBM",
@@ -39,6 +39,9 @@ _lib.lcq_workspace_bytes.argtypes = [_i32, _i32, _u64]
 _lib.lcq_workspace_bytes.restype = _u64
 _lib.lcq_quantize.argtypes = [_i32, _i32, _dbl, _vp, _u64, _vp, _u64, _vp, _vp, _u64, _vp]
 _lib.lcq_quantize.restype = _i32
+_lib.lcq_quantize_noalloc.argtypes = [_i32, _i32, _dbl, _vp, _u64, _vp, _u64, _vp, _vp]
+_lib.lcq_quantize_noalloc.restype = _i32
+NOALLOC_SCRATCH_BYTES = 32 << 20  # LCQ_NOALLOC_SCRATCH_BYTES of include/lcq.h
 _lib.lcq_dequantize.argtypes = [_i32, _vp, _u64, _vp, _u64, _vp, _u64, _vp]
 _lib.lcq_dequantize.restype = _i32
 _lib.lcq_inline_stream_bytes.argtypes = [_i32, _u64]
@@ -159,6 +162,21 @@ def quantize(x, q, eb, *, out=None, nbytes=None, ws=None, stream=None):
                            out.numel(), _ptr(nbytes), _ptr(ws), ws.numel(),
                            _stream_handle(stream))
     _check(st, "lcq_quantize")
+    return out, nbytes
+
+
+def quantize_noalloc(x, q, eb, *, out, nbytes, stream=None):
+    """quantize() with the library's fixed per-GPU workspace
+    (lcq_quantize_noalloc): the caller passes the stream buffer `out` (uint8,
+    at least max_stream_bytes) and the size word `nbytes` (int64, one
+    element); nothing is allocated.  Calls that overlap on one GPU race."""
+    if not x.is_cuda or not x.is_contiguous():
+        raise ValueError("x must be a contiguous CUDA tensor")
+    dt = _dtype_code(x.dtype)
+    n = x.numel()
+    st = _lib.lcq_quantize_noalloc(_q(q), dt, float(eb), _ptr(x) if n else None, n, _ptr(out),
+                                   out.numel(), _ptr(nbytes), _stream_handle(stream))
+    _check(st, "lcq_quantize_noalloc")
     return out, nbytes
 
 

@@ -21,6 +21,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 
 #include "lcq.h"
 #include "lcq_host.hpp"
@@ -561,6 +562,35 @@ uint64_t ws_need_inline(lcq_quantizer q) {
 
 }  // namespace
 
+// ------------------------------------------------- allocation-free form ---
+// The quantize workspace of lcq_quantize_noalloc: one fixed array per GPU,
+// reserved when the code object is loaded and held until the process ends.
+// On the host, `scratch` is only a stand-in for the symbol, not a device
+// address; host code uses the address hipGetSymbolAddress returns for the
+// current device (each GPU holds its own copy at its own address).
+static __device__ __align__(256) uint8_t scratch[LCQ_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_dev[kMaxDevices] = {};
+
+// Device address of `scratch` on the current device, looked up once per
+// device (with that device current) and kept.
+lcq_status scratch_address(void **out) {
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return LCQ_ERR_HIP;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_dev[dev]) {
+    void *p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return LCQ_ERR_HIP;
+    g_scratch_dev[dev] = p;
+  }
+  *out = g_scratch_dev[dev];
+  return LCQ_OK;
+}
+}  // namespace
+
 // ------------------------------------------------------------------- ABI ---
 extern "C" {
 
@@ -601,6 +631,23 @@ lcq_status lcq_quantize(lcq_quantizer q, lcq_dtype t, double eb, const void *d_i
     case LCQ_REL: return run_quantize<double, kREL>(eb, d_in, n, d_stream, d_stream_bytes, d_ws, stream);
     default: return run_quantize<double, kNOA>(eb, d_in, n, d_stream, d_stream_bytes, d_ws, stream);
   }
+}
+
+lcq_status lcq_quantize_noalloc(lcq_quantizer q, lcq_dtype t, double eb, const void *d_in,
+                                uint64_t n, void *d_stream, uint64_t stream_cap,
+                                uint64_t *d_stream_bytes, hipStream_t stream) {
+  if (q != LCQ_ABS && q != LCQ_REL && q != LCQ_NOA) return LCQ_ERR_ARG;
+  if (t != LCQ_F32 && t != LCQ_F64) return LCQ_ERR_ARG;
+  if (n > LCQ_MAX_N) return LCQ_ERR_ARG;
+  if (ws_need(q, t, n) > LCQ_NOALLOC_SCRATCH_BYTES) return LCQ_ERR_CAPACITY;
+  void *ws = nullptr;
+  const lcq_status st = scratch_address(&ws);
+  if (st != LCQ_OK) return st;
+  // every word of the workspace a quantize reads is written earlier in the
+  // same call (group sums and look-back words are cleared by its first
+  // kernel), so what the previous call left in the array does not matter
+  return lcq_quantize(q, t, eb, d_in, n, d_stream, stream_cap, d_stream_bytes, ws,
+                      LCQ_NOALLOC_SCRATCH_BYTES, stream);
 }
 
 lcq_status lcq_dequantize(lcq_dtype t, const void *d_stream, uint64_t stream_bytes, void *d_out,
