@@ -131,3 +131,42 @@ def load_or_tune(path=None, **kw):
     except OSError:
         pass
     return table
+
+
+def tune_batch(fields, reps=3, log=None):
+    """Pick the batch plan's tuning string for a set of fields (dicts with
+    x, q, eb as for batch.BatchPlan): each batch variant's quantize graph is
+    timed on the fields themselves (512 MiB written and 512 MiB read to
+    evict the caches before every run, median of `reps` after one untimed
+    run), the fastest wins.
+    Returns {"tune": string for lcq_batch_plan_create, "best": variant,
+    "quantize_ms": [median per variant]}."""
+    import torch
+    from paper_2407_15037_amd.batch import BatchPlan, variants
+    scratch = torch.empty(512 << 20, dtype=torch.uint8, device="cuda")
+    clean = torch.ones(64 << 20, dtype=torch.int64, device="cuda")
+    ms = []
+    for v in range(variants()):
+        plan = BatchPlan(fields, tune=f"batch={v}")
+        ts = []
+        for r in range(reps + 1):
+            scratch.fill_(0x5A)  # evict the caches: 512 MiB written, 512 MiB read
+            clean.sum()
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record()
+            plan.quantize()
+            e1.record()
+            torch.cuda.synchronize()
+            if r:
+                ts.append(e0.elapsed_time(e1))
+        ts.sort()
+        ms.append(round(ts[len(ts) // 2], 3))
+        plan.close()
+        del plan
+        torch.cuda.empty_cache()
+    best = min(range(len(ms)), key=lambda i: ms[i])
+    out = {"tune": f"batch={best}", "best": best, "quantize_ms": ms}
+    if log:
+        log(f"batch autotune (quantize ms per variant): {ms} -> {best}")
+    return out

@@ -42,9 +42,11 @@ def variants():
 
 class BatchPlan:
     """fields: list of dicts with keys x (CUDA tensor), q, eb, and optionally
-    out (decode tensor), stream (uint8 tensor), nbytes (int64 tensor)."""
+    out (decode tensor), stream (uint8 tensor), nbytes (int64 tensor).
+    tune: the plan's tuning string (lcq_batch_plan_create), e.g. the one
+    autotune.tune_batch returns; default "batch=<variant>"."""
 
-    def __init__(self, fields, variant=0, stream=None):
+    def __init__(self, fields, variant=0, stream=None, tune=None):
         import torch
         self.fields = []
         arr = (Field * max(len(fields), 1))()
@@ -68,7 +70,7 @@ class BatchPlan:
                            x.data_ptr() if n else None, n, st.data_ptr(), st.numel(),
                            nb.data_ptr(), out.data_ptr() if n else None)
             self.fields.append(dict(x=x, q=f["q"], eb=f["eb"], stream=st, nbytes=nb, out=out))
-        tune = f"batch={int(variant)}".encode()
+        tune = (tune if tune is not None else f"batch={int(variant)}").encode()
         self._arr = arr
         need = int(_L.lcq_batch_workspace_bytes(arr, len(fields), tune))
         if need == 0:

@@ -5,8 +5,13 @@ every decoded value must satisfy its bound (special values bit-exact), and
 the GPU stream of every 2^28-value chunk must equal the CPU oracle's (compared
 by digest, oracle chunks run in a process pool).
 
-Opt-in: runs only with LCQ_EXHAUSTIVE=1 (about 5 minutes on one MI355X machine
-with 16 host cores); the default GPU suite skips it.
+The full sweep is opt-in: it runs only with LCQ_EXHAUSTIVE=1 (about 5 minutes
+on one MI355X machine with 16 host cores).  The reduced sweep runs by
+default: every exponent field, both signs, the fraction fields k * 61 plus
+the edge fractions (0, 1, 2, 2^22, 2^23 - 2, 2^23 - 1) -- 70.4 million
+patterns, every class of value (zeros, denormals, normals of every binade,
+infinities, NaNs) -- through the same checks, stream and decode compared with
+the oracle's by digest.
 """
 import hashlib
 import os
@@ -39,11 +44,25 @@ def _gpu_check(q, eb, c, lcq, torch):
     base = torch.arange(c * CHUNK, (c + 1) * CHUNK, dtype=torch.int64, device="cuda")
     xb = (base & 0xFFFFFFFF).to(torch.int32)
     del base
+    dg, nviol, k, _ = _gpu_check_bits(q, eb, xb, lcq, torch)
+    return dg, nviol, k
+
+
+def _digest(a):
+    return hashlib.blake2b(np.ascontiguousarray(a).tobytes(), digest_size=16).hexdigest()
+
+
+def _gpu_check_bits(q, eb, xb, lcq, torch):
+    """Quantize + dequantize the float32 bit patterns xb (int32 CUDA tensor)
+    on the GPU; every decoded value checked against its bound (specials
+    bit-exact).  Returns (stream digest, violations, outliers, decode
+    digest)."""
     x = xb.view(torch.float32)
+    m = x.numel()
     buf, nb = lcq.quantize(x, q, eb)
     torch.cuda.synchronize()
     size = int(nb.item())
-    dec = lcq.dequantize(buf, torch.float32, CHUNK, stream_bytes=size)
+    dec = lcq.dequantize(buf, torch.float32, m, stream_bytes=size)
     u = xb.view(torch.int32).to(torch.int64) & 0xFFFFFFFF
     e = (u >> 23) & 0xFF
     frac = u & 0x7FFFFF
@@ -71,8 +90,39 @@ def _gpu_check(q, eb, c, lcq, torch):
                       (ad * (1 + eb) < a * (1 - 2 ** -50)) | (dec == 0))
     nviol = int(viol.sum().item()) + bad
     k = int(buf[16:24].cpu().numpy().view(np.uint64)[0])
-    host = buf[:size].cpu().numpy()
-    return hashlib.blake2b(host.tobytes(), digest_size=16).hexdigest(), nviol, k
+    return _digest(buf[:size].cpu().numpy()), nviol, k, _digest(dec.cpu().numpy())
+
+
+def _strided_patterns(stride=61):
+    """Every exponent field and sign with the fraction fields k * stride and
+    the edge fractions, as uint32 bit patterns."""
+    fr = np.arange(0, 1 << 23, stride, dtype=np.uint32)
+    fr = np.unique(np.concatenate([fr, np.array([0, 1, 2, 1 << 22, (1 << 23) - 2, (1 << 23) - 1],
+                                                dtype=np.uint32)]))
+    ex = np.arange(256, dtype=np.uint32) << 23
+    mag = (ex[:, None] | fr[None, :]).ravel()
+    return np.concatenate([mag, mag | np.uint32(0x80000000)])
+
+
+@pytest.mark.timeout(600)
+@pytest.mark.parametrize("q", ["abs", "rel", "noa"])
+def test_strided_float32_sweep(q):
+    import torch
+    import oracle as O
+    import paper_2407_15037_amd as lcq
+    from gpu_util import announce
+    pat = _strided_patterns()
+    xh = pat.view(np.float32)
+    xb = torch.from_numpy(pat.view(np.int32)).cuda()
+    for eb in EBS:
+        announce("strided float32 sweep", q, eb, pat.size)
+        dg, nviol, k, ddg = _gpu_check_bits(q, eb, xb, lcq, torch)
+        assert nviol == 0, (q, eb, nviol)
+        st = O.quantize_mt(q, xh, eb)
+        assert dg == _digest(st), (q, eb, "GPU stream differs from the oracle's")
+        assert ddg == _digest(O.dequantize_mt(st, np.float32, xh.size)), (
+            q, eb, "GPU decode differs from the oracle's")
+        assert k > 0  # specials are always stored losslessly
 
 
 @pytest.mark.skipif(os.environ.get("LCQ_EXHAUSTIVE") != "1",
