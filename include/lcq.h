@@ -61,14 +61,20 @@ typedef enum {
 /* Largest n any entry point accepts (2^38 values). */
 #define LCQ_MAX_N (1ull << 38)
 
-/* Worst-case size in bytes of a stream of n values (every value an outlier);
- * the capacity lcq_quantize requires.  Returns 0 for a bad dtype or n. */
+/* Worst-case size in bytes of a stream of n values: every value stored
+ * losslessly (section 3.1: a value whose double-check fails keeps its
+ * original bits, and nothing bounds how many fail), plus the header and
+ * chunk table of the format above.  The capacity lcq_quantize requires.
+ * Returns 0 for a bad dtype or n. */
 uint64_t lcq_max_stream_bytes(lcq_dtype t, uint64_t n);
 
 /* Bytes of device workspace lcq_quantize / lcq_dequantize need for n values
- * of type t under quantizer q.  The workspace needs no initialisation; its
- * first 8 bytes hold the status word of the last lcq_dequantize (each decode
- * call tags the word with its own epoch and replaces whatever it held). */
+ * of type t under quantizer q.  No passage of the paper defines it: it is
+ * this library's GPU scratch (outlier counts, staged outliers and group sums
+ * of the outlier compaction, NOA's per-workgroup range pairs).  The
+ * workspace needs no initialisation; its first 8 bytes hold the status word
+ * of the last lcq_dequantize (each decode call tags the word with its own
+ * epoch and replaces whatever it held). */
 uint64_t lcq_workspace_bytes(lcq_quantizer q, lcq_dtype t, uint64_t n);
 
 /* Quantize d_in[0..n) of type t under bound eb (sections 2.1, 3.1-3.3).
@@ -97,7 +103,7 @@ lcq_status lcq_quantize(lcq_quantizer q, lcq_dtype t, double eb,
  * looks the array's address up once.
  *  - LCQ_ERR_CAPACITY when lcq_workspace_bytes(q, t, n) exceeds
  *    LCQ_NOALLOC_SCRATCH_BYTES (float32: up to about 2.6e8 values, float64:
- *    about 1.3e8), checked on the host before anything is launched;
+ *    about 6.5e7), checked on the host before anything is launched;
  *    LCQ_ERR_HIP if the array's address cannot be found.  Other errors as
  *    for lcq_quantize.
  *  - Every call on one GPU shares that GPU's array: calls that overlap on
@@ -105,7 +111,7 @@ lcq_status lcq_quantize(lcq_quantizer q, lcq_dtype t, double eb,
  *    give undefined streams.  Calls ordered on one stream are safe; each
  *    clears the state it needs, so the previous call's leftovers are
  *    harmless. */
-#define LCQ_NOALLOC_SCRATCH_BYTES (32ull << 20)
+#define LCQ_NOALLOC_SCRATCH_BYTES (128ull << 20)
 lcq_status lcq_quantize_noalloc(lcq_quantizer q, lcq_dtype t, double eb,
                                 const void *d_in, uint64_t n,
                                 void *d_stream, uint64_t stream_cap,
@@ -123,7 +129,10 @@ lcq_status lcq_dequantize(lcq_dtype t, const void *d_stream, uint64_t stream_byt
                           void *d_ws, uint64_t ws_bytes, hipStream_t stream);
 
 /* Synchronises `stream` and stores in *h_err the status (LCQ_OK or
- * LCQ_ERR_STREAM) of the last lcq_dequantize that used d_ws. */
+ * LCQ_ERR_STREAM) of the last lcq_dequantize that used d_ws.  The paper
+ * defines no stream validation (its decompressor trusts its input, section
+ * 6); this call reports the checks this library's decoder makes on the
+ * format above, so a corrupted stream is refused instead of decoded. */
 lcq_status lcq_stream_status(const void *d_ws, hipStream_t stream, int32_t *h_err);
 
 /* Static description of a status code. */
@@ -249,11 +258,19 @@ typedef struct {
 
 typedef struct lcq_batch_plan lcq_batch_plan;
 
-/* Number of batch tile shapes the tuner may choose with "batch=<k>". */
+/* Number of batch kernel variants the tuner may choose with "batch=<k>". */
 int32_t lcq_batch_variants(void);
 
 /* Device workspace a plan over these fields needs (0 for bad arguments).
- * `tune` is null or a string containing "batch=<k>" (k < lcq_batch_variants). */
+ * `tune` is null (all defaults) or a tuning string, as the autotuner writes
+ * it, with up to three integer keys, each key followed by its value after
+ * any of '=', ':', '"' or blanks (so "batch=0 f32=4 f64=2" and
+ * {"batch": 0, "f32": 4, "f64": 2} read alike):
+ *   batch  kernel variant, < lcq_batch_variants() (default 0: the two-pass
+ *          chunk form; 1.. look-back tile shapes);
+ *   f32    chunk form: 1024-value chunks per wavefront in each quantize work
+ *   f64    item, for float32 / float64 fields: 1, 2, 4, 8 or 16 (default 1).
+ * Any other value of a present key makes the string invalid. */
 uint64_t lcq_batch_workspace_bytes(const lcq_field *f, uint32_t nf, const char *tune);
 
 /* Validates every field like lcq_quantize does, derives the per-field
@@ -340,11 +357,13 @@ int32_t lcq_tune_variants(void);
 lcq_status lcq_tune_set(int32_t op, lcq_dtype t, int32_t variant);
 int32_t lcq_tune_get(int32_t op, lcq_dtype t);
 
-/* Testing hook for the quantize kernel's outlier-offset scan.  A workgroup
- * waits for the outlier counts of the tiles before it; after `polls` polls
- * without an answer it counts the missing tile's outliers from the input
- * itself (same result, more work).  Default 4096; 0 makes every wait fall
- * back immediately.  Process-wide; affects launches made after the call. */
+/* Testing hook for the look-back scans (the quantize kernels' outlier
+ * offsets, the batched form's NOA parameter waits, lcq_pack's record
+ * offsets).  A workgroup waits for what the tiles before it publish; after
+ * `polls` polls without an answer it computes the missing tile's value from
+ * that tile's input itself (same result, more work).  Default 4096; 0 makes
+ * every wait fall back immediately.  Process-wide; affects launches and
+ * plans made after the call. */
 void lcq_debug_set_lookback_spin(uint32_t polls);
 
 #ifdef __cplusplus

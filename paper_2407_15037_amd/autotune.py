@@ -133,24 +133,28 @@ def load_or_tune(path=None, **kw):
     return table
 
 
-def tune_batch(fields, reps=3, log=None):
+def tune_batch(fields, reps=3, cpws=(1, 2, 4, 8), log=None):
     """Pick the batch plan's tuning string for a set of fields (dicts with
-    x, q, eb as for batch.BatchPlan): each batch variant's quantize graph is
-    timed on the fields themselves (512 MiB written and 512 MiB read to
-    evict the caches before every run, median of `reps` after one untimed
-    run), the fastest wins.
-    Returns {"tune": string for lcq_batch_plan_create, "best": variant,
-    "quantize_ms": [median per variant]}."""
+    x, q, eb as for batch.BatchPlan), timing the quantize graph on the
+    fields themselves (512 MiB written and 512 MiB read to evict the caches
+    before every run, median of `reps` after one untimed run): first each
+    kernel variant; if the chunk form wins, then its chunks per wavefront
+    for float32 fields (float64 at 1), then for float64 fields (float32 at
+    its best).  Returns {"tune": string for lcq_batch_plan_create, "ms":
+    {tuning string: median ms}}."""
     import torch
     from paper_2407_15037_amd.batch import BatchPlan, variants
     scratch = torch.empty(512 << 20, dtype=torch.uint8, device="cuda")
     clean = torch.ones(64 << 20, dtype=torch.int64, device="cuda")
-    ms = []
-    for v in range(variants()):
-        plan = BatchPlan(fields, tune=f"batch={v}")
+    ms = {}
+
+    def timed(tune):
+        if tune in ms:
+            return ms[tune]
+        plan = BatchPlan(fields, tune=tune)
         ts = []
         for r in range(reps + 1):
-            scratch.fill_(0x5A)  # evict the caches: 512 MiB written, 512 MiB read
+            scratch.fill_(0x5A)  # evict the caches
             clean.sum()
             e0 = torch.cuda.Event(enable_timing=True)
             e1 = torch.cuda.Event(enable_timing=True)
@@ -160,13 +164,19 @@ def tune_batch(fields, reps=3, log=None):
             torch.cuda.synchronize()
             if r:
                 ts.append(e0.elapsed_time(e1))
-        ts.sort()
-        ms.append(round(ts[len(ts) // 2], 3))
         plan.close()
         del plan
         torch.cuda.empty_cache()
-    best = min(range(len(ms)), key=lambda i: ms[i])
-    out = {"tune": f"batch={best}", "best": best, "quantize_ms": ms}
+        ts.sort()
+        ms[tune] = round(ts[len(ts) // 2], 3)
+        return ms[tune]
+
+    best = min((f"batch={v}" for v in range(variants())), key=timed)
+    if best == "batch=0":
+        c32 = min(cpws, key=lambda c: timed(f"batch=0 f32={c} f64=1"))
+        c64 = min(cpws, key=lambda c: timed(f"batch=0 f32={c32} f64={c}"))
+        best = f"batch=0 f32={c32} f64={c64}"
+    out = {"tune": best, "ms": ms}
     if log:
-        log(f"batch autotune (quantize ms per variant): {ms} -> {best}")
+        log(f"batch autotune (quantize ms): {ms} -> {best}")
     return out

@@ -340,7 +340,7 @@ __global__ __launch_bounds__(kBlock) void k_dequantize_inline(PlainD a) {
 // Workspace layout beyond the status word and the NOA parameters:
 //   single-pass variants  one look-back word per tile at kWsState
 //   two-pass variants     group sums at kWsState, chunk counts, staged raw
-//                         bits (kStageCap per chunk)
+//                         bits (stage_cap<T>() per chunk)
 //   NOA                   per-workgroup (min, max) pairs after both
 uint64_t align256(uint64_t v) { return (v + 255) & ~255ull; }
 uint64_t ws_counts_off() { return align256(kWsState + 8 * kMaxGroups); }
@@ -349,7 +349,8 @@ uint64_t ws_partials_off(lcq_dtype t, uint64_t n) {
   const uint64_t s = t == LCQ_F64 ? 8 : 4;
   const uint64_t tile = t == LCQ_F64 ? kMinTileF64 : kMinTileF32;
   const uint64_t lookback_end = kWsState + 8 * ((n + tile - 1) / tile);
-  const uint64_t staged_end = ws_stage_off(n) + (uint64_t)kStageCap * s * n_chunks(n);
+  const uint64_t cap = t == LCQ_F64 ? stage_cap<double>() : stage_cap<float>();
+  const uint64_t staged_end = ws_stage_off(n) + cap * s * n_chunks(n);
   return align256(std::max(lookback_end, staged_end));
 }
 uint64_t ws_need(lcq_quantizer q, lcq_dtype t, uint64_t n) {

@@ -46,9 +46,10 @@ using namespace lcq;
 
 namespace {
 
-// Batch quantize variants: variant 0 is the two-pass chunk form (4 chunks,
-// 4096 values, per workgroup); 1-3 are look-back tile shapes (slots, rounds)
-// per dtype.  The tuner picks one.
+// Batch quantize variants: variant 0 is the two-pass chunk form (one chunk
+// per wavefront at a time, cpw chunks per wavefront and workgroup item, cpw
+// chosen per dtype); 1-3 are look-back tile shapes (slots, rounds) per
+// dtype.  The tuner picks the variant and the chunk form's cpw per dtype.
 struct BatchShape {
   Shape f32, f64;
   bool chunk;
@@ -60,7 +61,16 @@ constexpr BatchShape kBatchVariants[kNumBatchVariants] = {
     {{4, 2}, {4, 4}, false},    // 8192
     {{4, 1}, {4, 2}, false},    // 4096
 };
-constexpr uint64_t kChunkTile = kChunk * kWaves;  // values per chunk-form workgroup
+constexpr uint64_t kChunkTile = kChunk * kWaves;  // values per chunk-form workgroup and cpw
+constexpr unsigned kMaxCpw = 16;                   // chunks per wavefront per item, at most
+
+// A plan's tuning: variant, and the chunk form's chunks per wavefront per
+// dtype.
+struct Tune {
+  int bv;
+  unsigned cpw32, cpw64;
+  unsigned cpw(int dtype) const { return dtype == LCQ_F64 ? cpw64 : cpw32; }
+};
 constexpr uint64_t kSlice = 1ull << 18;  // values per NOA range item
 constexpr uint64_t kDeqTile = kChunk * kWaves;  // codes per dequantize workgroup
 
@@ -76,6 +86,7 @@ struct BField {
   uint64_t ntiles;       // quantize tiles
   uint64_t counts_off, stage_off, group_off;  // chunk variant: workspace offsets
   uint64_t tiles_per_group, chunks_per_group, ngroups;
+  uint64_t cpw;          // chunk variant: chunks per wavefront per item
   uint64_t step, inv, bound, low;  // host-derived parameters (ABS / REL)
   uint64_t hdr[8];
   uint64_t eb_down;      // NOA: RD_T(eb)
@@ -273,7 +284,7 @@ __device__ __forceinline__ void chunk_item(const BatchQArgs &a, const BField &bf
   f.group = reinterpret_cast<unsigned long long *>(a.ws + bf.group_off);
   f.tiles_per_group = bf.tiles_per_group;
   f.p = field_params<T, Q>(a, bf, nullptr);
-  quant_chunks<T, Q, 1, 1>(f, tile);
+  quant_chunks_n<T, Q>(f, tile, (unsigned)bf.cpw);
 }
 
 // One workgroup per work item, in queue order: the hardware dispatcher hands
@@ -398,45 +409,53 @@ __global__ void k_batch_clear(uint64_t *p, uint64_t count) {
 
 uint64_t up256(uint64_t v) { return (v + 255) & ~255ull; }
 
+// Staged raw bits of one chunk (pass 1 of the chunk form).
+uint64_t stage_bytes_per_chunk(int dtype) {
+  return dtype == LCQ_F64 ? 8ull * stage_cap<double>() : 4ull * stage_cap<float>();
+}
+
 struct Counts {
   uint64_t n_a = 0, n_b = 0, n_d = 0, n_f = 0, states = 0, partial_bytes = 0;
   uint64_t group_words = 0, count_bytes = 0, stage_bytes = 0;
   uint32_t n_noa = 0;
 };
 
-uint64_t qtile_len(int dtype, int bv) {
-  if (kBatchVariants[bv].chunk) return kChunkTile;
+uint64_t qtile_len(int dtype, const Tune &tn) {
+  const int bv = tn.bv;
+  if (kBatchVariants[bv].chunk) return kChunkTile * tn.cpw(dtype);
   const Shape s = dtype == LCQ_F64 ? kBatchVariants[bv].f64 : kBatchVariants[bv].f32;
   return (uint64_t)kBlock * (dtype == LCQ_F64 ? 2 : 4) * s.slots * s.rounds;
 }
 
 // Quantize workgroups of a field: chunk variant n = 0 has none (its header
 // comes from pass 2); tile variants give n = 0 one header-only tile.
-uint64_t field_tiles(const lcq_field &x, int bv) {
-  const uint64_t tl = qtile_len(x.t, bv);
+uint64_t field_tiles(const lcq_field &x, const Tune &tn) {
+  const int bv = tn.bv;
+  const uint64_t tl = qtile_len(x.t, tn);
   if (kBatchVariants[bv].chunk) return (x.n + tl - 1) / tl;
   return x.n ? (x.n + tl - 1) / tl : 1;
 }
 
 // Chunk variant: pass-2 groups of a field (at most kMaxGroups, at least 1).
-void field_groups(uint64_t ntiles, uint64_t &tiles_per_group, uint64_t &ngroups) {
-  tiles_per_group = lcq::tiles_per_group(ntiles, kChunkTile / kChunk);
+void field_groups(uint64_t ntiles, unsigned cpw, uint64_t &tiles_per_group, uint64_t &ngroups) {
+  tiles_per_group = lcq::tiles_per_group(ntiles, (kChunkTile / kChunk) * cpw);
   ngroups = std::max<uint64_t>(1, (ntiles + tiles_per_group - 1) / tiles_per_group);
 }
 
-Counts count(const lcq_field *f, uint32_t nf, int bv) {
+Counts count(const lcq_field *f, uint32_t nf, const Tune &tn) {
+  const int bv = tn.bv;
   Counts c;
   const bool chunk = kBatchVariants[bv].chunk;
   for (uint32_t i = 0; i < nf; i++) {
-    const uint64_t nt = field_tiles(f[i], bv);
+    const uint64_t nt = field_tiles(f[i], tn);
     c.n_b += nt;
     if (chunk) {
       uint64_t tpg, ng;
-      field_groups(nt, tpg, ng);
+      field_groups(nt, tn.cpw(f[i].t), tpg, ng);
       c.n_f += ng;
       c.group_words += ng;
       c.count_bytes += up256(4 * n_chunks(f[i].n));
-      c.stage_bytes += up256((uint64_t)kStageCap * (f[i].t == LCQ_F64 ? 8 : 4) * n_chunks(f[i].n));
+      c.stage_bytes += up256(stage_bytes_per_chunk(f[i].t) * n_chunks(f[i].n));
     } else {
       c.states += nt;
     }
@@ -474,12 +493,36 @@ Layout layout_for(const Counts &c, uint32_t nf) {
   return L;
 }
 
-int parse_variant(const char *tune) {
-  if (!tune) return 0;
-  const char *p = std::strstr(tune, "batch=");
-  if (!p) return 0;
-  const int v = std::atoi(p + 6);
-  return (v >= 0 && v < kNumBatchVariants) ? v : -1;
+// Value of integer key `key` in a tuning string: the first run of digits
+// after the key (so "batch=2", "f32=4" and {"batch": 2, "f32": 4} read
+// alike); `dflt` when the key is absent, -1 when no digits follow it.
+long tune_value(const char *tune, const char *key, long dflt) {
+  const char *p = tune ? std::strstr(tune, key) : nullptr;
+  if (!p) return dflt;
+  p += std::strlen(key);
+  while (*p && (*p == '"' || *p == ':' || *p == '=' || *p == ' ')) p++;
+  if (*p < '0' || *p > '9') return -1;
+  long v = 0;
+  while (*p >= '0' && *p <= '9' && v < 1000000) v = v * 10 + (*p++ - '0');
+  return v;
+}
+
+// Tuning from the string ("batch", and "f32" / "f64" chunks per wavefront
+// per item for the chunk form, each 1, 2, 4, 8 or 16; defaults 0, 1, 1).
+// bv < 0 marks an invalid string.
+Tune parse_tune(const char *tune) {
+  Tune t{0, 1, 1};
+  const long v = tune_value(tune, "batch", 0);
+  const long c32 = tune_value(tune, "f32", 1), c64 = tune_value(tune, "f64", 1);
+  const auto ok_cpw = [](long c) { return c >= 1 && c <= (long)kMaxCpw && (c & (c - 1)) == 0; };
+  if (v < 0 || v >= kNumBatchVariants || !ok_cpw(c32) || !ok_cpw(c64)) {
+    t.bv = -1;
+    return t;
+  }
+  t.bv = (int)v;
+  t.cpw32 = (unsigned)c32;
+  t.cpw64 = (unsigned)c64;
+  return t;
 }
 
 lcq_status launch_batch_quantize(int bv, const BatchQArgs *a, unsigned grid, hipStream_t s) {
@@ -497,6 +540,7 @@ lcq_status launch_batch_quantize(int bv, const BatchQArgs *a, unsigned grid, hip
 
 struct lcq_batch_plan {
   int variant;
+  Tune tune;
   uint32_t nf;
   bool can_decode;  // every field with values has a decode buffer
   uint8_t *ws;
@@ -512,16 +556,17 @@ extern "C" {
 int32_t lcq_batch_variants(void) { return kNumBatchVariants; }
 
 uint64_t lcq_batch_workspace_bytes(const lcq_field *f, uint32_t nf, const char *tune) {
-  const int bv = parse_variant(tune);
-  if (bv < 0 || (nf && !f)) return 0;
-  return layout_for(count(f, nf, bv), nf).total;
+  const Tune tn = parse_tune(tune);
+  if (tn.bv < 0 || (nf && !f)) return 0;
+  return layout_for(count(f, nf, tn), nf).total;
 }
 
 lcq_status lcq_batch_plan_create(const lcq_field *f, uint32_t nf, const char *tune, void *d_ws,
                                  uint64_t ws_bytes, hipStream_t stream, lcq_batch_plan **out) {
   if (!out || (nf && !f) || !d_ws || !aligned16(d_ws)) return LCQ_ERR_ARG;
   *out = nullptr;
-  const int bv = parse_variant(tune);
+  const Tune tn = parse_tune(tune);
+  const int bv = tn.bv;
   if (bv < 0) return LCQ_ERR_ARG;
   for (uint32_t i = 0; i < nf; i++) {
     const lcq_field &x = f[i];
@@ -536,7 +581,7 @@ lcq_status lcq_batch_plan_create(const lcq_field *f, uint32_t nf, const char *tu
     if (x.d_out && !aligned16(x.d_out)) return LCQ_ERR_ARG;
     if (x.stream_cap < lcq_max_stream_bytes(x.t, x.n)) return LCQ_ERR_CAPACITY;
   }
-  const Counts c = count(f, nf, bv);
+  const Counts c = count(f, nf, tn);
   const Layout L = layout_for(c, nf);
   if (ws_bytes < L.total) return LCQ_ERR_CAPACITY;
   if (c.n_a + c.n_b >= (1ull << 32) || c.n_f >= (1ull << 32) || c.n_d >= (1ull << 32))
@@ -577,16 +622,17 @@ lcq_status lcq_batch_plan_create(const lcq_field *f, uint32_t nf, const char *tu
     d.hdr[5] = hp.bound;
     d.hdr[6] = hp.aux0;
     d.hdr[7] = hp.aux1;
-    d.ntiles = field_tiles(x, bv);
+    d.ntiles = field_tiles(x, tn);
+    d.cpw = tn.cpw(x.t);
     if (kBatchVariants[bv].chunk) {
-      field_groups(d.ntiles, d.tiles_per_group, d.ngroups);
-      d.chunks_per_group = d.tiles_per_group * (kChunkTile / kChunk);
+      field_groups(d.ntiles, tn.cpw(x.t), d.tiles_per_group, d.ngroups);
+      d.chunks_per_group = d.tiles_per_group * (kChunkTile / kChunk) * d.cpw;
       d.group_off = L.groups + 8 * group_off;
       d.counts_off = L.counts + count_off;
       d.stage_off = L.stage + stage_off;
       group_off += d.ngroups;
       count_off += up256(4 * n_chunks(x.n));
-      stage_off += up256((uint64_t)kStageCap * (x.t == LCQ_F64 ? 8 : 4) * n_chunks(x.n));
+      stage_off += up256(stage_bytes_per_chunk(x.t) * n_chunks(x.n));
       for (uint64_t g = 0; g < d.ngroups; g++) items_f.push_back(((uint64_t)i << 32) | g);
     } else {
       d.state_off = state_off;
@@ -625,6 +671,7 @@ lcq_status lcq_batch_plan_create(const lcq_field *f, uint32_t nf, const char *tu
   lcq_batch_plan *p = new (std::nothrow) lcq_batch_plan();
   if (!p) return LCQ_ERR_ARG;
   p->variant = bv;
+  p->tune = tn;
   p->nf = nf;
   p->can_decode = true;
   for (uint32_t i = 0; i < nf; i++)

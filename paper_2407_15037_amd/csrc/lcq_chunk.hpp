@@ -12,13 +12,13 @@
 // look-back:
 //   pass 1  per value classify / bin / reconstruct / verify (sections 2.2,
 //           3.1-3.3), int32 code stores, the chunk's outlier count, and the
-//           first kStageCap outliers' raw bits staged per chunk straight
-//           from registers; one atomic add per workgroup into the sum of
-//           its group of workgroups.
+//           first stage_cap<T>() outliers' raw bits staged per chunk; one
+//           atomic add per workgroup into the sum of its group of
+//           workgroups.
 //   pass 2  one workgroup per group: exclusive scan of the chunk counts
 //           (the chunk table), copy of staged outliers to their final,
 //           input-ordered place, header and size.  A chunk with more than
-//           kStageCap outliers has its codes rescanned and its raw bits
+//           stage_cap<T>() outliers has its codes rescanned and its raw bits
 //           read from the input, by a workgroup chosen so that runs of
 //           such chunks spread over all of them.
 // Dequantize gathers each outlier's bits before the single store of its
@@ -40,7 +40,17 @@ typedef double nt_d2 __attribute__((ext_vector_type(2)));
 typedef int nt_i4 __attribute__((ext_vector_type(4)));
 typedef int nt_i2 __attribute__((ext_vector_type(2)));
 
-constexpr int kStageCap = 32;       // outliers staged per chunk in pass 1
+// Outliers staged per chunk in pass 1: 512 bytes (float32) or 2 KiB
+// (float64) per 1024-value chunk.  Hard stretches of data put tens to
+// hundreds of outliers into a chunk (float32 REL at bounds near 1e-5: up to
+// about 100; float64 values placed on bin borders: about 200); a chunk over
+// the cap is rescanned from its codes and input in pass 2, at the cost of
+// reading both again.
+template <typename T> constexpr int stage_cap() { return sizeof(T) == 4 ? 128 : 256; }
+// Pass 2 copies the staged rows of chunks with at most kDirect outliers in
+// the chunk's own group; rows of chunks with more (hard stretches of data
+// come in runs) are spread over every pass-2 workgroup, as are the rescans.
+constexpr int kDirect = 32;
 constexpr uint64_t kMaxGroups = 1024;  // pass-2 workgroups (groups) at most
 constexpr uint64_t kGroupChunks = 64;  // chunks per group at least
 
@@ -160,7 +170,7 @@ template <typename T> struct StageField {
   uint64_t n;
   int32_t *codes;                 // stream + 64
   uint32_t *counts;               // one per chunk
-  typename FT<T>::U *stage;       // kStageCap per chunk
+  typename FT<T>::U *stage;       // stage_cap<T>() per chunk
   unsigned long long *group;      // one sum per group of workgroups
   uint64_t tiles_per_group;
   FieldParams<T> p;
@@ -198,12 +208,13 @@ __device__ __forceinline__ uint64_t valid_lanes(uint64_t left, int j, int e) {
 // sub-block: each value's outlier flag is one wavefront mask, and a
 // sub-block with outliers puts them into the wavefront's LDS row `srow` at
 // their ranks (running rank = outliers of earlier sub-blocks + set bits of
-// lower lanes); the first kStageCap then leave in one contiguous store.
+// lower lanes); the first stage_cap<T>() then leave in contiguous stores.
 template <typename T, int Q>
 __device__ __forceinline__ unsigned encode_chunk(const StageField<T> &f, uint64_t c, int lane,
                                                  const T (&x)[ChunkShape<T>::NSUB][ChunkShape<T>::W],
                                                  typename FT<T>::U *srow) {
   constexpr int W = ChunkShape<T>::W, NSUB = ChunkShape<T>::NSUB;
+  constexpr unsigned kCap = (unsigned)stage_cap<T>();
   const uint64_t n = f.n;
   const uint64_t left = n - c * kChunk;
   const bool full = left >= kChunk;
@@ -231,7 +242,7 @@ __device__ __forceinline__ unsigned encode_chunk(const StageField<T> &f, uint64_
       for (int e = 0; e < W; e++) {
         const bool mine = full ? code[e] == kSent : ((b[e] >> lane) & 1u) != 0;
         if (mine) {
-          if (r < (unsigned)kStageCap) srow[r] = to_bits(x[j][e]);
+          if (r < kCap) srow[r] = to_bits(x[j][e]);
           r++;
         }
       }
@@ -241,7 +252,9 @@ __device__ __forceinline__ unsigned encode_chunk(const StageField<T> &f, uint64_
   // fence orders them (LDS accesses of one wavefront complete in issue
   // order, so it costs no wait)
   __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-  if ((unsigned)lane < min(cnt, (unsigned)kStageCap)) f.stage[c * kStageCap + lane] = srow[lane];
+  const unsigned staged = min(cnt, kCap);  // uniform
+  for (unsigned b = 0; b < staged; b += 64)
+    if (b + (unsigned)lane < staged) f.stage[c * kCap + b + lane] = srow[b + lane];
   __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");  // before the next chunk's writes
   if (lane == 0) f.counts[c] = cnt;
   return cnt;
@@ -255,7 +268,7 @@ __device__ void quant_chunks(const StageField<T> &f, uint64_t tile) {
   static_assert(PF == 0 || CPW % PF == 0, "whole prefetch groups");
   constexpr int W = ChunkShape<T>::W, NSUB = ChunkShape<T>::NSUB;
   __shared__ unsigned s_cnt[kWaves];
-  __shared__ typename FT<T>::U s_stage[kWaves][kStageCap];  // one row per wavefront
+  __shared__ typename FT<T>::U s_stage[kWaves][stage_cap<T>()];  // one row per wavefront
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // uniform: chunk logic is scalar
   const uint64_t nch = n_chunks(f.n);
@@ -285,6 +298,36 @@ __device__ void quant_chunks(const StageField<T> &f, uint64_t tile) {
         if (c < nch) wsum += encode_chunk<T, Q>(f, c, lane, x[p], s_stage[wave]);  // uniform
       }
     }
+  }
+  if (lane == 0) s_cnt[wave] = wsum;
+  __syncthreads();
+  if (tid == 0) {
+    unsigned long long t = 0;
+#pragma unroll
+    for (int w = 0; w < kWaves; w++) t += s_cnt[w];
+    if (t) atomicAdd(f.group + tile / f.tiles_per_group, t);
+  }
+}
+
+// Pass 1 for the cpw * kWaves chunks of workgroup `tile`, cpw given at run
+// time (the batched form, where every workgroup item first loads its
+// field's descriptor): one chunk per wavefront at a time, chunk (tile cpw +
+// r) kWaves + wave in round r.
+template <typename T, int Q>
+__device__ void quant_chunks_n(const StageField<T> &f, uint64_t tile, unsigned cpw) {
+  constexpr int W = ChunkShape<T>::W, NSUB = ChunkShape<T>::NSUB;
+  __shared__ unsigned s_cnt[kWaves];
+  __shared__ typename FT<T>::U s_stage[kWaves][stage_cap<T>()];  // one row per wavefront
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // uniform: chunk logic is scalar
+  const uint64_t nch = n_chunks(f.n);
+  unsigned wsum = 0;
+  for (unsigned r = 0; r < cpw; r++) {
+    const uint64_t c = (tile * cpw + r) * kWaves + wave;
+    if (c >= nch) break;  // uniform
+    T x[NSUB][W];
+    load_chunk<T>(f.in, f.n, c, lane, x);
+    wsum += encode_chunk<T, Q>(f, c, lane, x, s_stage[wave]);
   }
   if (lane == 0) s_cnt[wave] = wsum;
   __syncthreads();
@@ -343,6 +386,28 @@ __device__ void rescan_chunk(const FinishField<T> &f, uint64_t c, uint64_t P, in
   }
 }
 
+// The staged row of chunk c (cnt <= stage cap outliers) to its place from
+// index P on.  One wavefront; every load is issued before the first store.
+template <typename T>
+__device__ __forceinline__ void copy_staged(const FinishField<T> &f, uint64_t c, uint64_t P,
+                                            unsigned cnt, int lane) {
+  using U = typename FT<T>::U;
+  constexpr unsigned kCap = (unsigned)stage_cap<T>();
+  constexpr int kR = (int)kCap / 64;
+  U *outl = reinterpret_cast<U *>(f.stream + outlier_offset(f.n));
+  U v[kR];
+#pragma unroll
+  for (int r = 0; r < kR; r++) {
+    const unsigned i = (unsigned)lane + 64u * r;
+    if (i < cnt) v[r] = f.stage[c * kCap + i];
+  }
+#pragma unroll
+  for (int r = 0; r < kR; r++) {
+    const unsigned i = (unsigned)lane + 64u * r;
+    if (i < cnt) outl[P + i] = v[r];
+  }
+}
+
 static_assert(LCQ_MAX_N / kChunk <= 0xFFFFFFFFull, "chunk indices fit 32 bits");
 
 // Index of chunk c's first outlier, from the pass-1 group sums and chunk
@@ -383,6 +448,7 @@ __device__ void quant_finish(const FinishField<T> &f, uint64_t g) {
   __shared__ unsigned s_wt[kWaves];
   __shared__ uint64_t s_P[kBlock];
   __shared__ unsigned s_c[kBlock];
+  constexpr unsigned kCap = (unsigned)stage_cap<T>();
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const uint64_t n = f.n;
   const uint64_t nch = n_chunks(n);
@@ -438,13 +504,14 @@ __device__ void quant_finish(const FinishField<T> &f, uint64_t g) {
     s_c[tid] = cnt;                    // (read after the barrier below)
     const int m = (int)min<uint64_t>((uint64_t)kBlock, c1 - cb);
     __syncthreads();  // s_P and s_c whole
-    // staged outliers: half a wavefront per chunk, word r of a row moved by
-    // lane r of the half (one row read and one contiguous run written per
-    // instruction); the loads of a round are all issued before its stores
+    // staged outliers of chunks with at most kDirect of them: half a
+    // wavefront per chunk, word r of a row moved by lane r of the half (one
+    // row read and one contiguous run written per instruction); the loads
+    // of a round are all issued before its stores
     {
-      constexpr int kHalves = kBlock / kStageCap, kRound = 16;
-      static_assert(kStageCap == 32, "a staged row is one half wavefront");
-      const int h = tid / kStageCap, r = tid % kStageCap;
+      constexpr int kHalves = kBlock / kDirect, kRound = 16;
+      static_assert(kDirect == 32, "a directly copied row is one half wavefront");
+      const int h = tid / kDirect, r = tid % kDirect;
       for (int i0 = h; i0 < m; i0 += kHalves * kRound) {
         U v[kRound];
         uint64_t dst[kRound];
@@ -453,9 +520,9 @@ __device__ void quant_finish(const FinishField<T> &f, uint64_t g) {
         for (int u = 0; u < kRound; u++) {
           const int i = i0 + u * kHalves;
           const unsigned ci = i < m ? s_c[i] : 0u;
-          mv[u] = ci <= (unsigned)kStageCap && (unsigned)r < ci;
+          mv[u] = ci <= (unsigned)kDirect && (unsigned)r < ci;
           dst[u] = mv[u] ? run + s_P[i] + (unsigned)r : 0;
-          if (mv[u]) v[u] = f.stage[(cb + (uint64_t)i) * kStageCap + r];
+          if (mv[u]) v[u] = f.stage[(cb + (uint64_t)i) * kCap + r];
         }
 #pragma unroll
         for (int u = 0; u < kRound; u++)
@@ -466,15 +533,16 @@ __device__ void quant_finish(const FinishField<T> &f, uint64_t g) {
     __syncthreads();  // s_wt, s_P, s_c are rewritten by the next batch
   }
 
-  // Chunks with more outliers than were staged are rescanned from their
-  // codes and input, and not by their own group: workgroup g takes chunks
-  // g, g + ngroups, g + 2 ngroups, ... so that runs of such chunks (a
-  // stretch of hard data) spread over every workgroup instead of queueing
-  // behind one.  One wavefront per such chunk.
+  // Chunks with more than kDirect outliers are finished not by their own
+  // group: workgroup g takes chunks g, g + ngroups, g + 2 ngroups, ... so
+  // that runs of such chunks (a stretch of hard data) spread over every
+  // workgroup instead of queueing behind one.  One wavefront per such
+  // chunk: its staged row is copied, or, past the stage cap, its outliers
+  // are rescanned from its codes and input.
   for (uint64_t t0 = 0; g + t0 * f.ngroups < nch; t0 += kBlock) {
     const uint64_t c = g + (t0 + (uint64_t)tid) * f.ngroups;
     const unsigned cn = t0 == 0 ? duty0 : (c < nch ? f.counts[c] : 0u);
-    const bool ov = cn > (unsigned)kStageCap;
+    const bool ov = cn > (unsigned)kDirect;
     if (!__syncthreads_or(ov)) continue;
     const uint64_t wb = __ballot(ov);
     if (lane == 0) s_wt[wave] = (unsigned)__popcll(wb);
@@ -485,13 +553,19 @@ __device__ void quant_finish(const FinishField<T> &f, uint64_t g) {
       if (w < wave) base += s_wt[w];
       nov += s_wt[w];
     }
-    if (ov) s_P[base + lanes_below(wb, 0u)] = c;  // compact list of this batch's chunks
+    if (ov) {  // compact list of this batch's chunks and their counts
+      s_P[base + lanes_below(wb, 0u)] = c;
+      s_c[base + lanes_below(wb, 0u)] = cn;
+    }
     __syncthreads();
     for (unsigned i = (unsigned)wave; i < nov; i += kWaves) {
       const uint64_t cv = s_P[i];
-      rescan_chunk<T>(f, cv, chunk_first_outlier<T>(f, cv, lane), lane);
+      const unsigned cc = s_c[i];
+      const uint64_t P = chunk_first_outlier<T>(f, cv, lane);
+      if (cc <= kCap) copy_staged<T>(f, cv, P, cc, lane);
+      else rescan_chunk<T>(f, cv, P, lane);
     }
-    __syncthreads();  // s_wt and s_P are rewritten by the next batch
+    __syncthreads();  // s_wt, s_P and s_c are rewritten by the next batch
   }
 
   if (g == f.ngroups - 1 && tid == 0) {

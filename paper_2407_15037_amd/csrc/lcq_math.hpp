@@ -153,7 +153,9 @@ template <typename T, int Q> __device__ __forceinline__ int32_t encode(T x, cons
   if (Q == kNOA) ok = ok && !p.lossless_all;
 
   if constexpr (is_rel_q<Q>()) {
-    const T a = from_bits((U)(u & ~F::kSign));
+    // |x| (an absolute-value source modifier where it is used, not an
+    // instruction of its own)
+    const T a = abs_t(x);
     // (the approximate log2 reads only the exponent and fraction fields)
     const T q = rint_t((Q == kREL_LIBM ? lib_log2(a) : log2approx_dev(x)) * p.inv);
     // section 3.3: both range tests, on the float, before any conversion
@@ -162,16 +164,17 @@ template <typename T, int Q> __device__ __forceinline__ int32_t encode(T x, cons
     const T qb = ok ? q : (T)0;
     const int32_t b = (int32_t)qb;
     const T rec = Q == kREL_LIBM ? lib_exp2(qb * p.step) : pow2approx_dev(qb * p.step);
-    // section 3.1 double-check against both sides of the section 2.1.2 range
-    // |rec - a| equals (a - rec) when rec < a: round-to-nearest is
-    // symmetric under negation, so one subtraction serves both sides
+    // section 3.1 double-check against the side of the section 2.1.2 range
+    // that rec lies on: (rec - a) < eh a above a, (a - rec) < el a below;
+    // |rec - a| equals (a - rec) when rec < a (round-to-nearest is
+    // symmetric under negation), so one subtraction serves both sides
     const bool up = rec >= a;
     const T diff = abs_t(rec - a);
-    // el <= eh, so passing the lower side's test implies passing the upper
-    // side's: one select-free form of (up ? diff < eh a : diff < el a)
-    const bool ok_up = diff < p.bound * a, ok_low = diff < p.low * a;
-    ok = ok & (ok_low | (up & ok_up));
-    const uint32_t code = ((uint32_t)b << 1) | (uint32_t)(u >> (sizeof(T) * 8 - 1));
+    ok = ok & (diff < (up ? p.bound : p.low) * a);  // bitwise: no branch per value
+    // (b << 1) | sign bit of x: one funnel shift of the pair (b, high word
+    // of x)
+    const uint32_t hi = (uint32_t)(u >> (sizeof(T) * 8 - 32));
+    const uint32_t code = __builtin_amdgcn_alignbit((uint32_t)b, hi, 31);
     return ok ? (int32_t)code : kSent;
   } else {
     const T q = rint_t(x * p.inv);

@@ -120,3 +120,26 @@ def test_per_value_kernels_have_no_fused_or_packed_fp(device_asm):
 def test_float32_subnormals_kept(device_asm):
     modes = re.findall(r"\.amdhsa_float_denorm_mode_32\s+(\d+)", device_asm)
     assert modes and all(m == "3" for m in modes), modes
+
+
+def test_batch_tuning_strings():
+    """The batch plan's tuning string is read on the host: both spellings of
+    the same tuning give the same workspace, chunks per wavefront change the
+    plan's layout, and a malformed value is refused (workspace 0)."""
+    import paper_2407_15037_amd as lcq
+    from paper_2407_15037_amd.batch import Field
+    L = lcq.lib()
+    arr = (Field * 3)()
+    fake = 1 << 20  # never dereferenced by the size query
+    for i, (q, t, n) in enumerate([(0, 0, 100000), (1, 1, 5000), (2, 0, 3 << 20)]):
+        arr[i] = Field(q, t, 1e-3, fake, n, fake, 1 << 40, fake, fake)
+
+    def ws(tune):
+        return int(L.lcq_batch_workspace_bytes(arr, 3, None if tune is None else tune.encode()))
+
+    base = ws(None)
+    assert base > 0 and ws("batch=0") == base and ws("batch=0 f32=1 f64=1") == base
+    assert ws("batch=0 f32=4 f64=2") == ws('{"batch": 0, "f32": 4, "f64": 2}') > 0
+    assert ws("batch=0 f32=4 f64=2") != base  # fewer quantize items, fewer group sums
+    for bad in ("batch=99", "batch=0 f32=3", "f64=0", "f32=32", "batch=x"):
+        assert ws(bad) == 0, bad

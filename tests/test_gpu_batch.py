@@ -32,11 +32,16 @@ def _fields(seed, nf, max_n):
     return out
 
 
-@pytest.mark.parametrize("variant", [0, 1, 2, 3])
+TUNES = ["batch=0", "batch=1", "batch=2", "batch=3", "batch=0 f32=4 f64=2",
+         '{"batch": 0, "f32": 16, "f64": 8}', "batch=0 f32=2 f64=16"]
+
+
+@pytest.mark.parametrize("variant", range(len(TUNES)), ids=TUNES)
 def test_batch_matches_oracle_and_plain(variant):
     import torch
     import paper_2407_15037_amd as lcq
     from paper_2407_15037_amd.batch import BatchPlan
+    tune = TUNES[variant]
     fl = _fields(100 + variant, 60, 300000)
     # fields where every value is stored losslessly (more outliers per chunk
     # than are staged), one per quantizer and dtype
@@ -45,13 +50,13 @@ def test_batch_matches_oracle_and_plain(variant):
                                         5000 + 777 * j, 91 + j, 1e-3)
         fl.append(dict(x_np=x, q=q, eb=1e-3))
     dev_fields = [dict(x=torch.from_numpy(f["x_np"]).cuda(), q=f["q"], eb=f["eb"]) for f in fl]
-    announce("batch plan", variant, len(fl))
-    plan = BatchPlan(dev_fields, variant=variant)
+    announce("batch plan", tune, len(fl))
+    plan = BatchPlan(dev_fields, tune=tune)
     for rep in range(2):  # a second run reuses the plan (graph replay)
-        announce("batch quantize", variant, rep)
+        announce("batch quantize", tune, rep)
         plan.quantize()
         torch.cuda.synchronize()
-        announce("batch dequantize", variant, rep)
+        announce("batch dequantize", tune, rep)
         plan.dequantize()
         torch.cuda.synchronize()
         assert plan.first_bad_field() == -1
@@ -94,7 +99,7 @@ def test_batch_dequant_reports_bad_field():
     plan.close()
 
 
-@pytest.mark.parametrize("variant", [0, 3])
+@pytest.mark.parametrize("variant", ["batch=0", "batch=3", "batch=0 f32=8 f64=4"])
 def test_batch_fallback_paths_same_bytes(variant):
     """With the look-back and NOA-parameter waits forced to fall back at once
     (every wait recomputes what it waits for from the input), the batch still
@@ -108,7 +113,7 @@ def test_batch_fallback_paths_same_bytes(variant):
     try:
         lcq.set_lookback_spin(0)
         announce("batch fallback plan", variant)
-        plan = BatchPlan(dev_fields, variant=variant)
+        plan = BatchPlan(dev_fields, tune=variant)
     finally:
         lcq.set_lookback_spin(4096)
     plan.quantize()

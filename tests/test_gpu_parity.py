@@ -301,7 +301,9 @@ def test_parity_random_float64_bit_patterns(q, eb):
 def test_parity_overflow_runs(dt, q, eb, nchunks):
     """Runs of chunks with more outliers than a chunk stages (NaN every other
     value, or random bit patterns) in a smooth field: a run across a group
-    boundary, a run of random bits, and a ragged last chunk full of NaNs.
+    boundary, a run of random bits, and a ragged last chunk full of NaNs;
+    runs of chunks whose staged rows are longer than one pass-2 copy round
+    or sit at the stage cap.
     Such chunks are rescanned by workgroups other than their own group's, at
     offsets found from the pass-1 sums; the stream must still equal the
     oracle's."""
@@ -314,6 +316,11 @@ def test_parity_overflow_runs(dt, q, eb, nchunks):
         ub = np.uint64 if dt == np.float64 else np.uint32
         lo, hi = 200 * 1024, 264 * 1024
         x[lo:hi] = rng.integers(0, np.iinfo(ub).max, hi - lo, dtype=ub, endpoint=True).view(dt)
+        # stretches with 114, 128, 256 and 342 outliers per chunk: staged
+        # rows copied whole by other pass-2 workgroups, rows at the float32
+        # and float64 stage caps (128, 256), and rows over both (rescanned)
+        for s0, step in ((90, 9), (100, 8), (120, 4), (140, 3)):
+            x[s0 * 1024:(s0 + 10) * 1024:step] = np.nan
     x[(nchunks - 1) * 1024:] = np.nan
     st, _ = _parity(q, x, eb, f"overflow runs {nchunks} chunks")
     k = int(st[16:24].view(np.uint64)[0])
