@@ -33,7 +33,9 @@ enum { ORC_ABS = 0, ORC_REL = 1, ORC_NOA = 2 };
 /* The two ablations of section 6 (not error-bound guaranteeing by design):
  * ABS without the double-check of section 3.1, and REL with the C library's
  * log2 / exp2 in place of the approximations of section 3.2.  Their streams
- * carry these codes in the header's quantizer byte. */
+ * carry these codes in the header's quantizer byte.  Parity unpinned: the
+ * REL_LIBM codes (host and device math libraries round apart; pinned only
+ * at exact powers of two and through the bound). */
 enum { ORC_ABS_UNCHECKED = 3, ORC_REL_LIBM = 4 };
 enum { ORC_OK = 0, ORC_ERR_ARG = 1, ORC_ERR_CAPACITY = 2, ORC_ERR_STREAM = 3,
        ORC_ERR_FPENV = 5 };
