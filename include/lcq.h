@@ -357,13 +357,13 @@ int32_t lcq_tune_variants(void);
 lcq_status lcq_tune_set(int32_t op, lcq_dtype t, int32_t variant);
 int32_t lcq_tune_get(int32_t op, lcq_dtype t);
 
-/* Testing hook for the look-back scans (the quantize kernels' outlier
- * offsets, the batched form's NOA parameter waits, lcq_pack's record
- * offsets).  A workgroup waits for what the tiles before it publish; after
- * `polls` polls without an answer it computes the missing tile's value from
- * that tile's input itself (same result, more work).  Default 4096; 0 makes
- * every wait fall back immediately.  Process-wide; affects launches and
- * plans made after the call. */
+/* Testing hook for the bounded waits (the look-back tile kernels' outlier
+ * offsets, the batched form's NOA parameter waits).  A workgroup waits for
+ * what the tiles before it publish; after `polls` polls without an answer
+ * it computes the missing tile's value from that tile's input itself (same
+ * result, more work).  Default 4096; 0 makes every wait fall back
+ * immediately.  Process-wide; affects launches and plans made after the
+ * call. */
 void lcq_debug_set_lookback_spin(uint32_t polls);
 
 #ifdef __cplusplus

@@ -124,10 +124,11 @@ __device__ __forceinline__ void load_codes(const int32_t *codes, uint64_t i0, ui
   }
 }
 
-template <int W>
+// (FULL: the caller knows all W lie below n)
+template <int W, bool FULL = false>
 __device__ __forceinline__ void store_codes(int32_t *codes, uint64_t i0, uint64_t n,
                                             const int32_t (&c)[W]) {
-  if (i0 + W <= n) {
+  if (FULL || i0 + W <= n) {
     if constexpr (W == 4) {
       const nt_i4 o = {c[0], c[1], c[2], c[3]};
       __builtin_nontemporal_store(o, reinterpret_cast<nt_i4 *>(codes + i0));
@@ -209,10 +210,11 @@ __device__ __forceinline__ uint64_t valid_lanes(uint64_t left, int j, int e) {
 // sub-block with outliers puts them into the wavefront's LDS row `srow` at
 // their ranks (running rank = outliers of earlier sub-blocks + set bits of
 // lower lanes); the first stage_cap<T>() then leave in contiguous stores.
+// k: the encoder's operands (enc_consts_pinned: held in vector registers).
 template <typename T, int Q>
 __device__ __forceinline__ unsigned encode_chunk(const StageField<T> &f, uint64_t c, int lane,
                                                  const T (&x)[ChunkShape<T>::NSUB][ChunkShape<T>::W],
-                                                 typename FT<T>::U *srow) {
+                                                 typename FT<T>::U *srow, const EncK<T> &k) {
   constexpr int W = ChunkShape<T>::W, NSUB = ChunkShape<T>::NSUB;
   constexpr unsigned kCap = (unsigned)stage_cap<T>();
   const uint64_t n = f.n;
@@ -226,7 +228,7 @@ __device__ __forceinline__ unsigned encode_chunk(const StageField<T> &f, uint64_
     uint64_t b[W], any = 0;
 #pragma unroll
     for (int e = 0; e < W; e++) {
-      code[e] = encode<T, Q>(x[j][e], f.p);
+      code[e] = encode<T, Q>(x[j][e], f.p, k);
       b[e] = __ballot(code[e] == kSent) & valid_lanes<W>(left, j, e);
       any |= b[e];
     }
@@ -272,6 +274,7 @@ __device__ void quant_chunks(const StageField<T> &f, uint64_t tile) {
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // uniform: chunk logic is scalar
   const uint64_t nch = n_chunks(f.n);
+  const EncK<T> k = enc_consts_pinned<T, Q>(f.p);
   unsigned wsum = 0;
   if constexpr (PF == 0) {
     T x[2][NSUB][W];
@@ -281,7 +284,7 @@ __device__ void quant_chunks(const StageField<T> &f, uint64_t tile) {
     for (int r = 0; r < CPW; r++) {
       const uint64_t c = c0 + (uint64_t)r * kWaves;
       if (r + 1 < CPW && c + kWaves < nch) load_chunk<T>(f.in, f.n, c + kWaves, lane, x[(r + 1) & 1]);
-      if (c < nch) wsum += encode_chunk<T, Q>(f, c, lane, x[r & 1], s_stage[wave]);  // uniform
+      if (c < nch) wsum += encode_chunk<T, Q>(f, c, lane, x[r & 1], s_stage[wave], k);  // uniform
     }
   } else {
 #pragma unroll
@@ -295,7 +298,7 @@ __device__ void quant_chunks(const StageField<T> &f, uint64_t tile) {
 #pragma unroll
       for (int p = 0; p < PF; p++) {
         const uint64_t c = (tile * CPW + r0 + p) * kWaves + wave;
-        if (c < nch) wsum += encode_chunk<T, Q>(f, c, lane, x[p], s_stage[wave]);  // uniform
+        if (c < nch) wsum += encode_chunk<T, Q>(f, c, lane, x[p], s_stage[wave], k);  // uniform
       }
     }
   }
@@ -321,13 +324,14 @@ __device__ void quant_chunks_n(const StageField<T> &f, uint64_t tile, unsigned c
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // uniform: chunk logic is scalar
   const uint64_t nch = n_chunks(f.n);
+  const EncK<T> k = enc_consts_pinned<T, Q>(f.p);
   unsigned wsum = 0;
   for (unsigned r = 0; r < cpw; r++) {
     const uint64_t c = (tile * cpw + r) * kWaves + wave;
     if (c >= nch) break;  // uniform
     T x[NSUB][W];
     load_chunk<T>(f.in, f.n, c, lane, x);
-    wsum += encode_chunk<T, Q>(f, c, lane, x, s_stage[wave]);
+    wsum += encode_chunk<T, Q>(f, c, lane, x, s_stage[wave], k);
   }
   if (lane == 0) s_cnt[wave] = wsum;
   __syncthreads();

@@ -99,15 +99,26 @@ template <typename T> __device__ __forceinline__ T log2approx_dev(T a) {
     return log2approx(a);
   }
 }
-template <typename T> __device__ __forceinline__ T pow2approx_dev(T y) {
+// (emax: the largest exponent field as a value of T, passed in so that a
+// kernel can hold it in a register)
+template <typename T> __device__ __forceinline__ T pow2approx_dev(T y, T emax) {
   if constexpr (sizeof(T) == 4) {
-    const float t = __builtin_amdgcn_fmed3f(y + 127.0f, 0.0f, 255.0f);
+    const float t = __builtin_amdgcn_fmed3f(y + 127.0f, 0.0f, emax);
     const int k = (int)t;
     const float g = __builtin_amdgcn_fractf(t) + 1.0f;
     return from_bits((uint32_t)(((uint32_t)k << 23) | (to_bits(g) & 0x007FFFFFu)));
   } else {
-    return pow2approx(y);
+    using F = FT<T>;
+    using U = typename F::U;
+    T t = y + (T)F::kBias;
+    t = fmin(fmax(t, (T)0), emax);
+    const int k = (int)t;
+    const T g = t - (T)(k - 1);
+    return from_bits((U)(((U)k << F::kMant) | (to_bits(g) & F::kFracMask)));
   }
+}
+template <typename T> __device__ __forceinline__ T pow2approx_dev(T y) {
+  return pow2approx_dev(y, (T)FT<T>::kExpMask);
 }
 
 // Parameters of one field in the field's type.
@@ -135,21 +146,59 @@ LCQ_HD double lib_exp2(double x) { return exp2(x); }
 // denormals are stored losslessly, and for REL zeros too.  One class test:
 // bits 3 and 8 of its mask are the negative and positive normals, bits 5
 // and 6 the negative and positive zeros.
-template <typename T, int Q> __device__ __forceinline__ bool quantizable(T x) {
+template <int Q> constexpr int class_mask() {
   constexpr int kNormal = (1 << 3) | (1 << 8), kZero = (1 << 5) | (1 << 6);
-  constexpr int m = is_rel_q<Q>() ? kNormal : (kNormal | kZero);
+  return is_rel_q<Q>() ? kNormal : (kNormal | kZero);
+}
+template <typename T> __device__ __forceinline__ bool class_test(T x, int m) {
   if constexpr (sizeof(T) == 4) return __builtin_amdgcn_classf(x, m);
   else return __builtin_amdgcn_class(x, m);
+}
+template <typename T, int Q> __device__ __forceinline__ bool quantizable(T x) {
+  return class_test(x, class_mask<Q>());
+}
+
+// Operands of the per-value encoder that its instructions cannot take as
+// immediates or as a second scalar operand (the class-test mask, the upper
+// end of pow2approx's clamp, the sentinel code, REL's two side bounds read
+// by one select).  A kernel may hold them in vector registers for its whole
+// run (pin_v); otherwise the compiler rebuilds each one at every use.
+template <typename T> struct EncK {
+  T emax, bound, low;
+  int32_t sent;
+  int cls;
+};
+template <typename T, int Q>
+__device__ __forceinline__ EncK<T> enc_consts(const FieldParams<T> &p) {
+  return EncK<T>{(T)FT<T>::kExpMask, p.bound, p.low, kSent, class_mask<Q>()};
+}
+// v, held in a vector register from here on (an empty asm the compiler
+// cannot see through, so it keeps the register instead of re-creating v).
+template <typename V> __device__ __forceinline__ V pin_v(V v) {
+  asm volatile("" : "+v"(v));
+  return v;
+}
+template <typename T, int Q>
+__device__ __forceinline__ EncK<T> enc_consts_pinned(const FieldParams<T> &p) {
+  EncK<T> k = enc_consts<T, Q>(p);
+  k.emax = pin_v(k.emax);
+  k.bound = pin_v(k.bound);
+  k.low = pin_v(k.low);
+  k.sent = pin_v(k.sent);
+  k.cls = pin_v(k.cls);
+  return k;
 }
 
 // One value -> its int32 code, or kSent if it must be stored losslessly.
 // Evaluates every step for every lane (no data-dependent branches) and only
-// converts the bin to int where it is in range.
-template <typename T, int Q> __device__ __forceinline__ int32_t encode(T x, const FieldParams<T> &p) {
+// converts the bin to int where it is in range.  k: enc_consts (or their
+// pinned copies).
+template <typename T, int Q>
+__device__ __forceinline__ int32_t encode(T x, const FieldParams<T> &p, const EncK<T> &k) {
   using F = FT<T>;
   using U = typename F::U;
   const U u = to_bits(x);
-  bool ok = quantizable<T, Q>(x);
+  bool ok = class_test(x, k.cls);
   if (Q == kNOA) ok = ok && !p.lossless_all;
 
   if constexpr (is_rel_q<Q>()) {
@@ -163,19 +212,19 @@ template <typename T, int Q> __device__ __forceinline__ int32_t encode(T x, cons
     // qb is integral and inside (-2^30, 2^30), so (T)(int)qb == qb exactly
     const T qb = ok ? q : (T)0;
     const int32_t b = (int32_t)qb;
-    const T rec = Q == kREL_LIBM ? lib_exp2(qb * p.step) : pow2approx_dev(qb * p.step);
+    const T rec = Q == kREL_LIBM ? lib_exp2(qb * p.step) : pow2approx_dev(qb * p.step, k.emax);
     // section 3.1 double-check against the side of the section 2.1.2 range
     // that rec lies on: (rec - a) < eh a above a, (a - rec) < el a below;
     // |rec - a| equals (a - rec) when rec < a (round-to-nearest is
     // symmetric under negation), so one subtraction serves both sides
     const bool up = rec >= a;
     const T diff = abs_t(rec - a);
-    ok = ok & (diff < (up ? p.bound : p.low) * a);  // bitwise: no branch per value
+    ok = ok & (diff < (up ? k.bound : k.low) * a);  // bitwise: no branch per value
     // (b << 1) | sign bit of x: one funnel shift of the pair (b, high word
     // of x)
     const uint32_t hi = (uint32_t)(u >> (sizeof(T) * 8 - 32));
     const uint32_t code = __builtin_amdgcn_alignbit((uint32_t)b, hi, 31);
-    return ok ? (int32_t)code : kSent;
+    return ok ? (int32_t)code : k.sent;
   } else {
     const T q = rint_t(x * p.inv);
     ok = ok && (q > (T)-kMaxBin) && (q < (T)kMaxBin);
@@ -183,8 +232,11 @@ template <typename T, int Q> __device__ __forceinline__ int32_t encode(T x, cons
     const int32_t b = (int32_t)qb;
     const T rec = qb * p.step;
     if constexpr (Q != kABS_UNCHECKED) ok = ok && (abs_t(x - rec) <= p.bound);
-    return ok ? b : kSent;
+    return ok ? b : k.sent;
   }
+}
+template <typename T, int Q> __device__ __forceinline__ int32_t encode(T x, const FieldParams<T> &p) {
+  return encode<T, Q>(x, p, enc_consts<T, Q>(p));
 }
 
 // One non-sentinel code -> its value (the decoder side of encode; LIBM: the

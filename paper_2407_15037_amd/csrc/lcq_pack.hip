@@ -25,8 +25,10 @@
 //                 workgroup into its group's byte count
 //   k_pack_scan   one workgroup per group: record offsets, header, padding,
 //                 packed size
-//   k_pack_write  records (z staged in LDS, each lane assembles whole 32-bit
-//                 output words), chunk table, outliers
+//   k_pack_write  records (each chunk's packed bits assembled in LDS by
+//                 atomic ORs and stored 128 bits at a time; tiles taken last
+//                 to first, so the codes k_pack_plan read last come from the
+//                 Infinity Cache), chunk table, outliers
 //   k_unpack      per chunk: record checks, bit extraction, inverse zigzag,
 //                 wavefront prefix sum (delta mode), sentinels from the
 //                 bitmap; header, chunk table, outliers
@@ -60,6 +62,16 @@ __host__ __device__ inline uint64_t record_bytes(uint64_t len, unsigned w, unsig
   return 16 + (hb ? 128 : 0) + align16((len * w + 7) / 8);
 }
 
+// Values of chunk c below n, and a lane's position inside its chunk (32-bit
+// bounds tests).
+__device__ __forceinline__ unsigned chunk_len(uint64_t n, uint64_t c) {
+  const uint64_t left = n - c * kChunk;
+  return left >= kChunk ? kChunk : (unsigned)left;
+}
+template <int W> __device__ __forceinline__ unsigned chunk_pos(int j, int lane) {
+  return (unsigned)(64 * W * j + W * lane);
+}
+
 __device__ __forceinline__ uint32_t zigzag(uint32_t v) {
   return (v << 1) ^ (uint32_t)((int32_t)v >> 31);
 }
@@ -89,17 +101,27 @@ struct ChunkCodes {
   unsigned flags;  // bit 4 j + e: outlier sentinel
 };
 
+// CACHED: ordinary loads, which leave the codes in the Infinity Cache for
+// the writing pass that re-reads them (otherwise streaming loads).
+template <bool CACHED = false>
 __device__ __forceinline__ void load_chunk(const int32_t *codes, uint64_t n, uint64_t c, int lane,
                                            ChunkCodes &cc) {
   cc.flags = 0;
+  const unsigned len = chunk_len(n, c);
 #pragma unroll
   for (int j = 0; j < kCSub; j++) {
     const uint64_t i0 = chunk_value<kCW>(c, j, lane);
+    const unsigned p = chunk_pos<kCW>(j, lane);
     int32_t v[kCW];
-    load_codes<kCW>(codes, i0, n, v);
+    if (CACHED && p + kCW <= len) {
+      const nt_i4 q = *reinterpret_cast<const nt_i4 *>(codes + i0);
+      v[0] = q.x; v[1] = q.y; v[2] = q.z; v[3] = q.w;
+    } else {
+      load_codes<kCW>(codes, i0, n, v);
+    }
 #pragma unroll
     for (int e = 0; e < kCW; e++) {
-      const bool sent = v[e] == kSent && i0 + e < n;
+      const bool sent = v[e] == kSent && p + e < len;
       cc.cv[j][e] = sent ? 0u : (uint32_t)v[e];
       if (sent) cc.flags |= 1u << (kCW * j + e);
     }
@@ -110,10 +132,11 @@ __device__ __forceinline__ void load_chunk(const int32_t *codes, uint64_t n, uin
 template <bool DELTA>
 __device__ __forceinline__ void chunk_z(const ChunkCodes &cc, uint64_t n, uint64_t c, int lane,
                                         uint32_t (&z)[kCSub][kCW]) {
+  const unsigned len = chunk_len(n, c);
   uint32_t carry = 0;  // last c' of the previous sub-block
 #pragma unroll
   for (int j = 0; j < kCSub; j++) {
-    const uint64_t i0 = chunk_value<kCW>(c, j, lane);
+    const unsigned p = chunk_pos<kCW>(j, lane);
     uint32_t prev = 0;
     if constexpr (DELTA) {
       const uint32_t up = __shfl_up(cc.cv[j][kCW - 1], 1, 64);
@@ -123,10 +146,54 @@ __device__ __forceinline__ void chunk_z(const ChunkCodes &cc, uint64_t n, uint64
 #pragma unroll
     for (int e = 0; e < kCW; e++) {
       const uint32_t d = DELTA ? cc.cv[j][e] - prev : cc.cv[j][e];
-      z[j][e] = i0 + e < n ? zigzag(d) : 0u;
+      z[j][e] = p + e < len ? zigzag(d) : 0u;
       prev = cc.cv[j][e];
     }
   }
+}
+
+// Packed words of a chunk of len values at w bits each (zeros up to the
+// record's 16-byte end): a multiple of 4.
+__device__ __forceinline__ unsigned packed_words(unsigned len, unsigned w) {
+  return (unsigned)(align16(((uint64_t)len * w + 7) / 8) / 4);
+}
+
+// The chunk's packed bits -- z values at w bits each, position j at bits
+// [j w, j w + w), least significant first -- assembled in the wavefront's
+// LDS row by atomic ORs (each value lands in one word, or straddles two).
+// z is zero past the chunk's end, so those positions add nothing.  LDS
+// operations of one wavefront complete in issue order, so wavefront-scope
+// fences suffice between the clearing, the ORs and later reads.
+__device__ __forceinline__ void pack_bits(const uint32_t (&z)[kCSub][kCW], unsigned len,
+                                          unsigned w, uint32_t *row, int lane) {
+  const unsigned nwords = packed_words(len, w);
+  const nt_u4 zero = {0u, 0u, 0u, 0u};
+  for (unsigned t = lane; 4 * t < nwords; t += 64) reinterpret_cast<nt_u4 *>(row)[t] = zero;
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  if (w) {
+    const unsigned lane_bp = (unsigned)(kCW * lane) * w;  // the lane's first bit in a sub-block
+#pragma unroll
+    for (int j = 0; j < kCSub; j++)
+#pragma unroll
+      for (int e = 0; e < kCW; e++) {
+        const unsigned bp = lane_bp + (unsigned)(64 * kCW * j + e) * w;
+        const unsigned q = bp >> 5, sh = bp & 31u;
+        const uint32_t v = z[j][e];
+        __hip_atomic_fetch_or(row + q, v << sh, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+        if (sh + w > 32)
+          __hip_atomic_fetch_or(row + q + 1, v >> (32 - sh), __ATOMIC_RELAXED,
+                                __HIP_MEMORY_SCOPE_WAVEFRONT);
+      }
+  }
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+}
+
+// The row's nwords packed words to dst (16-byte aligned), 128-bit stores.
+__device__ __forceinline__ void copy_words(const uint32_t *row, unsigned nwords, uint32_t *dst,
+                                           int lane) {
+  for (unsigned t = lane; 4 * t < nwords; t += 64)
+    __builtin_nontemporal_store(reinterpret_cast<const nt_u4 *>(row)[t],
+                                reinterpret_cast<nt_u4 *>(dst) + t);
 }
 
 // Width, mode and bitmap flag of one chunk (same on every lane).
@@ -175,7 +242,7 @@ __global__ __launch_bounds__(kBlock) void k_pack_plan(PackArgs a) {
   unsigned size = 0;
   if (c < nch) {
     ChunkCodes cc;
-    load_chunk(reinterpret_cast<const int32_t *>(a.in + 64), n, c, lane, cc);
+    load_chunk<true>(reinterpret_cast<const int32_t *>(a.in + 64), n, c, lane, cc);
     unsigned w, mode, hb;
     chunk_plan(cc, n, c, lane, w, mode, hb);
     const uint64_t len = min<uint64_t>(kChunk, n - c * kChunk);
@@ -256,16 +323,20 @@ __global__ __launch_bounds__(kBlock) void k_pack_scan(PackArgs a) {
   }
 }
 
-// Records, chunk table and outliers.  z values are staged in LDS so each
-// lane can assemble whole 32-bit output words.
+// Records, chunk table and outliers.  Each chunk's packed bits are
+// assembled in LDS (pack_bits) and leave in 128-bit stores.  Workgroups take
+// the tiles last to first: k_pack_plan read the codes first to last with
+// ordinary loads, so the codes it read last are still in the Infinity Cache
+// when this pass starts and are read from there.
 __global__ __launch_bounds__(kBlock) void k_pack_write(PackArgs a) {
-  __shared__ uint32_t s_z[kWaves][kChunk];
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  __shared__ uint32_t s_w[kWaves][kChunk];  // each wavefront's packed words
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const uint64_t n = a.n, nch = n_chunks(n);
   uint64_t k;
   if (!lcq1_header_ok(a.in, a.in_bytes, a.dtype, n, k)) return;  // uniform over the grid
   const uint64_t ot = packed_table_offset(nch), pl = packed_payload_offset(nch);
-  const uint64_t c = (uint64_t)blockIdx.x * kWaves + wave;
+  const uint64_t c = (uint64_t)(gridDim.x - 1 - blockIdx.x) * kWaves + wave;
   const bool active = c < nch;  // uniform over the wavefront
   unsigned w = 0, hb = 0;
   uint64_t len = 0;
@@ -282,10 +353,7 @@ __global__ __launch_bounds__(kBlock) void k_pack_write(PackArgs a) {
     uint32_t z[kCSub][kCW];
     if (mode) chunk_z<true>(cc, n, c, lane, z);
     else chunk_z<false>(cc, n, c, lane, z);
-#pragma unroll
-    for (int j = 0; j < kCSub; j++)
-#pragma unroll
-      for (int e = 0; e < kCW; e++) s_z[wave][64 * kCW * j + kCW * lane + e] = z[j][e];
+    pack_bits(z, (unsigned)len, w, s_w[wave], lane);
     // record header (16 bytes) and the outlier bitmap
     if (lane < 4) {
       const uint32_t word = lane == 0 ? (w | (mode << 8) | (hb << 16)) : 0u;
@@ -303,27 +371,9 @@ __global__ __launch_bounds__(kBlock) void k_pack_write(PackArgs a) {
       reinterpret_cast<uint64_t *>(a.out + 64)[c] = ct_in[c];
     }
   }
-  __syncthreads();  // every wavefront's z values are in LDS
-  if (active) {
-    // packed word t holds stream bits [32 t, 32 t + 32); the rest of the
-    // record, up to its 16-byte end, is zero
-    uint32_t *pw = reinterpret_cast<uint32_t *>(rec + 16 + (hb ? 128 : 0));
-    const uint64_t nbits = len * w;
-    const unsigned nwords = (unsigned)(align16((nbits + 7) / 8) / 4);
-    for (unsigned t = lane; t < nwords; t += 64) {
-      uint64_t acc = 0;
-      const uint64_t b0 = 32ull * t;
-      if (w && b0 < nbits) {
-        const uint64_t j0 = b0 / w, j1 = min<uint64_t>((b0 + 31) / w, len - 1);
-        for (uint64_t j = j0; j <= j1; j++) {
-          const uint64_t v = s_z[wave][j];
-          const int64_t sh = (int64_t)(j * w) - (int64_t)b0;
-          acc |= sh >= 0 ? (v << sh) : (v >> (-sh));
-        }
-      }
-      pw[t] = (uint32_t)acc;
-    }
-  }
+  if (active)
+    copy_words(s_w[wave], packed_words((unsigned)len, w),
+               reinterpret_cast<uint32_t *>(rec + 16 + (hb ? 128 : 0)), lane);
   // outliers, grid-stride over the raw words
   const uint64_t s = a.dtype == LCQ_F64 ? 8 : 4;
   const uint64_t payload = reinterpret_cast<const uint64_t *>(a.out + ot)[nch];
@@ -349,7 +399,8 @@ struct UnpackArgs {
 };
 
 __global__ __launch_bounds__(kBlock) void k_unpack(UnpackArgs a) {
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const uint64_t n = a.n, nch = n_chunks(n);
   const uint64_t s = a.dtype == LCQ_F64 ? 8 : 4;
   const uint64_t ot = packed_table_offset(nch), pl = packed_payload_offset(nch);
@@ -404,26 +455,30 @@ __global__ __launch_bounds__(kBlock) void k_unpack(UnpackArgs a) {
       s_w[wave][4 * t + 3] = v.w;
     }
   }
-  __syncthreads();
+  // each wavefront reads only its own row: LDS operations of one wavefront
+  // complete in issue order, so a wavefront-scope fence orders them
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
   if (ok) {
     const uint32_t mask = w == 32 ? 0xFFFFFFFFu : ((1u << w) - 1u);
+    const unsigned ulen = (unsigned)len;
+    const unsigned lane_bp = (unsigned)(kCW * lane) * w;  // the lane's first bit in a sub-block
     int32_t *codes = reinterpret_cast<int32_t *>(a.out + 64);
     uint32_t carry = 0;
 #pragma unroll
     for (int j = 0; j < kCSub; j++) {
       const uint64_t i0 = chunk_value<kCW>(c, j, lane);
-      const uint64_t l0 = i0 - c * kChunk;  // position in the chunk
+      const unsigned l0 = chunk_pos<kCW>(j, lane);  // position in the chunk
       uint32_t v[kCW];
 #pragma unroll
       for (int e = 0; e < kCW; e++) {
-        uint32_t z = 0;
-        if (w && l0 + e < len) {
-          const uint64_t b = (l0 + e) * w;
-          const unsigned q = (unsigned)(b >> 5), sh = (unsigned)(b & 31);
-          uint64_t pair = s_w[wave][q];
-          if (sh + w > 32 && q + 1 < nwords) pair |= (uint64_t)s_w[wave][q + 1] << 32;
-          z = (uint32_t)(pair >> sh) & mask;
-        }
+        // value bits [bp, bp + w): one funnel shift of the word pair (q, q+1)
+        // (the upper word only matters when the value straddles into it,
+        // and then it lies inside the record; otherwise its bits are
+        // masked off)
+        const unsigned bp = lane_bp + (unsigned)(64 * kCW * j + e) * w;
+        const unsigned q = bp >> 5, sh = bp & 31u;
+        const uint32_t lo = s_w[wave][q], hi = s_w[wave][min(q + 1, (unsigned)kChunk - 1)];
+        const uint32_t z = (w && l0 + e < ulen) ? __builtin_amdgcn_alignbit(hi, lo, sh) & mask : 0u;
         v[e] = unzigzag(z);
       }
       if (mode) {
@@ -446,7 +501,13 @@ __global__ __launch_bounds__(kBlock) void k_unpack(UnpackArgs a) {
       int32_t out[kCW];
 #pragma unroll
       for (int e = 0; e < kCW; e++) out[e] = ((fl >> e) & 1u) ? kSent : (int32_t)v[e];
-      store_codes<kCW>(codes, i0, n, out);
+      if (l0 + kCW <= ulen) {
+        store_codes<kCW, true>(codes, i0, n, out);
+      } else {
+#pragma unroll
+        for (int e = 0; e < kCW; e++)
+          if (l0 + e < ulen) codes[i0 + e] = out[e];
+      }
     }
     if (lane == 0) {
       reinterpret_cast<uint64_t *>(a.out + chunk_table_offset(n))[c] =

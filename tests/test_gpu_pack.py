@@ -120,3 +120,24 @@ def test_compress_decompress_pipeline():
             dec = lcq.decompress(pk, _tdt(dt), y.size).cpu().numpy()
             ref = O.dequantize(O.quantize(q, y, 1e-4), dt, y.size)
             assert np.array_equal(dec.view(np.uint8), ref.view(np.uint8))
+
+
+@pytest.mark.parametrize("q", ["abs", "rel"])
+def test_pack_many_groups_equals_oracle(q):
+    """2^21 + 333 codes: 513 workgroups of 4 chunks in 65 groups of the
+    record-offset scan, a ragged last chunk, records written by workgroups in
+    reverse order; packed bytes and the unpacked stream must equal the
+    oracle's."""
+    n = (1 << 21) + 333
+    x = synth.sines_1d(n, 710, dtype=np.float32)
+    x, _, _ = synth.inject_specials(x, n // 500, 711, 1e-3)
+    if q == "rel":
+        x = synth.rel_variant(np.nan_to_num(x.astype(np.float64)), 712, dtype=np.float32)
+    st = O.quantize(q, x, 1e-3)
+    want = O.pack(st, np.float32, n)
+    announce("pack many groups", q)
+    got, status = _gpu_pack(st, np.float32, n)
+    assert status == 0
+    assert first_diff(got, want) is None
+    back, status = _gpu_unpack(got, np.float32, n)
+    assert status == 0 and first_diff(back, st) is None
