@@ -161,35 +161,47 @@ class Clock:
         e.record()  # create it before it is handed to the library
         return e
 
-    def _once(self, fn, around_kernels):
+    def _once(self, fn, around_kernels, split=False):
         import paper_2407_15037_amd as lcq
         self.flush()
         e0, e1 = self._ev(), self._ev()
+        em = self._ev() if split else None
         if around_kernels:
             lcq.profile_events(e0, e1)
+            if split:
+                lcq.profile_mid_event(em)
             try:
                 fn()
             finally:
                 lcq.profile_events(None, None)
+                lcq.profile_mid_event(None)
         else:
             e0.record()
             fn()
             e1.record()
-        return e0, e1
+        return e0, e1, em
 
-    def _run(self, fns, around_kernels, warm, reps):
-        pairs = [[] for _ in fns]
+    def _run(self, fns, around_kernels, warm, reps, split=False):
+        evs = [[] for _ in fns]
         for r in range(warm + reps):
             for i, fn in enumerate(fns):
-                e = self._once(fn, around_kernels)
+                e = self._once(fn, around_kernels, split)
                 if r >= warm:
-                    pairs[i].append(e)
+                    evs[i].append(e)
         self.torch.cuda.synchronize()
-        return [summary([a.elapsed_time(b) * 1e3 for a, b in p]) for p in pairs]
+        out = []
+        for ev in evs:
+            t = summary([a.elapsed_time(b) * 1e3 for a, b, _ in ev])
+            if split:
+                # the two passes of a two-pass quantize, each on its own
+                t["pass1_us"] = summary([a.elapsed_time(m) * 1e3 for a, _, m in ev])["us"]
+                t["pass2_us"] = summary([m.elapsed_time(b) * 1e3 for _, b, m in ev])["us"]
+            out.append(t)
+        return out
 
-    def kernels(self, fn, warm=None, reps=None):
+    def kernels(self, fn, warm=None, reps=None, split=False):
         return self._run([fn], True, self.WARM if warm is None else warm,
-                         self.REPS if reps is None else reps)[0]
+                         self.REPS if reps is None else reps, split)[0]
 
     def whole(self, fn, warm=None, reps=None):
         return self._run([fn], False, self.WARM if warm is None else warm,
@@ -213,6 +225,19 @@ def op_entry(t, nbytes_alg, nbytes_in):
     e["frac_of_peak"] = round(rate(nbytes_alg, t["us"]) / HBM_PEAK_GBS, 4)
     e["alg_bytes"] = int(nbytes_alg)
     return e
+
+
+def pass_entries(t, n, s, k):
+    """The two kernels of a two-pass quantize, each against its share of the
+    operation's algorithmic bytes: pass 1 reads the n values and writes the
+    n codes; pass 2 writes the chunk table and the k outliers."""
+    p1 = n * s + 4 * n
+    p2 = 8 * ((n + 1023) // 1024) + k * s
+    return {"pass1": {"us": t["pass1_us"], "alg_bytes": p1,
+                      "alg_GBs": round(rate(p1, t["pass1_us"]), 1),
+                      "frac_of_peak": round(rate(p1, t["pass1_us"]) / HBM_PEAK_GBS, 4)},
+            "pass2": {"us": t["pass2_us"], "alg_bytes": p2,
+                      "alg_GBs": round(rate(p2, t["pass2_us"]), 1)}}
 
 
 # ------------------------------------------------------------------- plain --
@@ -265,14 +290,20 @@ def run_plain(args, clock, fields):
     ms_per_step = t_start.elapsed_time(t_end) / args.steps
     value = n * s * len(Q3) / (ms_per_step * 1e-3) / 1e9
 
-    # each operation alone: flushed, median of 9
+    # each operation alone: flushed, median of 9; then the quantize ops
+    # again with an event between their two kernels, for each pass alone
+    # (a separate set of runs: the extra event adds its own few us)
     tq = {q: clock.kernels(quant(q)) for q in Q3}
+    for q in ("abs", "rel"):
+        sp = clock.kernels(quant(q), split=True)
+        tq[q]["pass1_us"], tq[q]["pass2_us"] = sp["pass1_us"], sp["pass2_us"]
     noa_whole = clock.whole(quant("noa"))
     ks = {q: header_k(bufs[q]) for q in Q3}
     td = {q: clock.kernels(dequant(q)) for q in Q3}
     ops = {}
     for q in ("abs", "rel"):
         ops[f"quantize_{q}"] = op_entry(tq[q], alg_bytes_quant(n, s, ks[q]), n * s)
+        ops[f"quantize_{q}"].update(pass_entries(tq[q], n, s, ks[q]))
     # NOA quantize as a whole operation (range pass, parameters, both
     # quantize passes): its algorithmic bytes read the field twice
     ops["quantize_noa"] = op_entry(noa_whole, alg_bytes_quant(n, s, ks["noa"]) + n * s, n * s)
@@ -320,12 +351,16 @@ def run_f64(args, clock):
         return lambda: lcq.dequantize(bufs[q], torch.float64, n, out=outs[q], ws=ws[q])
 
     tq = {q: clock.kernels(quant(q)) for q in Q3}
+    for q in ("abs", "rel"):
+        sp = clock.kernels(quant(q), split=True)
+        tq[q]["pass1_us"], tq[q]["pass2_us"] = sp["pass1_us"], sp["pass2_us"]
     noa_whole = clock.whole(quant("noa"))
     ks = {q: header_k(bufs[q]) for q in Q3}
     td = {q: clock.kernels(dequant(q)) for q in Q3}
     ops = {}
     for q in ("abs", "rel"):
         ops[f"quantize_{q}"] = op_entry(tq[q], alg_bytes_quant(n, s, ks[q]), n * s)
+        ops[f"quantize_{q}"].update(pass_entries(tq[q], n, s, ks[q]))
     ops["quantize_noa"] = op_entry(noa_whole, alg_bytes_quant(n, s, ks["noa"]) + n * s, n * s)
     ops["quantize_noa"]["passes_only_us"] = tq["noa"]["us"]
     for q in Q3:
@@ -591,7 +626,10 @@ def run_batched(args, clock, oleg):
     log(f"batched: {len(fields)} fields, {total_bytes / 1e9:.2f} GB generated in "
         f"{time.time() - t0:.1f}s")
 
-    tuned = autotune.tune_batch(fields, log=log)
+    if args.batch_tune:
+        tuned = {"tune": args.batch_tune, "ms": None}  # fixed (profiler runs)
+    else:
+        tuned = autotune.tune_batch(fields, log=log)
     plan = BatchPlan(fields, tune=tuned["tune"])
     bq = clock.whole(plan.quantize)
     bd = clock.whole(plan.dequantize)
@@ -615,14 +653,18 @@ def run_batched(args, clock, oleg):
         for f, lb in zip(fields, loop_bufs):
             lcq.dequantize(lb["buf"], f["x"].dtype, f["x"].numel(), out=lb["out"], ws=lb["ws"])
 
-    lq = clock.whole(loop_q, warm=1, reps=5)
-    ld = clock.whole(loop_d, warm=1, reps=5)
+    if args.no_batch_loop:
+        lq = ld = None
+    else:
+        lq = clock.whole(loop_q, warm=1, reps=5)
+        ld = clock.whole(loop_d, warm=1, reps=5)
     # batch output == per-field output, every field, compared on the device
     same_streams = same_decodes = 0
-    for d, lb in zip(plan.fields, loop_bufs):
-        s1, s2 = int(d["nbytes"].item()), int(lb["nb"].item())
-        same_streams += int(s1 == s2 and torch.equal(d["stream"][:s1], lb["buf"][:s2]))
-        same_decodes += int(torch.equal(d["out"].view(torch.uint8), lb["out"].view(torch.uint8)))
+    if lq is not None:
+        for d, lb in zip(plan.fields, loop_bufs):
+            s1, s2 = int(d["nbytes"].item()), int(lb["nb"].item())
+            same_streams += int(s1 == s2 and torch.equal(d["stream"][:s1], lb["buf"][:s2]))
+            same_decodes += int(torch.equal(d["out"].view(torch.uint8), lb["out"].view(torch.uint8)))
     del loop_bufs
     torch.cuda.empty_cache()
     # algorithmic bytes of the batch: per field as for the plain path (NOA
@@ -640,16 +682,19 @@ def run_batched(args, clock, oleg):
         "total_input_GB": round(total_bytes / 1e9, 3),
         "tune": tuned,
         "batch_quantize_ms": round(bq["us"] / 1e3, 3), "batch_dequantize_ms": round(bd["us"] / 1e3, 3),
+        "alg_bytes_quantize": int(alg_q), "alg_bytes_dequantize": int(alg_d),
         "batch_quantize_frac_of_peak": round(rate(alg_q, bq["us"]) / HBM_PEAK_GBS, 4),
         "batch_dequantize_frac_of_peak": round(rate(alg_d, bd["us"]) / HBM_PEAK_GBS, 4),
-        "loop_quantize_ms": round(lq["us"] / 1e3, 3), "loop_dequantize_ms": round(ld["us"] / 1e3, 3),
         "batch_GBs": round(total_bytes / ((bq["us"] + bd["us"]) * 1e-6) / 1e9, 1),
-        "loop_GBs": round(total_bytes / ((lq["us"] + ld["us"]) * 1e-6) / 1e9, 1),
-        "speedup_vs_loop": round((lq["us"] + ld["us"]) / (bq["us"] + bd["us"]), 3),
-        "fields_equal_to_plain": f"{same_streams}/{len(fields)} streams, "
-                                 f"{same_decodes}/{len(fields)} decodes",
         "stream_check_first_bad": bad,
     }
+    if lq is not None:
+        res.update({
+            "loop_quantize_ms": round(lq["us"] / 1e3, 3), "loop_dequantize_ms": round(ld["us"] / 1e3, 3),
+            "loop_GBs": round(total_bytes / ((lq["us"] + ld["us"]) * 1e-6) / 1e9, 1),
+            "speedup_vs_loop": round((lq["us"] + ld["us"]) / (bq["us"] + bd["us"]), 3),
+            "fields_equal_to_plain": f"{same_streams}/{len(fields)} streams, "
+                                     f"{same_decodes}/{len(fields)} decodes"})
     if oleg:
         ok_s = ok_d = 0
         for i, (f, d) in enumerate(zip(fields, plan.fields)):
@@ -777,6 +822,13 @@ def main():
     ap.add_argument("--no-packing", action="store_true")
     ap.add_argument("--no-f64", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--batch-tune", default=None,
+                    help="fixed batch tuning string instead of the tuner (for profiler runs "
+                         "that must time the same plan)")
+    ap.add_argument("--no-batch-loop", action="store_true",
+                    help="skip the per-field launch loop the batched form is compared with "
+                         "(for hardware-counter runs: the profiler's counter mode cannot keep "
+                         "up with the loop's thousands of small launches)")
     ap.add_argument("--fields", type=int, default=2000)
     ap.add_argument("--pool", type=int, default=512)
     ap.add_argument("--rate", type=float, default=2000.0)
@@ -817,13 +869,17 @@ def main():
     fields = make_plain_inputs(args.grid, args.eb)
     plain = run_plain(args, clock, fields)
     ops = plain["ops"]
-    # dominant operation: the longest one that is a single per-value kernel
-    # path (NOA's quantize adds a range kernel, and its second read of the
-    # field may be served partly by the Infinity Cache, so it is reported as
-    # a whole operation but is no roofline candidate)
-    cands = [k for k in ops if k != "quantize_noa"]
-    dom_name = max(cands, key=lambda k: ops[k]["us"])
-    dom = ops[dom_name]
+    # dominant kernel: the longest-running per-value kernel of the step --
+    # pass 1 of the ABS / REL quantize, or a dequantize kernel (NOA's pass 1
+    # follows its range kernel inside the same call, so its read of the
+    # field may be served partly by the Infinity Cache: no candidate)
+    # name -> (timing entry, operation, key of the traffic table)
+    cands = {f"{k} pass 1 (k_quant_stage)": (ops[k]["pass1"], k, f"{k}_pass1")
+             for k in ("quantize_abs", "quantize_rel")}
+    cands.update({f"{k} (k_dequantize_chunks)": (ops[k], k, k)
+                  for k in ops if k.startswith("dequantize")})
+    dom_name = max(cands, key=lambda k: cands[k][0]["us"])
+    dom, dom_op, dom_key = cands[dom_name]
     result = {
         "metric": METRIC, "value": round(plain["value"], 2), "unit": "GB/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(plain["ms_per_step"], 4),
@@ -846,17 +902,18 @@ def main():
         "outlier_fraction": {q: plain["ks"][q] / plain["n"] for q in Q3},
         "stream_bytes": plain["sizes"],
         "autotune": tuned,
-        "roofline": {"kernel": dom_name + (" (pass 1 + pass 2)" if dom_name.startswith("quantize")
-                                           else ""),
+        "roofline": {"kernel": dom_name,
                      "bound": "hbm", "achieved": dom["alg_GBs"],
                      "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(dom["alg_GBs"] / HBM_PEAK_GBS, 4),
-                     "traffic": measured_traffic(dom_name, args.grid, args.eb,
+                     "traffic": measured_traffic(dom_key, args.grid, args.eb,
                                                  (lcq.tune_get("quantize", torch.float32),
                                                   lcq.tune_get("dequantize", torch.float32))),
                      "alg_bytes_per_launch": dom["alg_bytes"],
                      "alg_bytes_per_value": round(dom["alg_bytes"] / plain["n"], 4),
-                     "avg_launch_us": dom["us"], "timing": "median of 9, cache flushed"},
+                     "avg_launch_us": dom["us"], "timing": "median of 9, cache flushed",
+                     "operation": {"name": dom_op, "us": ops[dom_op]["us"],
+                                   "frac": ops[dom_op]["frac_of_peak"]}},
     }
     # each quantizer's quantize + dequantize pair on one field: algorithmic
     # bytes of both over their summed times (NOA: whole quantize operation,

@@ -144,6 +144,12 @@ const char *lcq_status_string(lcq_status s);
  * kernel (the per-value pass), on the call's stream.  Pass nulls to clear. */
 void lcq_profile_events(hipEvent_t before, hipEvent_t after);
 
+/* Measurement hook: when set (non-null), every following two-pass
+ * lcq_quantize call from the calling host thread also records `mid` between
+ * its two kernels (the streaming pass and the scan pass), so each pass can
+ * be timed on its own.  Pass null to clear. */
+void lcq_profile_mid_event(hipEvent_t mid);
+
 /* ------------------------------------------------- section 6 ablations --
  * The two variants the paper measures its guarantee against (section 6,
  * Table 7 and Tables 5-6).  They do NOT guarantee the bound / CPU-GPU
@@ -343,10 +349,8 @@ lcq_status lcq_serve(const lcq_server_config *cfg, const lcq_request *req, uint3
  * kernel variants; all produce the same bytes.  Variants 0-5: one
  * workgroup-wide tile per workgroup (loads in flight per thread x rounds;
  * quantize finds its outlier offset by a decoupled look-back over earlier
- * tiles).  Variants 6-10 (6 is the default): one wavefront per 1024-value
- * chunk, 1, 2 or 4 chunks per wavefront, loaded together (6-8) or software
- * pipelined (9, 10: the next chunk's loads in flight while one is
- * processed); quantize runs two kernels, a streaming pass that writes codes,
+ * tiles).  Variant 6 (the default): one wavefront per 1024-value chunk;
+ * quantize runs two kernels, a streaming pass that writes codes,
  * per-chunk outlier counts and staged outliers, then a scan pass that
  * writes the chunk table, the outliers and the header.  op 0 = quantize,
  * 1 = dequantize.  Process-wide; the tuner

@@ -13,7 +13,8 @@ __all__ = ["ABS", "REL", "NOA", "F32", "F64", "LCQError", "lib", "max_stream_byt
            "set_lookback_spin", "tune_variants", "tune_set", "tune_get",
            "inline_stream_bytes", "inline_workspace_bytes", "quantize_inline",
            "quantize_ablation", "dequantize_ablation", "ABL_ABS_UNCHECKED", "ABL_REL_LIBM",
-           "pack_max_bytes", "pack_workspace_bytes", "pack", "unpack", "compress", "decompress", "dequantize_inline", "SO_PATH"]
+           "pack_max_bytes", "pack_workspace_bytes", "pack", "unpack", "compress", "decompress", "dequantize_inline", "SO_PATH",
+           "profile_mid_event"]
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 SO_PATH = os.path.join(HERE, "liblcq.so")
@@ -69,6 +70,8 @@ _lib.lcq_status_string.argtypes = [_i32]
 _lib.lcq_status_string.restype = ctypes.c_char_p
 _lib.lcq_profile_events.argtypes = [_vp, _vp]
 _lib.lcq_profile_events.restype = None
+_lib.lcq_profile_mid_event.argtypes = [_vp]
+_lib.lcq_profile_mid_event.restype = None
 _lib.lcq_debug_set_lookback_spin.argtypes = [ctypes.c_uint32]
 _lib.lcq_debug_set_lookback_spin.restype = None
 _lib.lcq_tune_variants.argtypes = []
@@ -374,6 +377,12 @@ def set_lookback_spin(polls):
     """Testing hook: polls before the quantize look-back counts a missing
     predecessor tile from its input (default 4096; 0 = always)."""
     _lib.lcq_debug_set_lookback_spin(int(polls))
+
+
+def profile_mid_event(mid=None):
+    """Record a torch.cuda.Event between the two kernels of every following
+    two-pass quantize call from this thread (None clears)."""
+    _lib.lcq_profile_mid_event(ctypes.c_void_p(mid.cuda_event) if mid is not None else None)
 
 
 def profile_events(before=None, after=None):

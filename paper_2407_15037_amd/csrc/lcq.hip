@@ -50,7 +50,7 @@ constexpr uint64_t kWsState = 256;
 constexpr int kMinmaxBlocks = 8192;
 constexpr uint64_t kMinTileF32 = 4096, kMinTileF64 = 2048;  // smallest quantize tile of any variant
 
-thread_local hipEvent_t g_ev_before = nullptr, g_ev_after = nullptr;
+thread_local hipEvent_t g_ev_before = nullptr, g_ev_after = nullptr, g_ev_mid = nullptr;
 // Decode-call epochs tag the status word; starting from the clock keeps a
 // workspace left over from another process from matching a new call.
 uint64_t epoch_seed() {
@@ -369,6 +369,7 @@ void launch_quantize(const PlainQ &a, const StageQ &sq, hipStream_t s) {
   if constexpr (sh.cpw > 0) {
     hipLaunchKernelGGL((k_quant_stage<T, Q, sh.cpw, sh.pf>), dim3((unsigned)a.ntiles),
                        dim3(kBlock), 0, s, sq);
+    if (g_ev_mid) (void)hipEventRecord(g_ev_mid, s);
     hipLaunchKernelGGL((k_quant_finish<T, Q>), dim3((unsigned)sq.ngroups), dim3(kBlock), 0, s,
                        sq);
   } else {
@@ -386,10 +387,6 @@ void launch_quantize_variant(int v, const PlainQ &a, const StageQ &sq, hipStream
     case 4: return launch_quantize<T, Q, 4>(a, sq, s);
     case 5: return launch_quantize<T, Q, 5>(a, sq, s);
     case 6: return launch_quantize<T, Q, 6>(a, sq, s);
-    case 7: return launch_quantize<T, Q, 7>(a, sq, s);
-    case 8: return launch_quantize<T, Q, 8>(a, sq, s);
-    case 9: return launch_quantize<T, Q, 9>(a, sq, s);
-    case 10: return launch_quantize<T, Q, 10>(a, sq, s);
     default: return launch_quantize<T, Q, 0>(a, sq, s);
   }
 }
@@ -415,10 +412,6 @@ void launch_dequantize_variant(int v, uint64_t ntiles, const PlainD &a, hipStrea
     case 4: return launch_dequantize<T, 4>(ntiles, a, s);
     case 5: return launch_dequantize<T, 5>(ntiles, a, s);
     case 6: return launch_dequantize<T, 6>(ntiles, a, s);
-    case 7: return launch_dequantize<T, 7>(ntiles, a, s);
-    case 8: return launch_dequantize<T, 8>(ntiles, a, s);
-    case 9: return launch_dequantize<T, 9>(ntiles, a, s);
-    case 10: return launch_dequantize<T, 10>(ntiles, a, s);
     default: return launch_dequantize<T, 0>(ntiles, a, s);
   }
 }
@@ -844,5 +837,7 @@ void lcq_profile_events(hipEvent_t before, hipEvent_t after) {
   g_ev_before = before;
   g_ev_after = after;
 }
+
+void lcq_profile_mid_event(hipEvent_t mid) { g_ev_mid = mid; }
 
 }  // extern "C"

@@ -262,12 +262,11 @@ __device__ __forceinline__ unsigned encode_chunk(const StageField<T> &f, uint64_
   return cnt;
 }
 
-// Pass 1 for the CPW * kWaves chunks of workgroup `tile`.  PF > 0: PF
-// chunks per wavefront are loaded before any is encoded.  PF = 0: software
-// pipelined, the next chunk's loads are in flight while one is encoded.
+// Pass 1 for the CPW * kWaves chunks of workgroup `tile`, PF chunks per
+// wavefront loaded before any is encoded.
 template <typename T, int Q, int CPW, int PF>
 __device__ void quant_chunks(const StageField<T> &f, uint64_t tile) {
-  static_assert(PF == 0 || CPW % PF == 0, "whole prefetch groups");
+  static_assert(PF > 0 && CPW % PF == 0, "whole prefetch groups");
   constexpr int W = ChunkShape<T>::W, NSUB = ChunkShape<T>::NSUB;
   __shared__ unsigned s_cnt[kWaves];
   __shared__ typename FT<T>::U s_stage[kWaves][stage_cap<T>()];  // one row per wavefront
@@ -276,30 +275,18 @@ __device__ void quant_chunks(const StageField<T> &f, uint64_t tile) {
   const uint64_t nch = n_chunks(f.n);
   const EncK<T> k = enc_consts_pinned<T, Q>(f.p);
   unsigned wsum = 0;
-  if constexpr (PF == 0) {
-    T x[2][NSUB][W];
-    const uint64_t c0 = tile * CPW * kWaves + wave;
-    if (c0 < nch) load_chunk<T>(f.in, f.n, c0, lane, x[0]);
 #pragma unroll
-    for (int r = 0; r < CPW; r++) {
-      const uint64_t c = c0 + (uint64_t)r * kWaves;
-      if (r + 1 < CPW && c + kWaves < nch) load_chunk<T>(f.in, f.n, c + kWaves, lane, x[(r + 1) & 1]);
-      if (c < nch) wsum += encode_chunk<T, Q>(f, c, lane, x[r & 1], s_stage[wave], k);  // uniform
+  for (int r0 = 0; r0 < CPW; r0 += PF) {
+    T x[PF][NSUB][W];
+#pragma unroll
+    for (int p = 0; p < PF; p++) {
+      const uint64_t c = (tile * CPW + r0 + p) * kWaves + wave;
+      if (c < nch) load_chunk<T>(f.in, f.n, c, lane, x[p]);
     }
-  } else {
 #pragma unroll
-    for (int r0 = 0; r0 < CPW; r0 += PF) {
-      T x[PF][NSUB][W];
-#pragma unroll
-      for (int p = 0; p < PF; p++) {
-        const uint64_t c = (tile * CPW + r0 + p) * kWaves + wave;
-        if (c < nch) load_chunk<T>(f.in, f.n, c, lane, x[p]);
-      }
-#pragma unroll
-      for (int p = 0; p < PF; p++) {
-        const uint64_t c = (tile * CPW + r0 + p) * kWaves + wave;
-        if (c < nch) wsum += encode_chunk<T, Q>(f, c, lane, x[p], s_stage[wave], k);  // uniform
-      }
+    for (int p = 0; p < PF; p++) {
+      const uint64_t c = (tile * CPW + r0 + p) * kWaves + wave;
+      if (c < nch) wsum += encode_chunk<T, Q>(f, c, lane, x[p], s_stage[wave], k);  // uniform
     }
   }
   if (lane == 0) s_cnt[wave] = wsum;
@@ -656,43 +643,29 @@ __device__ __forceinline__ void decode_chunk(const DField<T> &f, uint64_t c, int
   for (int j = 0; j < NSUB; j++) store_vals<T, W>(f.out, chunk_value<W>(c, j, lane), n, y[j]);
 }
 
-// Decode the CPW * kWaves chunks of workgroup `tile`.  PF > 0: PF chunks per
-// wavefront loaded at a time.  PF = 0: software pipelined, the next chunk's
-// codes are in flight while one is decoded.
+// Decode the CPW * kWaves chunks of workgroup `tile`, PF chunks per
+// wavefront loaded at a time.
 template <typename T, int CPW, int PF, bool LIBM = false>
 __device__ void dequant_chunks(const DField<T> &f, uint64_t tile) {
-  static_assert(PF == 0 || CPW % PF == 0, "whole prefetch groups");
+  static_assert(PF > 0 && CPW % PF == 0, "whole prefetch groups");
   constexpr int W = ChunkShape<T>::W, NSUB = ChunkShape<T>::NSUB;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const uint64_t n = f.n;
   const uint64_t nch = n_chunks(n);
   const int32_t *codes = reinterpret_cast<const int32_t *>(f.stream + 64);
   const uint64_t lt = __lanemask_lt();
-  if constexpr (PF == 0) {
-    int32_t cc[2][NSUB][W];
-    const uint64_t c0 = tile * CPW * kWaves + wave;
-    if (c0 < nch) load_chunk_codes<W, NSUB>(codes, n, c0, lane, cc[0]);
 #pragma unroll
-    for (int r = 0; r < CPW; r++) {
-      const uint64_t c = c0 + (uint64_t)r * kWaves;
-      if (r + 1 < CPW && c + kWaves < nch)
-        load_chunk_codes<W, NSUB>(codes, n, c + kWaves, lane, cc[(r + 1) & 1]);
-      if (c < nch) decode_chunk<T, LIBM>(f, c, lane, lt, cc[r & 1]);  // uniform
+  for (int r0 = 0; r0 < CPW; r0 += PF) {
+    int32_t cc[PF][NSUB][W];
+#pragma unroll
+    for (int p = 0; p < PF; p++) {
+      const uint64_t c = (tile * CPW + r0 + p) * kWaves + wave;
+      if (c < nch) load_chunk_codes<W, NSUB>(codes, n, c, lane, cc[p]);
     }
-  } else {
 #pragma unroll
-    for (int r0 = 0; r0 < CPW; r0 += PF) {
-      int32_t cc[PF][NSUB][W];
-#pragma unroll
-      for (int p = 0; p < PF; p++) {
-        const uint64_t c = (tile * CPW + r0 + p) * kWaves + wave;
-        if (c < nch) load_chunk_codes<W, NSUB>(codes, n, c, lane, cc[p]);
-      }
-#pragma unroll
-      for (int p = 0; p < PF; p++) {
-        const uint64_t c = (tile * CPW + r0 + p) * kWaves + wave;
-        if (c < nch) decode_chunk<T, LIBM>(f, c, lane, lt, cc[p]);  // uniform
-      }
+    for (int p = 0; p < PF; p++) {
+      const uint64_t c = (tile * CPW + r0 + p) * kWaves + wave;
+      if (c < nch) decode_chunk<T, LIBM>(f, c, lane, lt, cc[p]);  // uniform
     }
   }
 }

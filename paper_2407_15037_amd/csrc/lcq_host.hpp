@@ -108,10 +108,10 @@ template <typename T> inline FieldParams<T> field_params(const HostParams &h) {
 // is one 128-bit load per thread of a 256-thread workgroup and a tile is
 // slots x rounds of them; quantize variants also choose the look-back depth
 // (loads per lane per round trip) and whether the rounds are unrolled.
-// Variants 6-10 are the chunk-per-wavefront kernels (two-pass quantize):
-// cpw chunks per wavefront per workgroup, pf of them loaded at a time, or
-// (pf = 0) software pipelined, one chunk's loads in flight while the
-// previous one is processed.
+// Variant 6 is the chunk-per-wavefront kernel (two-pass quantize): cpw
+// chunks per wavefront per workgroup, pf of them loaded at a time.  (More
+// chunks per wavefront, and software-pipelined forms, measured slower at
+// every size tried and were removed.)
 struct Shape {
   int slots, rounds;
   int cpw = 0, pf = 0;  // cpw > 0: chunk-per-wavefront kernel
@@ -121,15 +121,13 @@ struct QShape {
   bool unroll;
   int cpw = 0, pf = 0;  // cpw > 0: two-pass chunk-per-wavefront kernel
 };
-constexpr int kNumVariants = 11;
+constexpr int kNumVariants = 7;
 constexpr QShape kQVariants[kNumVariants] = {
     {4, 1, 1, true}, {4, 4, 1, true}, {4, 4, 4, true},
     {4, 4, 1, false}, {4, 2, 2, true}, {4, 1, 4, true},
-    {0, 0, 0, true, 1, 1}, {0, 0, 0, true, 2, 2}, {0, 0, 0, true, 4, 2},
-    {0, 0, 0, true, 2, 0}, {0, 0, 0, true, 4, 0}};
+    {0, 0, 0, true, 1, 1}};
 constexpr Shape kDVariants[kNumVariants] = {{4, 1}, {2, 2}, {4, 2}, {4, 4}, {2, 1}, {8, 1},
-                                            {0, 0, 1, 1}, {0, 0, 2, 2}, {0, 0, 4, 2},
-                                            {0, 0, 2, 0}, {0, 0, 4, 0}};
+                                            {0, 0, 1, 1}};
 
 // Values per quantize tile / codes per dequantize tile of a variant.
 inline uint64_t quant_tile_len(lcq_dtype t, int v) {

@@ -11,16 +11,16 @@ from gpu_util import announce
 pytestmark = pytest.mark.gpu
 
 
-def _pool(seed, m):
+def _pool(seed, m, lo=4 << 10, hi=8 << 20, grid=64):
     import torch
-    master = synth.grf_3d(64, seed, dtype=np.float64)
+    master = synth.grf_3d(grid, seed, dtype=np.float64)
     relm = synth.rel_variant(master, seed + 1, dtype=np.float64)
-    specs = synth.field_specs(m, seed + 2, 4 << 10, 8 << 20)
+    specs = synth.field_specs(m, seed + 2, lo, hi)
     pool = []
     for i, sp in enumerate(specs):
         x = synth.field_data(sp, master, relm, seed + 10 + i)
-        st = O.quantize(sp["q"], x, sp["eb"])
-        dec = O.dequantize(st, x.dtype, x.size)
+        st = O.quantize_mt(sp["q"], x, sp["eb"])
+        dec = O.dequantize_mt(st, x.dtype, x.size)
         tdt = torch.float32 if x.dtype == np.float32 else torch.float64
         pool.append(dict(spec=sp, tdt=tdt, x=torch.from_numpy(x).cuda(),
                          stream=torch.from_numpy(st).cuda(), stream_bytes=st.size,
@@ -62,6 +62,20 @@ def test_serve_mix_and_alone_match_oracle():
     alone = serve.run(alone_reqs, n_streams=1, arena_bytes=2 << 30)
     assert np.all(alone["status"] == 0)
     assert np.all(alone["mismatched"] == 0)
+
+
+def test_serve_full_size_range_matches_oracle():
+    """Payloads drawn from the served size range (64 KiB - 256 MiB,
+    log-uniform, mixed dtype / quantizer / bound), a Poisson mix of about
+    400 requests: every output equals the oracle's bytes."""
+    from paper_2407_15037_amd import serve
+    pool = _pool(25, 12, 64 << 10, 256 << 20, grid=256)
+    arr = synth.poisson_arrivals(2000, 0.2, 26)
+    reqs = _requests(pool, arr, 27)
+    announce("serve full range", len(reqs), max(p["spec"]["n"] for p in pool))
+    res = serve.run(reqs, n_streams=8, arena_bytes=16 << 30)
+    assert np.all(res["status"] == 0), res["status"]
+    assert np.all(res["mismatched"] == 0), np.flatnonzero(res["mismatched"])
 
 
 def test_serve_admission_under_tight_budget():
