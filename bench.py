@@ -433,7 +433,12 @@ def run_packing(args, clock, fields):
     against the LCQ1 stream), pack / unpack medians (events around each
     call, all of its kernels), and the unpacked stream equal to the
     original.  Algorithmic bytes: pack reads the LCQ1 stream and writes the
-    packed one; unpack the reverse."""
+    packed one; unpack the reverse.  Then the fused forms: compress (input to
+    packed stream in one call; algorithmic bytes: the input read -- twice
+    for NOA, whose range pass the method needs -- and the packed stream
+    written) against quantize then pack timed as one, and decompress
+    (packed stream to values) against unpack then dequantize; their bytes
+    and values compared with the two-call results on the device."""
     import torch
     import paper_2407_15037_amd as lcq
     dev = torch.device("cuda:0")
@@ -444,7 +449,6 @@ def run_packing(args, clock, fields):
         xt = torch.from_numpy(fields[q]).to(dev)
         st, nb = lcq.quantize(xt, q, eb)
         size = int(nb.item())
-        del xt
         pk = torch.empty(lcq.pack_max_bytes(torch.float32, n), dtype=torch.uint8, device=dev)
         pnb = torch.zeros(1, dtype=torch.int64, device=dev)
         ws = torch.empty(lcq.pack_workspace_bytes(torch.float32, n), dtype=torch.uint8, device=dev)
@@ -455,13 +459,47 @@ def run_packing(args, clock, fields):
         psize = int(pnb.item())
         tu = clock.whole(lambda: lcq.unpack(pk, torch.float32, n, out=back, nbytes=bnb, ws=ws))
         same = int(bnb.item()) == size and torch.equal(back[:size], st[:size])
+        del back
         alg = size + psize
         res[q] = {"lcq1_bytes": size, "packed_bytes": psize,
                   "ratio_vs_input": round(n * 4 / psize, 3), "ratio_vs_lcq1": round(size / psize, 3),
                   "pack_us": tp["us"], "unpack_us": tu["us"],
                   "pack": op_entry(tp, alg, n * 4), "unpack": op_entry(tu, alg, n * 4),
                   "unpacked_equals_stream": bool(same)}
-        del st, pk, ws, back
+        # fused forms
+        cpk = torch.empty_like(pk)
+        cnb = torch.zeros(1, dtype=torch.int64, device=dev)
+        cws = torch.empty(lcq.compress_workspace_bytes(q, torch.float32, n), dtype=torch.uint8,
+                          device=dev)
+        tc = clock.whole(lambda: lcq.compress(xt, q, eb, out=cpk, nbytes=cnb, ws=cws))
+        c_same = int(cnb.item()) == psize and torch.equal(cpk[:psize], pk[:psize])
+        qws = torch.empty(lcq.workspace_bytes(q, torch.float32, n), dtype=torch.uint8, device=dev)
+        t2 = clock.whole(lambda: (lcq.quantize(xt, q, eb, out=st, nbytes=nb, ws=qws),
+                                  lcq.pack(st, torch.float32, n, stream_bytes=size, out=pk,
+                                           nbytes=pnb, ws=ws)))
+        del cws, qws
+        out = torch.empty(n, dtype=torch.float32, device=dev)
+        ref = torch.empty(n, dtype=torch.float32, device=dev)
+        dws = torch.zeros(64, dtype=torch.uint8, device=dev)
+        td = clock.whole(lambda: lcq.decompress(cpk, torch.float32, n, packed_bytes=psize, out=out,
+                                                ws=dws))
+        d_ok = lcq.stream_status(dws) == 0
+        back = torch.empty(lcq.max_stream_bytes(torch.float32, n), dtype=torch.uint8, device=dev)
+        t2d = clock.whole(lambda: (lcq.unpack(pk, torch.float32, n, packed_bytes=psize, out=back,
+                                              nbytes=bnb, ws=ws),
+                                   lcq.dequantize(back, torch.float32, n, stream_bytes=size, out=ref,
+                                                  ws=ws)))
+        d_same = d_ok and torch.equal(out.view(torch.int32), ref.view(torch.int32))
+        reads = 2 if q == "noa" else 1
+        res[q]["compress"] = op_entry(tc, reads * n * 4 + psize, n * 4)
+        res[q]["compress"]["quantize_then_pack_us"] = t2["us"]
+        res[q]["compress"]["speedup_vs_two_calls"] = round(t2["us"] / tc["us"], 3)
+        res[q]["compress"]["equals_two_calls"] = bool(c_same)
+        res[q]["decompress"] = op_entry(td, psize + n * 4, n * 4)
+        res[q]["decompress"]["unpack_then_dequantize_us"] = t2d["us"]
+        res[q]["decompress"]["speedup_vs_two_calls"] = round(t2d["us"] / td["us"], 3)
+        res[q]["decompress"]["equals_two_calls"] = bool(d_same)
+        del st, pk, ws, back, cpk, out, ref, xt
         torch.cuda.empty_cache()
     return res
 

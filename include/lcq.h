@@ -214,6 +214,32 @@ lcq_status lcq_unpack(lcq_dtype t, const void *d_packed, uint64_t packed_bytes, 
                       void *d_stream, uint64_t stream_cap, uint64_t *d_stream_bytes,
                       void *d_ws, uint64_t ws_bytes, hipStream_t stream);
 
+/* ----------------------------------------- fused compress / decompress --
+ * The quantizer (sections 2.2, 3.1-3.3) and the packing stage above in one
+ * call each, for HBM-bound use: the int32 codes never reach memory.
+ * lcq_compress writes exactly the bytes lcq_pack(lcq_quantize(...)) writes
+ * for the same q, t, eb and input (packed_cap >= lcq_pack_max_bytes(t, n),
+ * ws_bytes >= lcq_compress_workspace_bytes(q, t, n), arguments and errors
+ * as for lcq_quantize; never fails because of the data).  Its input is read
+ * twice: the first pass classifies, bins and checks every value (sections
+ * 2.2, 3.1-3.3) and sizes the records; the second takes the outliers from
+ * the first pass's flags and recomputes the other values' bins with the
+ * encoder's own operations, so both see the same codes.
+ * lcq_decompress decodes a packed stream into d_out[0..n) with exactly the
+ * values lcq_dequantize(lcq_unpack(...)) gives; the header, every record's
+ * offset, width and extent, and every chunk-table entry are checked on the
+ * device, a mismatch recorded in the status word (first 8 bytes of d_ws,
+ * >= 8 bytes; read with lcq_stream_status) and the output then unspecified
+ * (nothing outside it is written).  The workspace needs no initialisation. */
+uint64_t lcq_compress_workspace_bytes(lcq_quantizer q, lcq_dtype t, uint64_t n); /* 0: bad args */
+lcq_status lcq_compress(lcq_quantizer q, lcq_dtype t, double eb,
+                        const void *d_in, uint64_t n,
+                        void *d_packed, uint64_t packed_cap, uint64_t *d_packed_bytes,
+                        void *d_ws, uint64_t ws_bytes, hipStream_t stream);
+lcq_status lcq_decompress(lcq_dtype t, const void *d_packed, uint64_t packed_bytes,
+                          void *d_out, uint64_t n,
+                          void *d_ws, uint64_t ws_bytes, hipStream_t stream);
+
 /* ---------------------------------------------- in-line outlier layout --
  * The paper's own layout (section 3.1): outliers stored in-line with the
  * bins.  One word of the field type's width per value -- its code (the same

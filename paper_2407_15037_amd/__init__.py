@@ -13,7 +13,8 @@ __all__ = ["ABS", "REL", "NOA", "F32", "F64", "LCQError", "lib", "max_stream_byt
            "set_lookback_spin", "tune_variants", "tune_set", "tune_get",
            "inline_stream_bytes", "inline_workspace_bytes", "quantize_inline",
            "quantize_ablation", "dequantize_ablation", "ABL_ABS_UNCHECKED", "ABL_REL_LIBM",
-           "pack_max_bytes", "pack_workspace_bytes", "pack", "unpack", "compress", "decompress", "dequantize_inline", "SO_PATH",
+           "pack_max_bytes", "pack_workspace_bytes", "pack", "unpack", "compress", "decompress",
+           "compress_workspace_bytes", "dequantize_inline", "SO_PATH",
            "profile_mid_event"]
 
 HERE = os.path.dirname(os.path.abspath(__file__))
@@ -42,7 +43,7 @@ _lib.lcq_quantize.argtypes = [_i32, _i32, _dbl, _vp, _u64, _vp, _u64, _vp, _vp, 
 _lib.lcq_quantize.restype = _i32
 _lib.lcq_quantize_noalloc.argtypes = [_i32, _i32, _dbl, _vp, _u64, _vp, _u64, _vp, _vp]
 _lib.lcq_quantize_noalloc.restype = _i32
-NOALLOC_SCRATCH_BYTES = 32 << 20  # LCQ_NOALLOC_SCRATCH_BYTES of include/lcq.h
+NOALLOC_SCRATCH_BYTES = 128 << 20  # LCQ_NOALLOC_SCRATCH_BYTES of include/lcq.h
 _lib.lcq_dequantize.argtypes = [_i32, _vp, _u64, _vp, _u64, _vp, _u64, _vp]
 _lib.lcq_dequantize.restype = _i32
 _lib.lcq_inline_stream_bytes.argtypes = [_i32, _u64]
@@ -64,6 +65,12 @@ _lib.lcq_pack_workspace_bytes.restype = _u64
 for _name in ("lcq_pack", "lcq_unpack"):
     getattr(_lib, _name).argtypes = [_i32, _vp, _u64, _u64, _vp, _u64, _vp, _vp, _u64, _vp]
     getattr(_lib, _name).restype = _i32
+_lib.lcq_compress_workspace_bytes.argtypes = [_i32, _i32, _u64]
+_lib.lcq_compress_workspace_bytes.restype = _u64
+_lib.lcq_compress.argtypes = [_i32, _i32, _dbl, _vp, _u64, _vp, _u64, _vp, _vp, _u64, _vp]
+_lib.lcq_compress.restype = _i32
+_lib.lcq_decompress.argtypes = [_i32, _vp, _u64, _vp, _u64, _vp, _u64, _vp]
+_lib.lcq_decompress.restype = _i32
 _lib.lcq_stream_status.argtypes = [_vp, _vp, ctypes.POINTER(ctypes.c_int32)]
 _lib.lcq_stream_status.restype = _i32
 _lib.lcq_status_string.argtypes = [_i32]
@@ -286,24 +293,46 @@ def unpack(packed_buf, dtype, n, *, packed_bytes=None, out=None, nbytes=None, ws
     return out, nbytes
 
 
-def compress(x, q, eb, *, stream=None):
-    """Quantize then pack: the guaranteed quantizer followed by the lossless
-    packing stage.  Returns the packed stream as a uint8 CUDA tensor of
-    exactly its size (one host synchronisation to read that size)."""
-    buf, nb = quantize(x, q, eb, stream=stream)
-    pk, pnb = pack(buf, x.dtype, x.numel(), stream=stream)
-    return pk[: int(pnb.item())]
+def compress_workspace_bytes(q, dtype, n):
+    return int(_lib.lcq_compress_workspace_bytes(_q(q), _dtype_code(dtype), n))
 
 
-def decompress(packed, dtype, n, *, stream=None):
-    """Unpack then dequantize a compress() result; raises LCQError if either
-    stage finds the stream inconsistent."""
+def compress(x, q, eb, *, out=None, nbytes=None, ws=None, stream=None):
+    """Quantize x and pack the codes in one call (lcq_compress): the bytes of
+    pack(quantize(x)), the codes never written to memory.  Returns (packed,
+    nbytes): a uint8 device tensor of capacity pack_max_bytes and a
+    one-element int64 device tensor receiving the packed size."""
     import torch
-    ws = _empty(64, torch.uint8, packed.device, stream, zero=True)
-    st, nb = unpack(packed, dtype, n, ws=ws, stream=stream)
-    _check(stream_status(ws, stream), "lcq_unpack")
-    out = dequantize(st, dtype, n, ws=ws, stream=stream)
-    _check(stream_status(ws, stream), "lcq_dequantize")
+    if not x.is_cuda or not x.is_contiguous():
+        raise ValueError("x must be a contiguous CUDA tensor")
+    dt = _dtype_code(x.dtype)
+    n = x.numel()
+    if out is None:
+        out = _empty(int(_lib.lcq_pack_max_bytes(dt, n)), torch.uint8, x.device, stream)
+    if nbytes is None:
+        nbytes = _empty(1, torch.int64, x.device, stream)
+    if ws is None:
+        ws = _empty(compress_workspace_bytes(q, x.dtype, n), torch.uint8, x.device, stream)
+    st = _lib.lcq_compress(_q(q), dt, float(eb), _ptr(x) if n else None, n, _ptr(out),
+                           out.numel(), _ptr(nbytes), _ptr(ws), ws.numel(), _stream_handle(stream))
+    _check(st, "lcq_compress")
+    return out, nbytes
+
+
+def decompress(packed, dtype, n, *, packed_bytes=None, out=None, ws=None, stream=None):
+    """Decode a packed stream straight to n values (lcq_decompress): the
+    values of dequantize(unpack(packed)).  The device checks land in ws (read
+    them with stream_status); packed_bytes defaults to the tensor's size."""
+    import torch
+    dt = _dtype_code(dtype)
+    if out is None:
+        out = _empty(n, dtype, packed.device, stream)
+    if ws is None:
+        ws = _empty(64, torch.uint8, packed.device, stream)
+    pb = packed.numel() if packed_bytes is None else int(packed_bytes)
+    st = _lib.lcq_decompress(dt, _ptr(packed), pb, _ptr(out) if n else None, n, _ptr(ws),
+                             ws.numel(), _stream_handle(stream))
+    _check(st, "lcq_decompress")
     return out
 
 

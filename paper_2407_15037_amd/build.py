@@ -14,7 +14,7 @@ ROOT = os.path.dirname(HERE)
 SO = os.path.join(HERE, "liblcq.so")
 OBJDIR = os.path.join(HERE, "_build")
 SRCS = [os.path.join(HERE, "csrc", f) for f in ("lcq.hip", "lcq_batch.hip", "lcq_serve.hip",
-                                                       "lcq_pack.hip")]
+                                                       "lcq_pack.hip", "lcq_compress.hip")]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [

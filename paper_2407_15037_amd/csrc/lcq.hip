@@ -5,10 +5,11 @@
 //
 // Kernels (all memory-bound; no MFMA, nothing here is a contraction):
 //   k_clear        zero the look-back state before a quantize (ABS / REL)
-//   k_minmax       NOA pass 1: finite min / max per workgroup (section 2.1.3);
-//                  also zeroes the look-back state
-//   k_noa_params   NOA pass 2 (one workgroup): reduce the per-workgroup
-//                  results and derive ebR, step, 1/step on the device
+//   k_minmax       NOA pass 1 (lcq_range.hpp): finite min / max per
+//                  workgroup (section 2.1.3); also zeroes the look-back state
+//   k_noa_params   NOA pass 2 (lcq_range.hpp, one workgroup): reduce the
+//                  per-workgroup results and derive ebR, step, 1/step on the
+//                  device
 //   k_quantize     one tile per workgroup, tile = workgroup index (no atomic
 //                  counter): quant_tile (classify / bin / reconstruct / verify,
 //                  code stores, in-tile ranks, bounded decoupled look-back,
@@ -28,6 +29,7 @@
 #include "lcq_math.hpp"
 #include "lcq_tile.hpp"
 #include "lcq_chunk.hpp"
+#include "lcq_range.hpp"
 
 #pragma clang fp contract(off)
 
@@ -47,7 +49,6 @@ namespace {
 // then       NOA per-workgroup (min, max) pairs
 constexpr uint64_t kWsParams = 64;
 constexpr uint64_t kWsState = 256;
-constexpr int kMinmaxBlocks = 8192;
 constexpr uint64_t kMinTileF32 = 4096, kMinTileF64 = 2048;  // smallest quantize tile of any variant
 
 thread_local hipEvent_t g_ev_before = nullptr, g_ev_after = nullptr, g_ev_mid = nullptr;
@@ -121,68 +122,6 @@ __global__ void k_clear(uint64_t *p, uint64_t count) {
   for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count;
        i += (uint64_t)gridDim.x * blockDim.x)
     p[i] = 0;
-}
-
-// NOA pass 1: finite min / max of a contiguous share of the input.
-template <typename T>
-__global__ __launch_bounds__(kBlock) void k_minmax(const T *in, uint64_t n, uint64_t share,
-                                                   T *partials, uint64_t *clear,
-                                                   uint64_t clear_count) {
-  const uint64_t gtid = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
-  const uint64_t gsize = (uint64_t)gridDim.x * kBlock;
-  for (uint64_t i = gtid; i < clear_count; i += gsize) clear[i] = 0;
-  const uint64_t b = min((uint64_t)blockIdx.x * share, n);
-  const uint64_t e = min(b + share, n);
-  T lo, hi;
-  block_minmax<T>(in, b, e, lo, hi);
-  if (threadIdx.x == 0) {
-    partials[2 * blockIdx.x] = lo;
-    partials[2 * blockIdx.x + 1] = hi;
-  }
-}
-
-// NOA pass 2: reduce the shares and derive the parameters.
-template <typename T>
-__global__ __launch_bounds__(kBlock) void k_noa_params(const T *partials, int nparts, T eb_down,
-                                                       DevParams *out) {
-  T lo = (T)INFINITY, hi = (T)-INFINITY;
-  // eight (min, max) pairs in flight per thread, then the rest one by one
-  int i = threadIdx.x;
-  for (; i + 7 * kBlock < nparts; i += 8 * kBlock) {
-    T l[8], h[8];
-#pragma unroll
-    for (int u = 0; u < 8; u++) {
-      l[u] = partials[2 * (i + u * kBlock)];
-      h[u] = partials[2 * (i + u * kBlock) + 1];
-    }
-#pragma unroll
-    for (int u = 0; u < 8; u++) {
-      lo = fmin(lo, l[u]);
-      hi = fmax(hi, h[u]);
-    }
-  }
-  for (; i < nparts; i += kBlock) {
-    lo = fmin(lo, partials[2 * i]);
-    hi = fmax(hi, partials[2 * i + 1]);
-  }
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) {
-    lo = fmin(lo, __shfl_xor(lo, o, 64));
-    hi = fmax(hi, __shfl_xor(hi, o, 64));
-  }
-  __shared__ T s_lo[kWaves], s_hi[kWaves];
-  const int wave = threadIdx.x >> 6;
-  if ((threadIdx.x & 63) == 0) {
-    s_lo[wave] = lo;
-    s_hi[wave] = hi;
-  }
-  __syncthreads();
-  if (threadIdx.x != 0) return;
-  for (int w = 1; w < kWaves; w++) {
-    lo = fmin(lo, s_lo[w]);
-    hi = fmax(hi, s_hi[w]);
-  }
-  *out = noa_params<T>(lo, hi, eb_down);
 }
 
 // Two-pass chunk-per-wavefront quantize (lcq_chunk.hpp).
@@ -477,18 +416,9 @@ lcq_status run_quantize(double eb, const void *d_in, uint64_t n, void *d_stream,
 
   if (Q == kNOA) {
     T *partials = reinterpret_cast<T *>(ws + ws_partials_off((lcq_dtype)dt, n));
-    // each workgroup reduces a contiguous share of whole 128-bit vectors
-    const uint64_t W = 16 / sizeof(T);
-    const uint64_t per = (uint64_t)kBlock * W * 8;  // >= 8 vectors per thread
-    uint64_t nb = (n + per - 1) / per;
-    nb = nb < 1 ? 1 : (nb > (uint64_t)kMinmaxBlocks ? kMinmaxBlocks : nb);
-    uint64_t share = (n + nb - 1) / nb;
-    share = (share + W - 1) / W * W;
-    hipLaunchKernelGGL(k_minmax<T>, dim3((unsigned)nb), dim3(kBlock), 0, s,
-                       static_cast<const T *>(d_in), n, share, partials, clear_ptr, clear_count);
-    hipLaunchKernelGGL(k_noa_params<T>, dim3(1), dim3(kBlock), 0, s, partials, (int)nb,
-                       from_bits((typename FT<T>::U)hp.eb_down),
-                       reinterpret_cast<DevParams *>(ws + kWsParams));
+    launch_noa_range<T>(static_cast<const T *>(d_in), n, partials, clear_ptr, clear_count,
+                        from_bits((typename FT<T>::U)hp.eb_down),
+                        reinterpret_cast<DevParams *>(ws + kWsParams), s);
   } else if (clear_count) {
     const unsigned nb = (unsigned)std::min<uint64_t>((clear_count + kBlock - 1) / kBlock, 1024);
     hipLaunchKernelGGL(k_clear, dim3(nb), dim3(kBlock), 0, s, clear_ptr, clear_count);
@@ -529,18 +459,9 @@ lcq_status run_quantize_inline(double eb, const void *d_in, uint64_t n, void *d_
   a.hdr[7] = hp.aux1;
   if (Q == kNOA) {
     T *partials = reinterpret_cast<T *>(ws + kWsState);
-    const uint64_t W = 16 / sizeof(T);
-    const uint64_t per = (uint64_t)kBlock * W * 8;
-    uint64_t nb = (n + per - 1) / per;
-    nb = nb < 1 ? 1 : (nb > (uint64_t)kMinmaxBlocks ? kMinmaxBlocks : nb);
-    uint64_t share = (n + nb - 1) / nb;
-    share = (share + W - 1) / W * W;
-    hipLaunchKernelGGL(k_minmax<T>, dim3((unsigned)nb), dim3(kBlock), 0, s,
-                       static_cast<const T *>(d_in), n, share, partials, (uint64_t *)nullptr,
-                       (uint64_t)0);
-    hipLaunchKernelGGL(k_noa_params<T>, dim3(1), dim3(kBlock), 0, s, partials, (int)nb,
-                       from_bits((typename FT<T>::U)hp.eb_down),
-                       reinterpret_cast<DevParams *>(ws + kWsParams));
+    launch_noa_range<T>(static_cast<const T *>(d_in), n, partials, nullptr, 0,
+                        from_bits((typename FT<T>::U)hp.eb_down),
+                        reinterpret_cast<DevParams *>(ws + kWsParams), s);
   }
   const uint64_t tile = (uint64_t)kBlock * (16 / sizeof(T)) * kInlineSlots;
   const uint64_t ntiles = n ? (n + tile - 1) / tile : 1;

@@ -346,14 +346,13 @@ template <typename T> struct FinishField {
 };
 
 // Outliers of chunk c from its codes and the input (a chunk with more
-// outliers than were staged), written from index P on.  One wavefront; all
+// outliers than were staged), written to outl from index P on.  One wavefront; all
 // code and value loads of the chunk are issued before the first rank.
 template <typename T>
-__device__ void rescan_chunk(const FinishField<T> &f, uint64_t c, uint64_t P, int lane) {
-  using U = typename FT<T>::U;
+__device__ void rescan_chunk(const FinishField<T> &f, typename FT<T>::U *outl, uint64_t c,
+                             uint64_t P, int lane) {
   constexpr int W = ChunkShape<T>::W, NSUB = ChunkShape<T>::NSUB;
   const int32_t *codes = reinterpret_cast<const int32_t *>(f.stream + 64);
-  U *outl = reinterpret_cast<U *>(f.stream + outlier_offset(f.n));
   int32_t cc[NSUB][W];
   T x[NSUB][W];
 #pragma unroll
@@ -377,15 +376,14 @@ __device__ void rescan_chunk(const FinishField<T> &f, uint64_t c, uint64_t P, in
   }
 }
 
-// The staged row of chunk c (cnt <= stage cap outliers) to its place from
-// index P on.  One wavefront; every load is issued before the first store.
+// The staged row of chunk c (cnt <= stage cap outliers) to outl from index
+// P on.  One wavefront; every load is issued before the first store.
 template <typename T>
-__device__ __forceinline__ void copy_staged(const FinishField<T> &f, uint64_t c, uint64_t P,
-                                            unsigned cnt, int lane) {
+__device__ __forceinline__ void copy_staged(const FinishField<T> &f, typename FT<T>::U *outl,
+                                            uint64_t c, uint64_t P, unsigned cnt, int lane) {
   using U = typename FT<T>::U;
   constexpr unsigned kCap = (unsigned)stage_cap<T>();
   constexpr int kR = (int)kCap / 64;
-  U *outl = reinterpret_cast<U *>(f.stream + outlier_offset(f.n));
   U v[kR];
 #pragma unroll
   for (int r = 0; r < kR; r++) {
@@ -553,8 +551,8 @@ __device__ void quant_finish(const FinishField<T> &f, uint64_t g) {
       const uint64_t cv = s_P[i];
       const unsigned cc = s_c[i];
       const uint64_t P = chunk_first_outlier<T>(f, cv, lane);
-      if (cc <= kCap) copy_staged<T>(f, cv, P, cc, lane);
-      else rescan_chunk<T>(f, cv, P, lane);
+      if (cc <= kCap) copy_staged<T>(f, outl, cv, P, cc, lane);
+      else rescan_chunk<T>(f, outl, cv, P, lane);
     }
     __syncthreads();  // s_wt, s_P and s_c are rewritten by the next batch
   }
@@ -594,18 +592,19 @@ __device__ __forceinline__ void load_chunk_codes(const int32_t *codes, uint64_t 
 
 // Decode chunk c from its codes cc: gather its outliers, check its
 // chunk-table entry, store its values (LIBM: the library-exp2 REL ablation).
-template <typename T, bool LIBM>
-__device__ __forceinline__ void decode_chunk(const DField<T> &f, uint64_t c, int lane, uint64_t lt,
-                                             const int32_t (&cc)[ChunkShape<T>::NSUB][ChunkShape<T>::W]) {
-  using U = typename FT<T>::U;
+// cur and nxt: the chunk's chunk-table entry and the next one (the
+// outlier count after the last chunk), loaded by the caller; the outliers
+// are at outl (their LCQ1 place for decode_chunk).  REL: the stream's
+// quantizer is REL (a template parameter, so each value's decode is
+// straight-line code and a sentinel's zero one select).
+template <typename T, bool LIBM, bool REL>
+__device__ __forceinline__ void decode_chunk_at(const DField<T> &f, uint64_t cur, uint64_t nxt,
+                                                const typename FT<T>::U *outl, uint64_t c,
+                                                int lane, uint64_t lt,
+                                                const int32_t (&cc)[ChunkShape<T>::NSUB][ChunkShape<T>::W]) {
   constexpr int W = ChunkShape<T>::W, NSUB = ChunkShape<T>::NSUB;
   constexpr unsigned kLaneMask = (1u << W) - 1;
   const uint64_t n = f.n;
-  const uint64_t nch = n_chunks(n);
-  const uint64_t *chunk_tab = reinterpret_cast<const uint64_t *>(f.stream + chunk_table_offset(n));
-  const U *outl = reinterpret_cast<const U *>(f.stream + outlier_offset(n));
-  const uint64_t cur = chunk_tab[c];
-  const uint64_t nxt = (c + 1 < nch) ? chunk_tab[c + 1] : f.k;
   unsigned om = 0;
   T y[NSUB][W];
 #pragma unroll
@@ -614,7 +613,8 @@ __device__ __forceinline__ void decode_chunk(const DField<T> &f, uint64_t c, int
 #pragma unroll
     for (int e = 0; e < W; e++) {
       const bool sent = cc[j][e] == kSent;
-      y[j][e] = sent ? (T)0 : decode<T, LIBM>(cc[j][e], f.step, f.rel);
+      const T v = decode<T, LIBM>(cc[j][e], f.step, REL);  // (harmless for a sentinel)
+      y[j][e] = sent ? (T)0 : v;
       if (sent && i0 + e < n) om |= 1u << (W * j + e);
     }
   }
@@ -641,6 +641,18 @@ __device__ __forceinline__ void decode_chunk(const DField<T> &f, uint64_t c, int
     report_status(f.status, f.tag, LCQ_ERR_STREAM);
 #pragma unroll
   for (int j = 0; j < NSUB; j++) store_vals<T, W>(f.out, chunk_value<W>(c, j, lane), n, y[j]);
+}
+
+template <typename T, bool LIBM>
+__device__ __forceinline__ void decode_chunk(const DField<T> &f, uint64_t c, int lane, uint64_t lt,
+                                             const int32_t (&cc)[ChunkShape<T>::NSUB][ChunkShape<T>::W]) {
+  using U = typename FT<T>::U;
+  const uint64_t *chunk_tab = reinterpret_cast<const uint64_t *>(f.stream + chunk_table_offset(f.n));
+  const U *outl = reinterpret_cast<const U *>(f.stream + outlier_offset(f.n));
+  const uint64_t cur = chunk_tab[c];
+  const uint64_t nxt = (c + 1 < n_chunks(f.n)) ? chunk_tab[c + 1] : f.k;
+  if (f.rel) decode_chunk_at<T, LIBM, true>(f, cur, nxt, outl, c, lane, lt, cc);  // uniform
+  else decode_chunk_at<T, LIBM, false>(f, cur, nxt, outl, c, lane, lt, cc);
 }
 
 // Decode the CPW * kWaves chunks of workgroup `tile`, PF chunks per

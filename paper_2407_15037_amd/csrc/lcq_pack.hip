@@ -1,24 +1,10 @@
 // lcq_pack.hip -- lossless packing stage for LCQ1 streams on gfx950.
 //
 // The paper hands the quantizer's output to further lossless stages of its
-// framework without naming them; this stage is defined here.  Per chunk of
-// 1024 codes (the stream format's chunk), with c'_j = code_j or 0 for an
-// outlier sentinel:
-//   plain mode  z_j = zigzag(c'_j)
-//   delta mode  z_j = zigzag(c'_j - c'_{j-1}), c'_{-1} = 0 (mod 2^32)
-// w = bit length of the chunk's largest z (0..32), the narrower mode kept
-// (plain on a tie); z_j occupies bits [j w, j w + w) of the chunk's record,
-// least significant bit first.  A chunk with outliers also carries a
-// 1024-bit outlier bitmap.  The LCQ1 chunk table and outliers are carried
-// over verbatim, so unpacking restores the LCQ1 stream byte for byte.
-//
-//   [0,64)                  LCQ1 header with magic "LCQP"
-//   [64, 64+8C)             LCQ1 chunk table
-//   ot = align16(64+8C)     u64 record offset per chunk (+1: payload size)
-//   pl = align16(ot+8(C+1)) records: 16-byte header (u8 w, u8 mode, u8
-//                           has_bitmap, 13 zero bytes), [128-byte bitmap],
-//                           packed bits, zeros to a 16-byte boundary
-//   oo = align16(pl+payload) the k raw outliers
+// framework without naming them; this stage is defined here (format and
+// shared device helpers in lcq_packfmt.hpp).  The LCQ1 chunk table and
+// outliers are carried over verbatim, so unpacking restores the LCQ1 stream
+// byte for byte.
 //
 // Kernels (one wavefront per chunk, the chunk-per-wavefront mapping):
 //   k_pack_plan   widths, modes and record sizes; one atomic add per
@@ -43,46 +29,16 @@
 #include "lcq_chunk.hpp"
 #include "lcq_host.hpp"
 #include "lcq_math.hpp"
+#include "lcq_packfmt.hpp"
 #include "lcq_tile.hpp"
 
 using namespace lcq;
 
 namespace {
 
-constexpr uint32_t kMagicPacked = 0x5051434Cu;  // "LCQP"
 constexpr int kCW = 4;                           // codes per lane per sub-block
 constexpr int kCSub = (int)kChunk / (64 * kCW);  // 4 sub-blocks per chunk
 constexpr uint64_t kPackTile = kChunk * kWaves;  // codes per workgroup (4 chunks)
-
-__host__ __device__ inline uint64_t packed_table_offset(uint64_t C) { return align16(64 + 8 * C); }
-__host__ __device__ inline uint64_t packed_payload_offset(uint64_t C) {
-  return align16(packed_table_offset(C) + 8 * (C + 1));
-}
-__host__ __device__ inline uint64_t record_bytes(uint64_t len, unsigned w, unsigned hb) {
-  return 16 + (hb ? 128 : 0) + align16((len * w + 7) / 8);
-}
-
-// Values of chunk c below n, and a lane's position inside its chunk (32-bit
-// bounds tests).
-__device__ __forceinline__ unsigned chunk_len(uint64_t n, uint64_t c) {
-  const uint64_t left = n - c * kChunk;
-  return left >= kChunk ? kChunk : (unsigned)left;
-}
-template <int W> __device__ __forceinline__ unsigned chunk_pos(int j, int lane) {
-  return (unsigned)(64 * W * j + W * lane);
-}
-
-__device__ __forceinline__ uint32_t zigzag(uint32_t v) {
-  return (v << 1) ^ (uint32_t)((int32_t)v >> 31);
-}
-__device__ __forceinline__ uint32_t unzigzag(uint32_t z) { return (z >> 1) ^ (0u - (z & 1u)); }
-__device__ __forceinline__ unsigned bitlen(uint32_t v) { return v ? 32u - (unsigned)__clz((int)v) : 0u; }
-
-__device__ __forceinline__ uint32_t wave_or(uint32_t v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v |= __shfl_xor(v, o, 64);
-  return v;
-}
 
 // The LCQ1 header of an input stream describes exactly this call.
 __device__ __forceinline__ bool lcq1_header_ok(const uint8_t *s, uint64_t bytes, int dtype,
@@ -101,9 +57,6 @@ struct ChunkCodes {
   unsigned flags;  // bit 4 j + e: outlier sentinel
 };
 
-// CACHED: ordinary loads, which leave the codes in the Infinity Cache for
-// the writing pass that re-reads them (otherwise streaming loads).
-template <bool CACHED = false>
 __device__ __forceinline__ void load_chunk(const int32_t *codes, uint64_t n, uint64_t c, int lane,
                                            ChunkCodes &cc) {
   cc.flags = 0;
@@ -113,12 +66,7 @@ __device__ __forceinline__ void load_chunk(const int32_t *codes, uint64_t n, uin
     const uint64_t i0 = chunk_value<kCW>(c, j, lane);
     const unsigned p = chunk_pos<kCW>(j, lane);
     int32_t v[kCW];
-    if (CACHED && p + kCW <= len) {
-      const nt_i4 q = *reinterpret_cast<const nt_i4 *>(codes + i0);
-      v[0] = q.x; v[1] = q.y; v[2] = q.z; v[3] = q.w;
-    } else {
-      load_codes<kCW>(codes, i0, n, v);
-    }
+    load_codes<kCW>(codes, i0, n, v);
 #pragma unroll
     for (int e = 0; e < kCW; e++) {
       const bool sent = v[e] == kSent && p + e < len;
@@ -132,88 +80,15 @@ __device__ __forceinline__ void load_chunk(const int32_t *codes, uint64_t n, uin
 template <bool DELTA>
 __device__ __forceinline__ void chunk_z(const ChunkCodes &cc, uint64_t n, uint64_t c, int lane,
                                         uint32_t (&z)[kCSub][kCW]) {
-  const unsigned len = chunk_len(n, c);
-  uint32_t carry = 0;  // last c' of the previous sub-block
-#pragma unroll
-  for (int j = 0; j < kCSub; j++) {
-    const unsigned p = chunk_pos<kCW>(j, lane);
-    uint32_t prev = 0;
-    if constexpr (DELTA) {
-      const uint32_t up = __shfl_up(cc.cv[j][kCW - 1], 1, 64);
-      prev = lane == 0 ? carry : up;
-      carry = __shfl(cc.cv[j][kCW - 1], 63, 64);
-    }
-#pragma unroll
-    for (int e = 0; e < kCW; e++) {
-      const uint32_t d = DELTA ? cc.cv[j][e] - prev : cc.cv[j][e];
-      z[j][e] = p + e < len ? zigzag(d) : 0u;
-      prev = cc.cv[j][e];
-    }
-  }
-}
-
-// Packed words of a chunk of len values at w bits each (zeros up to the
-// record's 16-byte end): a multiple of 4.
-__device__ __forceinline__ unsigned packed_words(unsigned len, unsigned w) {
-  return (unsigned)(align16(((uint64_t)len * w + 7) / 8) / 4);
-}
-
-// The chunk's packed bits -- z values at w bits each, position j at bits
-// [j w, j w + w), least significant first -- assembled in the wavefront's
-// LDS row by atomic ORs (each value lands in one word, or straddles two).
-// z is zero past the chunk's end, so those positions add nothing.  LDS
-// operations of one wavefront complete in issue order, so wavefront-scope
-// fences suffice between the clearing, the ORs and later reads.
-__device__ __forceinline__ void pack_bits(const uint32_t (&z)[kCSub][kCW], unsigned len,
-                                          unsigned w, uint32_t *row, int lane) {
-  const unsigned nwords = packed_words(len, w);
-  const nt_u4 zero = {0u, 0u, 0u, 0u};
-  for (unsigned t = lane; 4 * t < nwords; t += 64) reinterpret_cast<nt_u4 *>(row)[t] = zero;
-  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-  if (w) {
-    const unsigned lane_bp = (unsigned)(kCW * lane) * w;  // the lane's first bit in a sub-block
-#pragma unroll
-    for (int j = 0; j < kCSub; j++)
-#pragma unroll
-      for (int e = 0; e < kCW; e++) {
-        const unsigned bp = lane_bp + (unsigned)(64 * kCW * j + e) * w;
-        const unsigned q = bp >> 5, sh = bp & 31u;
-        const uint32_t v = z[j][e];
-        __hip_atomic_fetch_or(row + q, v << sh, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
-        if (sh + w > 32)
-          __hip_atomic_fetch_or(row + q + 1, v >> (32 - sh), __ATOMIC_RELAXED,
-                                __HIP_MEMORY_SCOPE_WAVEFRONT);
-      }
-  }
-  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-}
-
-// The row's nwords packed words to dst (16-byte aligned), 128-bit stores.
-__device__ __forceinline__ void copy_words(const uint32_t *row, unsigned nwords, uint32_t *dst,
-                                           int lane) {
-  for (unsigned t = lane; 4 * t < nwords; t += 64)
-    __builtin_nontemporal_store(reinterpret_cast<const nt_u4 *>(row)[t],
-                                reinterpret_cast<nt_u4 *>(dst) + t);
+  lcq::chunk_z<DELTA, kCW, kCSub>(cc.cv, chunk_len(n, c), lane, z);
 }
 
 // Width, mode and bitmap flag of one chunk (same on every lane).
 __device__ __forceinline__ void chunk_plan(const ChunkCodes &cc, uint64_t n, uint64_t c, int lane,
                                            unsigned &w, unsigned &mode, unsigned &hb) {
-  uint32_t z[kCSub][kCW];
-  uint32_t op = 0, od = 0;
-  chunk_z<false>(cc, n, c, lane, z);
-#pragma unroll
-  for (int j = 0; j < kCSub; j++)
-#pragma unroll
-    for (int e = 0; e < kCW; e++) op |= z[j][e];
-  chunk_z<true>(cc, n, c, lane, z);
-#pragma unroll
-  for (int j = 0; j < kCSub; j++)
-#pragma unroll
-    for (int e = 0; e < kCW; e++) od |= z[j][e];
-  const unsigned wp = bitlen(wave_or(op)), wd = bitlen(wave_or(od));
-  mode = wd < wp ? 1u : 0u;
-  w = mode ? wd : wp;
+  const unsigned len = chunk_len(n, c);
+  if (len == kChunk) chunk_width<true, kCW, kCSub>(cc.cv, len, lane, w, mode);
+  else chunk_width<false, kCW, kCSub>(cc.cv, len, lane, w, mode);
   hb = __ballot(cc.flags != 0) ? 1u : 0u;
 }
 
@@ -242,7 +117,7 @@ __global__ __launch_bounds__(kBlock) void k_pack_plan(PackArgs a) {
   unsigned size = 0;
   if (c < nch) {
     ChunkCodes cc;
-    load_chunk<true>(reinterpret_cast<const int32_t *>(a.in + 64), n, c, lane, cc);
+    load_chunk(reinterpret_cast<const int32_t *>(a.in + 64), n, c, lane, cc);
     unsigned w, mode, hb;
     chunk_plan(cc, n, c, lane, w, mode, hb);
     const uint64_t len = min<uint64_t>(kChunk, n - c * kChunk);
@@ -324,10 +199,7 @@ __global__ __launch_bounds__(kBlock) void k_pack_scan(PackArgs a) {
 }
 
 // Records, chunk table and outliers.  Each chunk's packed bits are
-// assembled in LDS (pack_bits) and leave in 128-bit stores.  Workgroups take
-// the tiles last to first: k_pack_plan read the codes first to last with
-// ordinary loads, so the codes it read last are still in the Infinity Cache
-// when this pass starts and are read from there.
+// assembled in LDS (pack_bits) and leave in 128-bit stores.
 __global__ __launch_bounds__(kBlock) void k_pack_write(PackArgs a) {
   __shared__ uint32_t s_w[kWaves][kChunk];  // each wavefront's packed words
   const int lane = threadIdx.x & 63;
@@ -336,7 +208,7 @@ __global__ __launch_bounds__(kBlock) void k_pack_write(PackArgs a) {
   uint64_t k;
   if (!lcq1_header_ok(a.in, a.in_bytes, a.dtype, n, k)) return;  // uniform over the grid
   const uint64_t ot = packed_table_offset(nch), pl = packed_payload_offset(nch);
-  const uint64_t c = (uint64_t)(gridDim.x - 1 - blockIdx.x) * kWaves + wave;
+  const uint64_t c = (uint64_t)blockIdx.x * kWaves + wave;
   const bool active = c < nch;  // uniform over the wavefront
   unsigned w = 0, hb = 0;
   uint64_t len = 0;
@@ -353,19 +225,8 @@ __global__ __launch_bounds__(kBlock) void k_pack_write(PackArgs a) {
     uint32_t z[kCSub][kCW];
     if (mode) chunk_z<true>(cc, n, c, lane, z);
     else chunk_z<false>(cc, n, c, lane, z);
-    pack_bits(z, (unsigned)len, w, s_w[wave], lane);
-    // record header (16 bytes) and the outlier bitmap
-    if (lane < 4) {
-      const uint32_t word = lane == 0 ? (w | (mode << 8) | (hb << 16)) : 0u;
-      reinterpret_cast<uint32_t *>(rec)[lane] = word;
-    }
-    if (hb) {
-#pragma unroll
-      for (int j = 0; j < kCSub; j++) {
-        const unsigned fw = gather_flag_word<kCW>((cc.flags >> (kCW * j)) & 0xFu, lane);
-        if ((lane & 7) == 0) reinterpret_cast<uint32_t *>(rec + 16)[8 * j + lane / 8] = fw;
-      }
-    }
+    pack_bits<kCW, kCSub>(z, (unsigned)len, w, s_w[wave], lane);
+    write_record_head<kCW, kCSub>(rec, w, mode, hb, cc.flags, lane);
     if (lane == 0) {
       const uint64_t *ct_in = reinterpret_cast<const uint64_t *>(a.in + chunk_table_offset(n));
       reinterpret_cast<uint64_t *>(a.out + 64)[c] = ct_in[c];
@@ -410,9 +271,7 @@ __global__ __launch_bounds__(kBlock) void k_unpack(UnpackArgs a) {
   const uint64_t h0 = hd[0], k = hd[2];
   const uint64_t *offs = reinterpret_cast<const uint64_t *>(a.in + ot);
   const uint64_t payload = offs[nch];
-  const uint64_t want0 = (uint64_t)kMagicPacked | (1ull << 32) | ((uint64_t)a.dtype << 40) |
-                         ((uint64_t)kLog2Chunk << 56);
-  const bool bad = (h0 & ~(0xFFull << 48)) != want0 || ((h0 >> 48) & 0xFF) > 2 || hd[1] != n ||
+  const bool bad = (h0 & ~(0xFFull << 48)) != packed_word0(a.dtype) || ((h0 >> 48) & 0xFF) > 2 || hd[1] != n ||
                    k > n || payload > a.in_bytes - pl ||
                    align16(pl + payload) + k * s > a.in_bytes ||
                    outlier_offset(n) + k * s > a.out_cap;
@@ -441,72 +300,24 @@ __global__ __launch_bounds__(kBlock) void k_unpack(UnpackArgs a) {
     }
     if (!ok && lane == 0) report_status(a.status, tag, LCQ_ERR_STREAM);
   }
-  // stage the record's packed words with 128-bit loads (the packed area is
-  // a whole number of 16-byte units inside the record)
-  const uint64_t nbits = ok ? len * w : 0;
-  const unsigned nwords = (unsigned)((nbits + 31) / 32);
+  // the record's packed words (a whole number of 16-byte units inside the
+  // record) staged in LDS, then its codes
   if (ok) {
-    const nt_u4 *pw4 = reinterpret_cast<const nt_u4 *>(rec + 16 + (hb ? 128 : 0));
-    for (unsigned t = lane; 4 * t < nwords; t += 64) {
-      const nt_u4 v = __builtin_nontemporal_load(pw4 + t);
-      s_w[wave][4 * t] = v.x;
-      s_w[wave][4 * t + 1] = v.y;
-      s_w[wave][4 * t + 2] = v.z;
-      s_w[wave][4 * t + 3] = v.w;
-    }
-  }
-  // each wavefront reads only its own row: LDS operations of one wavefront
-  // complete in issue order, so a wavefront-scope fence orders them
-  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-  if (ok) {
-    const uint32_t mask = w == 32 ? 0xFFFFFFFFu : ((1u << w) - 1u);
     const unsigned ulen = (unsigned)len;
-    const unsigned lane_bp = (unsigned)(kCW * lane) * w;  // the lane's first bit in a sub-block
+    stage_words(rec + 16 + (hb ? 128 : 0), packed_words(ulen, w), s_w[wave], lane);
+    int32_t out[kCSub][kCW];
+    record_codes<kCW, kCSub>(s_w[wave], hb ? rec + 16 : nullptr, w, mode, ulen, lane, out);
     int32_t *codes = reinterpret_cast<int32_t *>(a.out + 64);
-    uint32_t carry = 0;
 #pragma unroll
     for (int j = 0; j < kCSub; j++) {
       const uint64_t i0 = chunk_value<kCW>(c, j, lane);
       const unsigned l0 = chunk_pos<kCW>(j, lane);  // position in the chunk
-      uint32_t v[kCW];
-#pragma unroll
-      for (int e = 0; e < kCW; e++) {
-        // value bits [bp, bp + w): one funnel shift of the word pair (q, q+1)
-        // (the upper word only matters when the value straddles into it,
-        // and then it lies inside the record; otherwise its bits are
-        // masked off)
-        const unsigned bp = lane_bp + (unsigned)(64 * kCW * j + e) * w;
-        const unsigned q = bp >> 5, sh = bp & 31u;
-        const uint32_t lo = s_w[wave][q], hi = s_w[wave][min(q + 1, (unsigned)kChunk - 1)];
-        const uint32_t z = (w && l0 + e < ulen) ? __builtin_amdgcn_alignbit(hi, lo, sh) & mask : 0u;
-        v[e] = unzigzag(z);
-      }
-      if (mode) {
-        // prefix sum over the chunk in value order (mod 2^32)
-#pragma unroll
-        for (int e = 1; e < kCW; e++) v[e] += v[e - 1];
-        uint32_t incl = v[kCW - 1];
-#pragma unroll
-        for (int o = 1; o < 64; o <<= 1) {
-          const uint32_t t = __shfl_up(incl, o, 64);
-          if (lane >= o) incl += t;
-        }
-        const uint32_t excl = incl - v[kCW - 1] + carry;
-#pragma unroll
-        for (int e = 0; e < kCW; e++) v[e] += excl;
-        carry += __shfl(incl, 63, 64);
-      }
-      unsigned fl = 0;
-      if (hb) fl = (rec[16 + l0 / 8] >> (l0 % 8)) & 0xFu;
-      int32_t out[kCW];
-#pragma unroll
-      for (int e = 0; e < kCW; e++) out[e] = ((fl >> e) & 1u) ? kSent : (int32_t)v[e];
       if (l0 + kCW <= ulen) {
-        store_codes<kCW, true>(codes, i0, n, out);
+        store_codes<kCW, true>(codes, i0, n, out[j]);
       } else {
 #pragma unroll
         for (int e = 0; e < kCW; e++)
-          if (l0 + e < ulen) codes[i0 + e] = out[e];
+          if (l0 + e < ulen) codes[i0 + e] = out[j][e];
       }
     }
     if (lane == 0) {

@@ -1,0 +1,277 @@
+// lcq_packfmt.hpp -- device helpers of the packed (LCQP) stream format,
+// shared by the packing stage (lcq_pack.hip) and the fused compress /
+// decompress path (lcq_compress.hip).
+//
+// Per chunk of 1024 codes, with c'_j = code_j or 0 for an outlier sentinel:
+//   plain mode  z_j = zigzag(c'_j)
+//   delta mode  z_j = zigzag(c'_j - c'_{j-1}), c'_{-1} = 0 (mod 2^32)
+// w = bit length of the chunk's largest z (0..32), the narrower mode kept
+// (plain on a tie); z_j occupies bits [j w, j w + w) of the chunk's record,
+// least significant bit first.  A chunk with outliers also carries a
+// 1024-bit outlier bitmap.
+//
+//   [0,64)                  LCQ1 header with magic "LCQP"
+//   [64, 64+8C)             LCQ1 chunk table
+//   ot = align16(64+8C)     u64 record offset per chunk (+1: payload size)
+//   pl = align16(ot+8(C+1)) records: 16-byte header (u8 w, u8 mode, u8
+//                           has_bitmap, 13 zero bytes), [128-byte bitmap],
+//                           packed bits, zeros to a 16-byte boundary
+//   oo = align16(pl+payload) the k raw outliers
+//
+// Lane layout: the chunk kernels' W x NSUB (lcq_chunk.hpp): lane l holds
+// positions 64 W j + W l + e of the chunk, e < W, j < NSUB.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "lcq_math.hpp"
+#include "lcq_tile.hpp"
+
+namespace lcq {
+
+constexpr uint32_t kMagicPacked = 0x5051434Cu;  // "LCQP"
+
+__host__ __device__ inline uint64_t packed_table_offset(uint64_t C) { return align16(64 + 8 * C); }
+__host__ __device__ inline uint64_t packed_payload_offset(uint64_t C) {
+  return align16(packed_table_offset(C) + 8 * (C + 1));
+}
+__host__ __device__ inline uint64_t record_bytes(uint64_t len, unsigned w, unsigned hb) {
+  return 16 + (hb ? 128 : 0) + align16((len * w + 7) / 8);
+}
+// Header word 0 of a packed stream of dtype t (quantizer byte masked off).
+__host__ __device__ inline uint64_t packed_word0(int dtype) {
+  return (uint64_t)kMagicPacked | (1ull << 32) | ((uint64_t)dtype << 40) |
+         ((uint64_t)kLog2Chunk << 56);
+}
+
+// Values of chunk c below n, and a lane's position inside its chunk (32-bit
+// bounds tests).
+__device__ __forceinline__ unsigned chunk_len(uint64_t n, uint64_t c) {
+  const uint64_t left = n - c * kChunk;
+  return left >= kChunk ? kChunk : (unsigned)left;
+}
+template <int W> __device__ __forceinline__ unsigned chunk_pos(int j, int lane) {
+  return (unsigned)(64 * W * j + W * lane);
+}
+
+__device__ __forceinline__ uint32_t zigzag(uint32_t v) {
+  return (v << 1) ^ (uint32_t)((int32_t)v >> 31);
+}
+__device__ __forceinline__ uint32_t unzigzag(uint32_t z) { return (z >> 1) ^ (0u - (z & 1u)); }
+__device__ __forceinline__ unsigned bitlen(uint32_t v) { return v ? 32u - (unsigned)__clz((int)v) : 0u; }
+
+// z values of a chunk from its c' values (sentinels already 0) in plain
+// (DELTA false) or delta mode; 0 at positions len and beyond (FULL: len is
+// 1024).
+template <bool DELTA, int W, int NSUB, bool FULL = false>
+__device__ __forceinline__ void chunk_z(const uint32_t (&cv)[NSUB][W], unsigned len, int lane,
+                                        uint32_t (&z)[NSUB][W]) {
+  uint32_t carry = 0;  // last c' of the previous sub-block
+#pragma unroll
+  for (int j = 0; j < NSUB; j++) {
+    const unsigned p = chunk_pos<W>(j, lane);
+    uint32_t prev = 0;
+    if constexpr (DELTA) {
+      const uint32_t up = __shfl_up(cv[j][W - 1], 1, 64);
+      prev = lane == 0 ? carry : up;
+      carry = __shfl(cv[j][W - 1], 63, 64);
+    }
+#pragma unroll
+    for (int e = 0; e < W; e++) {
+      const uint32_t d = DELTA ? cv[j][e] - prev : cv[j][e];
+      z[j][e] = (FULL || p + e < len) ? zigzag(d) : 0u;
+      prev = cv[j][e];
+    }
+  }
+}
+
+// Bit length of the largest zigzag code of the int32 values in [lo, hi]
+// (zigzag grows with |v| on either side of 0, so the extremes decide).
+__device__ __forceinline__ unsigned zz_width(int32_t lo, int32_t hi) {
+  return bitlen(max(zigzag((uint32_t)lo), zigzag((uint32_t)hi)));
+}
+
+__device__ __forceinline__ int32_t wave_max_i(int32_t v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o, 64));
+  return v;
+}
+__device__ __forceinline__ int32_t wave_min_i(int32_t v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = min(v, __shfl_xor(v, o, 64));
+  return v;
+}
+
+// Width and mode of a chunk from its c' values (sentinels already 0; same
+// on every lane), from extremes instead of every z: the plain width is that
+// of the largest zigzag of the c' values, the delta width that of their
+// differences (mod 2^32, read as int32).  FULL: the chunk has 1024 values
+// (no position to mask).
+template <bool FULL, int W, int NSUB>
+__device__ __forceinline__ void chunk_width(const uint32_t (&cv)[NSUB][W], unsigned len,
+                                               int lane, unsigned &w, unsigned &mode) {
+  int32_t plo = 0, phi = 0, dlo = 0, dhi = 0;
+  uint32_t carry = 0;  // last c' of the previous sub-block
+#pragma unroll
+  for (int j = 0; j < NSUB; j++) {
+    const uint32_t up = __shfl_up(cv[j][W - 1], 1, 64);
+    uint32_t prev = lane == 0 ? carry : up;
+    carry = __shfl(cv[j][W - 1], 63, 64);
+    const unsigned p = chunk_pos<W>(j, lane);
+#pragma unroll
+    for (int e = 0; e < W; e++) {
+      const bool in = FULL || p + e < len;
+      const int32_t v = in ? (int32_t)cv[j][e] : 0;
+      const int32_t d = in ? (int32_t)(cv[j][e] - prev) : 0;
+      plo = min(plo, v);
+      phi = max(phi, v);
+      dlo = min(dlo, d);
+      dhi = max(dhi, d);
+      prev = cv[j][e];
+    }
+  }
+  const unsigned wp = zz_width(wave_min_i(plo), wave_max_i(phi));
+  const unsigned wd = zz_width(wave_min_i(dlo), wave_max_i(dhi));
+  mode = wd < wp ? 1u : 0u;
+  w = mode ? wd : wp;
+}
+
+// Packed words of a chunk of len values at w bits each (zeros up to the
+// record's 16-byte end): a multiple of 4.
+__device__ __forceinline__ unsigned packed_words(unsigned len, unsigned w) {
+  return (unsigned)(align16(((uint64_t)len * w + 7) / 8) / 4);
+}
+
+// The chunk's packed bits -- z values at w bits each, position p at bits
+// [p w, p w + w), least significant first -- assembled in the wavefront's
+// LDS row by atomic ORs.  A lane's values of a sub-block are consecutive
+// positions, so they go two at a time: the pair as one 64-bit piece (2 w <=
+// 64 bits), shifted to its bit offset inside its first word, lands in at
+// most three words.  z is zero past the chunk's end, so those positions add
+// nothing, and every word touched lies inside the 1024-word row.  LDS
+// operations of one wavefront complete in issue order, so wavefront-scope
+// fences suffice between the clearing, the ORs and later reads.
+template <int W, int NSUB>
+__device__ __forceinline__ void pack_bits(const uint32_t (&z)[NSUB][W], unsigned len, unsigned w,
+                                          uint32_t *row, int lane) {
+  static_assert(W % 2 == 0, "values go in pairs");
+  const unsigned nwords = packed_words(len, w);
+  const nt_u4 zero = {0u, 0u, 0u, 0u};
+  for (unsigned t = lane; 4 * t < nwords; t += 64) reinterpret_cast<nt_u4 *>(row)[t] = zero;
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  if (w) {
+    const unsigned lane_bp = (unsigned)(W * lane) * w;  // the lane's first bit in a sub-block
+#pragma unroll
+    for (int j = 0; j < NSUB; j++)
+#pragma unroll
+      for (int e = 0; e < W; e += 2) {
+        const unsigned bp = lane_bp + (unsigned)(64 * W * j + e) * w;
+        const unsigned q = bp >> 5, sh = bp & 31u;
+        const uint64_t piece = (uint64_t)z[j][e] | ((uint64_t)z[j][e + 1] << w);
+        const uint64_t lo = piece << sh;  // bits [0, 64) of the shifted piece
+        const uint32_t hi = sh ? (uint32_t)(piece >> (64 - sh)) : 0u;  // bits [64, 96)
+        __hip_atomic_fetch_or(row + q, (uint32_t)lo, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+        if (sh + 2 * w > 32)
+          __hip_atomic_fetch_or(row + q + 1, (uint32_t)(lo >> 32), __ATOMIC_RELAXED,
+                                __HIP_MEMORY_SCOPE_WAVEFRONT);
+        if (sh + 2 * w > 64)
+          __hip_atomic_fetch_or(row + q + 2, hi, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+      }
+  }
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+}
+
+// The row's nwords packed words to dst (16-byte aligned), 128-bit stores.
+__device__ __forceinline__ void copy_words(const uint32_t *row, unsigned nwords, uint32_t *dst,
+                                           int lane) {
+  for (unsigned t = lane; 4 * t < nwords; t += 64)
+    __builtin_nontemporal_store(reinterpret_cast<const nt_u4 *>(row)[t],
+                                reinterpret_cast<nt_u4 *>(dst) + t);
+}
+
+// A record's 16-byte header and (hb) its outlier bitmap; flags: bit W j + e
+// marks the lane's position 64 W j + W lane + e as an outlier.
+template <int W, int NSUB>
+__device__ __forceinline__ void write_record_head(uint8_t *rec, unsigned w, unsigned mode,
+                                                  unsigned hb, unsigned flags, int lane) {
+  if (lane < 4) {
+    const uint32_t word = lane == 0 ? (w | (mode << 8) | (hb << 16)) : 0u;
+    reinterpret_cast<uint32_t *>(rec)[lane] = word;
+  }
+  if (hb) {
+    constexpr int LANES = 32 / W;  // lanes per bitmap word
+    constexpr unsigned kLaneMask = (1u << W) - 1;
+#pragma unroll
+    for (int j = 0; j < NSUB; j++) {
+      const unsigned fw = gather_flag_word<W>((flags >> (W * j)) & kLaneMask, lane);
+      if ((lane & (LANES - 1)) == 0)
+        reinterpret_cast<uint32_t *>(rec + 16)[2 * W * j + lane / LANES] = fw;
+    }
+  }
+}
+
+// Stage a record's nwords packed words (16-byte aligned at pw) in the
+// wavefront's LDS row with 128-bit loads, then order them before the
+// wavefront's reads.
+__device__ __forceinline__ void stage_words(const uint8_t *pw, unsigned nwords, uint32_t *row,
+                                            int lane) {
+  const nt_u4 *pw4 = reinterpret_cast<const nt_u4 *>(pw);
+  for (unsigned t = lane; 4 * t < nwords; t += 64) {
+    const nt_u4 v = __builtin_nontemporal_load(pw4 + t);
+    row[4 * t] = v.x;
+    row[4 * t + 1] = v.y;
+    row[4 * t + 2] = v.z;
+    row[4 * t + 3] = v.w;
+  }
+  // each wavefront reads only its own row: LDS operations of one wavefront
+  // complete in issue order, so a wavefront-scope fence orders them
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+}
+
+// Codes of a chunk from its staged record bits (row), width w, mode and
+// bitmap bm (null without one): sentinels where the bitmap says so, 0 at
+// positions len and beyond.
+template <int W, int NSUB>
+__device__ __forceinline__ void record_codes(const uint32_t *row, const uint8_t *bm, unsigned w,
+                                             unsigned mode, unsigned len, int lane,
+                                             int32_t (&out)[NSUB][W]) {
+  const uint32_t mask = w == 32 ? 0xFFFFFFFFu : ((1u << w) - 1u);
+  const unsigned lane_bp = (unsigned)(W * lane) * w;  // the lane's first bit in a sub-block
+  uint32_t carry = 0;
+#pragma unroll
+  for (int j = 0; j < NSUB; j++) {
+    const unsigned l0 = chunk_pos<W>(j, lane);  // position in the chunk
+    uint32_t v[W];
+#pragma unroll
+    for (int e = 0; e < W; e++) {
+      // value bits [bp, bp + w): one funnel shift of the word pair (q, q+1)
+      // (the upper word only matters when the value straddles into it, and
+      // then it lies inside the record; otherwise its bits are masked off)
+      const unsigned bp = lane_bp + (unsigned)(64 * W * j + e) * w;
+      const unsigned q = bp >> 5, sh = bp & 31u;
+      const uint32_t lo = row[q], hi = row[min(q + 1, (unsigned)kChunk - 1)];
+      const uint32_t z = (w && l0 + e < len) ? __builtin_amdgcn_alignbit(hi, lo, sh) & mask : 0u;
+      v[e] = unzigzag(z);
+    }
+    if (mode) {
+      // prefix sum over the chunk in position order (mod 2^32)
+#pragma unroll
+      for (int e = 1; e < W; e++) v[e] += v[e - 1];
+      uint32_t incl = v[W - 1];
+#pragma unroll
+      for (int o = 1; o < 64; o <<= 1) {
+        const uint32_t t = __shfl_up(incl, o, 64);
+        if (lane >= o) incl += t;
+      }
+      const uint32_t excl = incl - v[W - 1] + carry;
+#pragma unroll
+      for (int e = 0; e < W; e++) v[e] += excl;
+      carry += __shfl(incl, 63, 64);
+    }
+    const unsigned fl = bm ? (bm[l0 / 8] >> (l0 % 8)) & ((1u << W) - 1u) : 0u;
+#pragma unroll
+    for (int e = 0; e < W; e++)
+      out[j][e] = ((fl >> e) & 1u) ? kSent : (l0 + e < len ? (int32_t)v[e] : 0);
+  }
+}
+
+}  // namespace lcq

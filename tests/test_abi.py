@@ -117,6 +117,60 @@ def test_per_value_kernels_have_no_fused_or_packed_fp(device_asm):
     assert libm == 4, libm
 
 
+@pytest.fixture(scope="module")
+def compress_asm(tmp_path_factory):
+    from paper_2407_15037_amd import build
+    path = str(tmp_path_factory.mktemp("asm") / "lcq_compress.s")
+    build.asm(path, src=os.path.join(ROOT, "paper_2407_15037_amd", "csrc", "lcq_compress.hip"))
+    return open(path).read()
+
+
+def test_fused_kernels_have_no_fused_or_packed_fp(compress_asm):
+    """The fused compress / decompress encode and decode every value too:
+    the same rule holds for their kernels."""
+    bodies = kernel_bodies(compress_asm)
+    fused_path = {k: v for k, v in bodies.items()
+                  if any(p in k for p in ("k_cmp_stage", "k_cmp_write", "k_cmp_finish",
+                                          "k_decompress"))}
+    assert len(fused_path) == 3 * 2 * 3 + 2, sorted(bodies)
+    fused = re.compile(r"^\s*(v_(?:fma|fmac|mad|mac)\w*_f(?:16|32|64)\w*|v_mad_legacy\w*|"
+                       r"v_fma_legacy\w*|v_pk_fma_f32|v_pk_mul_f32|v_pk_add_f32)\b", flags=re.M)
+    for name, body in fused_path.items():
+        hits = fused.findall(body)
+        assert not hits, (name, hits[:5])
+    modes = re.findall(r"\.amdhsa_float_denorm_mode_32\s+(\d+)", compress_asm)
+    assert modes and all(m == "3" for m in modes), modes
+
+
+def test_fused_entry_points_refuse_bad_arguments():
+    import paper_2407_15037_amd as lcq
+    L = lcq.lib()
+    vp = ctypes.c_void_p
+    fake = vp(1 << 20)  # never dereferenced: every call below fails on the host
+    n = 1 << 20
+    assert L.lcq_compress_workspace_bytes(0, 0, n) > L.lcq_compress_workspace_bytes(0, 0, 1000) > 0
+    assert L.lcq_compress_workspace_bytes(2, 1, n) > L.lcq_compress_workspace_bytes(0, 1, n)
+    assert L.lcq_compress_workspace_bytes(3, 0, n) == 0
+    assert L.lcq_compress_workspace_bytes(0, 2, n) == 0
+    big = 1 << 40
+    for q, t, eb in [(7, 0, 1e-3), (0, 9, 1e-3), (0, 0, 0.0), (0, 0, float("nan")), (1, 0, 1.0)]:
+        st = L.lcq_compress(q, t, eb, fake, 16, fake, big, fake, fake, big, None)
+        assert st == lcq.ERR_ARG, (q, t, eb, st)
+    st = L.lcq_compress(0, 0, 1e-3, vp((1 << 20) + 4), 16, fake, big, fake, fake, big, None)
+    assert st == lcq.ERR_ARG
+    # packed capacity below pack_max_bytes, workspace below its size
+    cap = L.lcq_pack_max_bytes(0, 1000)
+    st = L.lcq_compress(0, 0, 1e-3, fake, 1000, fake, cap - 1, fake, fake, big, None)
+    assert st == lcq.ERR_CAPACITY
+    wsb = L.lcq_compress_workspace_bytes(0, 0, 1000)
+    st = L.lcq_compress(0, 0, 1e-3, fake, 1000, fake, cap, fake, fake, wsb - 1, None)
+    assert st == lcq.ERR_CAPACITY
+    # decompress: too short for the offset table, bad dtype, small workspace
+    assert L.lcq_decompress(0, fake, 64, fake, 1000, fake, 64, None) == lcq.ERR_STREAM
+    assert L.lcq_decompress(5, fake, 1 << 20, fake, 10, fake, 64, None) == lcq.ERR_ARG
+    assert L.lcq_decompress(0, fake, 1 << 20, fake, 10, fake, 4, None) == lcq.ERR_CAPACITY
+
+
 def test_float32_subnormals_kept(device_asm):
     modes = re.findall(r"\.amdhsa_float_denorm_mode_32\s+(\d+)", device_asm)
     assert modes and all(m == "3" for m in modes), modes

@@ -105,8 +105,9 @@ def test_pack_of_gpu_stream_and_errors():
 
 
 def test_compress_decompress_pipeline():
-    """quantize + pack and unpack + dequantize through the one-call helpers:
-    the decode equals the oracle's decode of its own stream."""
+    """The one-call forms (lcq_compress, lcq_decompress) on the same fields as
+    the two-call pipeline: packed bytes equal the oracle's pack of its own
+    stream, and the decode equals the oracle's decode."""
     import torch
     import paper_2407_15037_amd as lcq
     for dt in DTYPES:
@@ -115,18 +116,20 @@ def test_compress_decompress_pipeline():
         for q in ("abs", "noa", "rel"):
             y = x if q != "rel" else synth.rel_variant(np.nan_to_num(x.astype(np.float64)), 902, dtype=dt)
             announce("compress pipeline", np.dtype(dt).name, q)
-            pk = lcq.compress(torch.from_numpy(y).cuda(), q, 1e-4)
+            pk, nb = lcq.compress(torch.from_numpy(y).cuda(), q, 1e-4)
+            pk = pk[: int(nb.item())]
             assert first_diff(pk.cpu().numpy(), O.pack(O.quantize(q, y, 1e-4), dt, y.size)) is None
-            dec = lcq.decompress(pk, _tdt(dt), y.size).cpu().numpy()
+            ws = torch.zeros(64, dtype=torch.uint8, device="cuda")
+            dec = lcq.decompress(pk, _tdt(dt), y.size, ws=ws)
+            assert lcq.stream_status(ws) == 0
             ref = O.dequantize(O.quantize(q, y, 1e-4), dt, y.size)
-            assert np.array_equal(dec.view(np.uint8), ref.view(np.uint8))
+            assert np.array_equal(dec.cpu().numpy().view(np.uint8), ref.view(np.uint8))
 
 
 @pytest.mark.parametrize("q", ["abs", "rel"])
 def test_pack_many_groups_equals_oracle(q):
     """2^21 + 333 codes: 513 workgroups of 4 chunks in 65 groups of the
-    record-offset scan, a ragged last chunk, records written by workgroups in
-    reverse order; packed bytes and the unpacked stream must equal the
+    record-offset scan, a ragged last chunk; packed bytes and the unpacked stream must equal the
     oracle's."""
     n = (1 << 21) + 333
     x = synth.sines_1d(n, 710, dtype=np.float32)
