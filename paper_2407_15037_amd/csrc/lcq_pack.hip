@@ -57,6 +57,9 @@ struct ChunkCodes {
   unsigned flags;  // bit 4 j + e: outlier sentinel
 };
 
+// CACHED: ordinary loads (the plan pass: measured faster there than
+// streaming loads); otherwise streaming loads.
+template <bool CACHED = false>
 __device__ __forceinline__ void load_chunk(const int32_t *codes, uint64_t n, uint64_t c, int lane,
                                            ChunkCodes &cc) {
   cc.flags = 0;
@@ -66,7 +69,12 @@ __device__ __forceinline__ void load_chunk(const int32_t *codes, uint64_t n, uin
     const uint64_t i0 = chunk_value<kCW>(c, j, lane);
     const unsigned p = chunk_pos<kCW>(j, lane);
     int32_t v[kCW];
-    load_codes<kCW>(codes, i0, n, v);
+    if (CACHED && p + kCW <= len) {
+      const nt_i4 q = *reinterpret_cast<const nt_i4 *>(codes + i0);
+      v[0] = q.x; v[1] = q.y; v[2] = q.z; v[3] = q.w;
+    } else {
+      load_codes<kCW>(codes, i0, n, v);
+    }
 #pragma unroll
     for (int e = 0; e < kCW; e++) {
       const bool sent = v[e] == kSent && p + e < len;
@@ -117,7 +125,7 @@ __global__ __launch_bounds__(kBlock) void k_pack_plan(PackArgs a) {
   unsigned size = 0;
   if (c < nch) {
     ChunkCodes cc;
-    load_chunk(reinterpret_cast<const int32_t *>(a.in + 64), n, c, lane, cc);
+    load_chunk<true>(reinterpret_cast<const int32_t *>(a.in + 64), n, c, lane, cc);
     unsigned w, mode, hb;
     chunk_plan(cc, n, c, lane, w, mode, hb);
     const uint64_t len = min<uint64_t>(kChunk, n - c * kChunk);
@@ -305,19 +313,20 @@ __global__ __launch_bounds__(kBlock) void k_unpack(UnpackArgs a) {
   if (ok) {
     const unsigned ulen = (unsigned)len;
     stage_words(rec + 16 + (hb ? 128 : 0), packed_words(ulen, w), s_w[wave], lane);
-    int32_t out[kCSub][kCW];
-    record_codes<kCW, kCSub>(s_w[wave], hb ? rec + 16 : nullptr, w, mode, ulen, lane, out);
     int32_t *codes = reinterpret_cast<int32_t *>(a.out + 64);
+    uint32_t carry = 0;
 #pragma unroll
-    for (int j = 0; j < kCSub; j++) {
+    for (int j = 0; j < kCSub; j++) {  // each sub-block stored as soon as it is decoded
+      int32_t out[kCW];
+      record_codes_sub<kCW>(s_w[wave], hb ? rec + 16 : nullptr, w, mode, ulen, lane, j, carry, out);
       const uint64_t i0 = chunk_value<kCW>(c, j, lane);
       const unsigned l0 = chunk_pos<kCW>(j, lane);  // position in the chunk
       if (l0 + kCW <= ulen) {
-        store_codes<kCW, true>(codes, i0, n, out[j]);
+        store_codes<kCW, true>(codes, i0, n, out);
       } else {
 #pragma unroll
         for (int e = 0; e < kCW; e++)
-          if (l0 + e < ulen) codes[i0 + e] = out[j][e];
+          if (l0 + e < ulen) codes[i0 + e] = out[e];
       }
     }
     if (lane == 0) {

@@ -227,51 +227,59 @@ __device__ __forceinline__ void stage_words(const uint8_t *pw, unsigned nwords, 
   __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
 }
 
-// Codes of a chunk from its staged record bits (row), width w, mode and
-// bitmap bm (null without one): sentinels where the bitmap says so, 0 at
-// positions len and beyond.
+// Codes of sub-block j of a chunk from its staged record bits (row), width
+// w, mode and bitmap bm (null without one): sentinels where the bitmap says
+// so, 0 at positions len and beyond.  carry: the running delta-mode sum,
+// updated for the next sub-block.
+template <int W>
+__device__ __forceinline__ void record_codes_sub(const uint32_t *row, const uint8_t *bm,
+                                                 unsigned w, unsigned mode, unsigned len,
+                                                 int lane, int j, uint32_t &carry,
+                                                 int32_t (&out)[W]) {
+  const uint32_t mask = w == 32 ? 0xFFFFFFFFu : ((1u << w) - 1u);
+  const unsigned lane_bp = (unsigned)(W * lane) * w;  // the lane's first bit in a sub-block
+  const unsigned l0 = chunk_pos<W>(j, lane);         // position in the chunk
+  uint32_t v[W];
+#pragma unroll
+  for (int e = 0; e < W; e++) {
+    // value bits [bp, bp + w): one funnel shift of the word pair (q, q+1)
+    // (the upper word only matters when the value straddles into it, and
+    // then it lies inside the record; otherwise its bits are masked off)
+    const unsigned bp = lane_bp + (unsigned)(64 * W * j + e) * w;
+    const unsigned q = bp >> 5, sh = bp & 31u;
+    const uint32_t lo = row[q], hi = row[min(q + 1, (unsigned)kChunk - 1)];
+    const uint32_t z = (w && l0 + e < len) ? __builtin_amdgcn_alignbit(hi, lo, sh) & mask : 0u;
+    v[e] = unzigzag(z);
+  }
+  if (mode) {
+    // prefix sum over the chunk in position order (mod 2^32)
+#pragma unroll
+    for (int e = 1; e < W; e++) v[e] += v[e - 1];
+    uint32_t incl = v[W - 1];
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      const uint32_t t = __shfl_up(incl, o, 64);
+      if (lane >= o) incl += t;
+    }
+    const uint32_t excl = incl - v[W - 1] + carry;
+#pragma unroll
+    for (int e = 0; e < W; e++) v[e] += excl;
+    carry += __shfl(incl, 63, 64);
+  }
+  const unsigned fl = bm ? (bm[l0 / 8] >> (l0 % 8)) & ((1u << W) - 1u) : 0u;
+#pragma unroll
+  for (int e = 0; e < W; e++) out[e] = ((fl >> e) & 1u) ? kSent : (int32_t)v[e];
+}
+
+// The codes of every sub-block (record_codes_sub); positions len and
+// beyond are left as extracted (their stores are skipped by the callers).
 template <int W, int NSUB>
 __device__ __forceinline__ void record_codes(const uint32_t *row, const uint8_t *bm, unsigned w,
                                              unsigned mode, unsigned len, int lane,
                                              int32_t (&out)[NSUB][W]) {
-  const uint32_t mask = w == 32 ? 0xFFFFFFFFu : ((1u << w) - 1u);
-  const unsigned lane_bp = (unsigned)(W * lane) * w;  // the lane's first bit in a sub-block
   uint32_t carry = 0;
 #pragma unroll
-  for (int j = 0; j < NSUB; j++) {
-    const unsigned l0 = chunk_pos<W>(j, lane);  // position in the chunk
-    uint32_t v[W];
-#pragma unroll
-    for (int e = 0; e < W; e++) {
-      // value bits [bp, bp + w): one funnel shift of the word pair (q, q+1)
-      // (the upper word only matters when the value straddles into it, and
-      // then it lies inside the record; otherwise its bits are masked off)
-      const unsigned bp = lane_bp + (unsigned)(64 * W * j + e) * w;
-      const unsigned q = bp >> 5, sh = bp & 31u;
-      const uint32_t lo = row[q], hi = row[min(q + 1, (unsigned)kChunk - 1)];
-      const uint32_t z = (w && l0 + e < len) ? __builtin_amdgcn_alignbit(hi, lo, sh) & mask : 0u;
-      v[e] = unzigzag(z);
-    }
-    if (mode) {
-      // prefix sum over the chunk in position order (mod 2^32)
-#pragma unroll
-      for (int e = 1; e < W; e++) v[e] += v[e - 1];
-      uint32_t incl = v[W - 1];
-#pragma unroll
-      for (int o = 1; o < 64; o <<= 1) {
-        const uint32_t t = __shfl_up(incl, o, 64);
-        if (lane >= o) incl += t;
-      }
-      const uint32_t excl = incl - v[W - 1] + carry;
-#pragma unroll
-      for (int e = 0; e < W; e++) v[e] += excl;
-      carry += __shfl(incl, 63, 64);
-    }
-    const unsigned fl = bm ? (bm[l0 / 8] >> (l0 % 8)) & ((1u << W) - 1u) : 0u;
-#pragma unroll
-    for (int e = 0; e < W; e++)
-      out[j][e] = ((fl >> e) & 1u) ? kSent : (l0 + e < len ? (int32_t)v[e] : 0);
-  }
+  for (int j = 0; j < NSUB; j++) record_codes_sub<W>(row, bm, w, mode, len, lane, j, carry, out[j]);
 }
 
 }  // namespace lcq

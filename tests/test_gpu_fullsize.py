@@ -198,3 +198,24 @@ def test_fullsize_packing_stage(fields, q):
     back, bnb = lcq.unpack(pk, torch.float32, x.size, packed_bytes=psize)
     assert int(bnb.item()) == st_o.size
     assert torch.equal(back[: st_o.size], buf)
+
+
+@pytest.mark.parametrize("q", ["abs", "noa", "rel"])
+def test_fullsize_compress_decompress(fields, q):
+    """The fused forms on the full-size fields: compress equals the oracle's
+    pack of the oracle's stream, decompress of it equals the oracle's
+    decode."""
+    import torch
+    import paper_2407_15037_amd as lcq
+    x = fields[q]
+    announce("fullsize compress / decompress", q, x.size)
+    st_o = O.quantize_mt(q, x, EB)
+    pk_o = O.pack(st_o, np.float32, x.size)
+    pk, pnb = lcq.compress(torch.from_numpy(x).cuda(), q, EB)
+    psize = int(pnb.item())
+    assert first_diff(pk[:psize].cpu().numpy(), pk_o) is None
+    ws = torch.zeros(64, dtype=torch.uint8, device="cuda")
+    dec = lcq.decompress(pk, torch.float32, x.size, packed_bytes=psize, ws=ws)
+    assert lcq.stream_status(ws) == 0
+    ref = O.dequantize_mt(st_o, np.float32, x.size)
+    assert first_diff(bits(dec.cpu().numpy()), bits(ref)) is None
