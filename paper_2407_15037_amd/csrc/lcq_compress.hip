@@ -170,6 +170,11 @@ __device__ __forceinline__ void stage_chunk(const CmpArgs &a, const FieldParams<
   }
 }
 
+// Pass 1 for the kCmpCpw * kWaves chunks of workgroup blockIdx.x: chunk
+// (tile kCmpCpw + r) kWaves + wave in round r, every round's input loaded
+// before the first is encoded.
+constexpr int kCmpCpw = 1;
+
 template <typename T, int Q>
 __global__ __launch_bounds__(kBlock) void k_cmp_stage(CmpArgs a) {
   using U = typename FT<T>::U;
@@ -182,14 +187,24 @@ __global__ __launch_bounds__(kBlock) void k_cmp_stage(CmpArgs a) {
   const uint64_t n = a.n, nch = n_chunks(n);
   const FieldParams<T> p = cmp_params<T, Q>(a);
   const EncK<T> k = enc_consts_pinned<T, Q>(p);
-  const uint64_t c = (uint64_t)blockIdx.x * kWaves + wave;
   unsigned cnt = 0, rb = 0;
-  if (c < nch) {  // uniform over the wavefront
-    T x[NSUB][W];
-    load_chunk<T>(static_cast<const T *>(a.in), n, c, lane, x);
-    const unsigned len = chunk_len(n, c);
-    if (len == kChunk) stage_chunk<T, Q, true>(a, p, k, c, len, lane, x, s_stage[wave], cnt, rb);
-    else stage_chunk<T, Q, false>(a, p, k, c, len, lane, x, s_stage[wave], cnt, rb);
+  T x[kCmpCpw][NSUB][W];
+#pragma unroll
+  for (int r = 0; r < kCmpCpw; r++) {
+    const uint64_t c = ((uint64_t)blockIdx.x * kCmpCpw + r) * kWaves + wave;
+    if (c < nch) load_chunk<T>(static_cast<const T *>(a.in), n, c, lane, x[r]);
+  }
+#pragma unroll
+  for (int r = 0; r < kCmpCpw; r++) {
+    const uint64_t c = ((uint64_t)blockIdx.x * kCmpCpw + r) * kWaves + wave;
+    if (c < nch) {  // uniform over the wavefront
+      const unsigned len = chunk_len(n, c);
+      unsigned cc, rr;
+      if (len == kChunk) stage_chunk<T, Q, true>(a, p, k, c, len, lane, x[r], s_stage[wave], cc, rr);
+      else stage_chunk<T, Q, false>(a, p, k, c, len, lane, x[r], s_stage[wave], cc, rr);
+      cnt += cc;
+      rb += rr;
+    }
   }
   if (lane == 0) {
     s_cnt[wave] = cnt;
@@ -503,14 +518,11 @@ struct DcmpArgs {
   int dtype;
 };
 
-// Largest record: header, bitmap and 1024 values of 32 bits.
-constexpr unsigned kMaxRecord = 16 + 128 + 4 * (unsigned)kChunk;
-
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_decompress(DcmpArgs a) {
   using U = typename FT<T>::U;
   constexpr int W = ChunkShape<T>::W, NSUB = ChunkShape<T>::NSUB;
-  __shared__ uint32_t s_rec[kWaves][kMaxRecord / 4];  // each wavefront's whole record
+  __shared__ uint32_t s_rec[kWaves][kMaxRecord / 4 + kRowPad];  // each wavefront's whole record
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const uint64_t n = a.n, nch = n_chunks(n);
@@ -537,8 +549,7 @@ __global__ __launch_bounds__(kBlock) void k_decompress(DcmpArgs a) {
   const uint64_t *chunk_tab = reinterpret_cast<const uint64_t *>(a.in + 64);
   const uint64_t ct_cur = chunk_tab[c], ct_nxt = c + 1 < nch ? chunk_tab[c + 1] : k;
   const unsigned len = chunk_len(n, c);
-  bool ok = (off & 15) == 0 && off <= nxt && nxt <= payload && nxt - off >= 16 &&
-            nxt - off <= kMaxRecord && ((nxt - off) & 15) == 0;
+  bool ok = record_extent_ok(off, nxt, payload);
   if (!ok) {
     if (lane == 0) report_status(a.status, tag, LCQ_ERR_STREAM);
     return;
@@ -556,7 +567,7 @@ __global__ __launch_bounds__(kBlock) void k_decompress(DcmpArgs a) {
   }
   int32_t cc[NSUB][W];
   record_codes<W, NSUB>(row + (hb ? 36 : 4), hb ? reinterpret_cast<const uint8_t *>(row + 4) : nullptr,
-                        w, mode, len, lane, cc);
+                        w, mode, lane, cc);
   DField<T> f;
   f.stream = a.in;
   f.n = n;
@@ -567,8 +578,7 @@ __global__ __launch_bounds__(kBlock) void k_decompress(DcmpArgs a) {
   f.status = a.status;
   f.tag = tag;
   const U *outl = reinterpret_cast<const U *>(a.in + align16(pl + payload));
-  if (f.rel) decode_chunk_at<T, false, true>(f, ct_cur, ct_nxt, outl, c, lane, __lanemask_lt(), cc);
-  else decode_chunk_at<T, false, false>(f, ct_cur, ct_nxt, outl, c, lane, __lanemask_lt(), cc);
+  decode_chunk_any<T, false>(f, ct_cur, ct_nxt, outl, c, lane, __lanemask_lt(), cc);
 }
 
 __global__ void k_clear_cmp(uint64_t *p, uint64_t count) {
@@ -616,7 +626,8 @@ lcq_status run_compress(double eb, const void *d_in, uint64_t n, void *d_out, ui
   const HostParams hp = host_params<T>(Q, eb);
   uint8_t *ws = static_cast<uint8_t *>(d_ws);
   const uint64_t C = n_chunks(n);
-  const uint64_t ntiles = (C + kWaves - 1) / kWaves;
+  const uint64_t ntiles = (C + kWaves - 1) / kWaves;  // pass 3: one chunk per wavefront
+  const uint64_t stiles = (C + kWaves * kCmpCpw - 1) / (kWaves * kCmpCpw);  // pass 1
   CmpArgs a{};
   a.in = d_in;
   a.n = n;
@@ -629,9 +640,9 @@ lcq_status run_compress(double eb, const void *d_in, uint64_t n, void *d_out, ui
   a.stage = ws + cw_stage_off(C);
   a.group = reinterpret_cast<unsigned long long *>(ws + kCwGroups);
   a.rgroup = a.group + kMaxGroups;
-  a.tiles_per_group = tiles_per_group(ntiles, kWaves);
-  a.chunks_per_group = a.tiles_per_group * kWaves;
-  a.ngroups = std::max<uint64_t>(1, (ntiles + a.tiles_per_group - 1) / a.tiles_per_group);
+  a.tiles_per_group = tiles_per_group(stiles, kWaves * kCmpCpw);
+  a.chunks_per_group = a.tiles_per_group * kWaves * kCmpCpw;
+  a.ngroups = std::max<uint64_t>(1, (stiles + a.tiles_per_group - 1) / a.tiles_per_group);
   a.noa = reinterpret_cast<const DevParams *>(ws + kCwParams);
   a.step = hp.step;
   a.inv = hp.inv;
@@ -657,7 +668,7 @@ lcq_status run_compress(double eb, const void *d_in, uint64_t n, void *d_out, ui
                        clear_ptr, clear_count);
   }
   if (ntiles)
-    hipLaunchKernelGGL((k_cmp_stage<T, Q>), dim3((unsigned)ntiles), dim3(kBlock), 0, s, a);
+    hipLaunchKernelGGL((k_cmp_stage<T, Q>), dim3((unsigned)stiles), dim3(kBlock), 0, s, a);
   hipLaunchKernelGGL((k_cmp_finish<T, Q>), dim3((unsigned)a.ngroups), dim3(kBlock), 0, s, a);
   if (ntiles)
     hipLaunchKernelGGL((k_cmp_write<T, Q>), dim3((unsigned)ntiles), dim3(kBlock), 0, s, a);

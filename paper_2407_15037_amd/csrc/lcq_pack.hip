@@ -58,8 +58,9 @@ struct ChunkCodes {
 };
 
 // CACHED: ordinary loads (the plan pass: measured faster there than
-// streaming loads); otherwise streaming loads.
-template <bool CACHED = false>
+// streaming loads); otherwise streaming loads.  FULL: the chunk has 1024
+// codes (no position to mask).
+template <bool CACHED, bool FULL>
 __device__ __forceinline__ void load_chunk(const int32_t *codes, uint64_t n, uint64_t c, int lane,
                                            ChunkCodes &cc) {
   cc.flags = 0;
@@ -69,35 +70,55 @@ __device__ __forceinline__ void load_chunk(const int32_t *codes, uint64_t n, uin
     const uint64_t i0 = chunk_value<kCW>(c, j, lane);
     const unsigned p = chunk_pos<kCW>(j, lane);
     int32_t v[kCW];
-    if (CACHED && p + kCW <= len) {
+    if (CACHED && (FULL || p + kCW <= len)) {
       const nt_i4 q = *reinterpret_cast<const nt_i4 *>(codes + i0);
+      v[0] = q.x; v[1] = q.y; v[2] = q.z; v[3] = q.w;
+    } else if (FULL) {
+      const nt_i4 q = __builtin_nontemporal_load(reinterpret_cast<const nt_i4 *>(codes + i0));
       v[0] = q.x; v[1] = q.y; v[2] = q.z; v[3] = q.w;
     } else {
       load_codes<kCW>(codes, i0, n, v);
     }
 #pragma unroll
     for (int e = 0; e < kCW; e++) {
-      const bool sent = v[e] == kSent && p + e < len;
+      const bool sent = v[e] == kSent && (FULL || p + e < len);
       cc.cv[j][e] = sent ? 0u : (uint32_t)v[e];
       if (sent) cc.flags |= 1u << (kCW * j + e);
     }
   }
 }
 
-// z values of a chunk in plain (DELTA false) or delta mode; 0 past n.
-template <bool DELTA>
-__device__ __forceinline__ void chunk_z(const ChunkCodes &cc, uint64_t n, uint64_t c, int lane,
-                                        uint32_t (&z)[kCSub][kCW]) {
-  lcq::chunk_z<DELTA, kCW, kCSub>(cc.cv, chunk_len(n, c), lane, z);
+// Width, mode, bitmap flag and record size of chunk c (same on every lane).
+template <bool FULL>
+__device__ __forceinline__ unsigned plan_chunk(const int32_t *codes, uint64_t n, uint64_t c,
+                                               int lane, unsigned &meta) {
+  ChunkCodes cc;
+  load_chunk<true, FULL>(codes, n, c, lane, cc);
+  const unsigned len = chunk_len(n, c);
+  unsigned w, mode;
+  chunk_width<FULL, kCW, kCSub>(cc.cv, len, lane, w, mode);
+  const unsigned hb = __ballot(cc.flags != 0) ? 1u : 0u;
+  meta = w | (mode << 8) | (hb << 16);
+  return (unsigned)record_bytes(len, w, hb);
 }
 
-// Width, mode and bitmap flag of one chunk (same on every lane).
-__device__ __forceinline__ void chunk_plan(const ChunkCodes &cc, uint64_t n, uint64_t c, int lane,
-                                           unsigned &w, unsigned &mode, unsigned &hb) {
+// Record of chunk c (width, mode and bitmap flag in meta) at rec, its packed
+// bits assembled in the wavefront's LDS row.
+template <bool FULL>
+__device__ __forceinline__ void write_chunk_record(const int32_t *codes, uint64_t n, uint64_t c,
+                                                   int lane, uint32_t meta, uint32_t *row,
+                                                   uint8_t *rec) {
+  const unsigned w = meta & 0xFF, mode = (meta >> 8) & 1, hb = (meta >> 16) & 1;
   const unsigned len = chunk_len(n, c);
-  if (len == kChunk) chunk_width<true, kCW, kCSub>(cc.cv, len, lane, w, mode);
-  else chunk_width<false, kCW, kCSub>(cc.cv, len, lane, w, mode);
-  hb = __ballot(cc.flags != 0) ? 1u : 0u;
+  ChunkCodes cc;
+  load_chunk<false, FULL>(codes, n, c, lane, cc);
+  uint32_t z[kCSub][kCW];
+  if (mode) lcq::chunk_z<true, kCW, kCSub, FULL>(cc.cv, len, lane, z);
+  else lcq::chunk_z<false, kCW, kCSub, FULL>(cc.cv, len, lane, z);
+  pack_bits<kCW, kCSub>(z, len, w, row, lane);
+  write_record_head<kCW, kCSub>(rec, w, mode, hb, cc.flags, lane);
+  copy_words(row, packed_words(len, w), reinterpret_cast<uint32_t *>(rec + 16 + (hb ? 128 : 0)),
+             lane);
 }
 
 struct PackArgs {
@@ -124,15 +145,13 @@ __global__ __launch_bounds__(kBlock) void k_pack_plan(PackArgs a) {
   const uint64_t c = (uint64_t)blockIdx.x * kWaves + wave;
   unsigned size = 0;
   if (c < nch) {
-    ChunkCodes cc;
-    load_chunk<true>(reinterpret_cast<const int32_t *>(a.in + 64), n, c, lane, cc);
-    unsigned w, mode, hb;
-    chunk_plan(cc, n, c, lane, w, mode, hb);
-    const uint64_t len = min<uint64_t>(kChunk, n - c * kChunk);
-    size = (unsigned)record_bytes(len, w, hb);
+    const int32_t *codes = reinterpret_cast<const int32_t *>(a.in + 64);
+    unsigned meta;
+    if (chunk_len(n, c) == kChunk) size = plan_chunk<true>(codes, n, c, lane, meta);
+    else size = plan_chunk<false>(codes, n, c, lane, meta);
     if (lane == 0) {
       a.sizes[c] = size;
-      a.meta[c] = w | (mode << 8) | (hb << 16);
+      a.meta[c] = meta;
     }
   }
   if (lane == 0) s_tot[wave] = size;
@@ -217,32 +236,17 @@ __global__ __launch_bounds__(kBlock) void k_pack_write(PackArgs a) {
   if (!lcq1_header_ok(a.in, a.in_bytes, a.dtype, n, k)) return;  // uniform over the grid
   const uint64_t ot = packed_table_offset(nch), pl = packed_payload_offset(nch);
   const uint64_t c = (uint64_t)blockIdx.x * kWaves + wave;
-  const bool active = c < nch;  // uniform over the wavefront
-  unsigned w = 0, hb = 0;
-  uint64_t len = 0;
-  uint8_t *rec = nullptr;
-  if (active) {
+  if (c < nch) {  // uniform over the wavefront
+    const int32_t *codes = reinterpret_cast<const int32_t *>(a.in + 64);
     const uint32_t m = a.meta[c];
-    w = m & 0xFF;
-    const unsigned mode = (m >> 8) & 1;
-    hb = (m >> 16) & 1;
-    len = min<uint64_t>(kChunk, n - c * kChunk);
-    rec = a.out + pl + reinterpret_cast<const uint64_t *>(a.out + ot)[c];
-    ChunkCodes cc;
-    load_chunk(reinterpret_cast<const int32_t *>(a.in + 64), n, c, lane, cc);
-    uint32_t z[kCSub][kCW];
-    if (mode) chunk_z<true>(cc, n, c, lane, z);
-    else chunk_z<false>(cc, n, c, lane, z);
-    pack_bits<kCW, kCSub>(z, (unsigned)len, w, s_w[wave], lane);
-    write_record_head<kCW, kCSub>(rec, w, mode, hb, cc.flags, lane);
+    uint8_t *rec = a.out + pl + reinterpret_cast<const uint64_t *>(a.out + ot)[c];
+    if (chunk_len(n, c) == kChunk) write_chunk_record<true>(codes, n, c, lane, m, s_w[wave], rec);
+    else write_chunk_record<false>(codes, n, c, lane, m, s_w[wave], rec);
     if (lane == 0) {
       const uint64_t *ct_in = reinterpret_cast<const uint64_t *>(a.in + chunk_table_offset(n));
       reinterpret_cast<uint64_t *>(a.out + 64)[c] = ct_in[c];
     }
   }
-  if (active)
-    copy_words(s_w[wave], packed_words((unsigned)len, w),
-               reinterpret_cast<uint32_t *>(rec + 16 + (hb ? 128 : 0)), lane);
   // outliers, grid-stride over the raw words
   const uint64_t s = a.dtype == LCQ_F64 ? 8 : 4;
   const uint64_t payload = reinterpret_cast<const uint64_t *>(a.out + ot)[nch];
@@ -286,39 +290,39 @@ __global__ __launch_bounds__(kBlock) void k_unpack(UnpackArgs a) {
   if (blockIdx.x == 0 && threadIdx.x == 0)
     report_status(a.status, tag, bad ? LCQ_ERR_STREAM : LCQ_OK);
   if (bad) return;
-  __shared__ uint32_t s_w[kWaves][kChunk];  // the record's packed words
+  __shared__ uint32_t s_rec[kWaves][kMaxRecord / 4 + kRowPad];  // each wavefront's whole record
   const uint64_t c = (uint64_t)blockIdx.x * kWaves + wave;
   const bool act = c < nch;  // uniform over the wavefront
   bool ok = false;
   unsigned w = 0, mode = 0, hb = 0;
-  uint64_t len = 0;
-  const uint8_t *rec = a.in + pl;
+  unsigned len = 0;
+  uint32_t *row = s_rec[wave];
   if (act) {
+    // the record's extent from the offset table, then the whole record
+    // (header, bitmap, bits) staged in LDS in one round trip
     const uint64_t off = offs[c], nxt = offs[c + 1];
-    len = min<uint64_t>(kChunk, n - c * kChunk);
-    ok = off <= payload && payload - off >= 16;
+    len = chunk_len(n, c);
+    ok = record_extent_ok(off, nxt, payload);
     if (ok) {
-      rec = a.in + pl + off;
-      const uint32_t h = reinterpret_cast<const uint32_t *>(rec)[0];
+      stage_words(a.in + pl + off, (unsigned)((nxt - off) / 4), row, lane);
+      const uint32_t h = row[0];
       w = h & 0xFF;
       mode = (h >> 8) & 0xFF;
       hb = (h >> 16) & 0xFF;
-      ok = w <= 32 && mode <= 1 && hb <= 1 && payload - off >= record_bytes(len, w, hb) &&
-           nxt == off + record_bytes(len, w, hb);
+      ok = w <= 32 && mode <= 1 && hb <= 1 && nxt - off == record_bytes(len, w, hb);
     }
     if (!ok && lane == 0) report_status(a.status, tag, LCQ_ERR_STREAM);
   }
-  // the record's packed words (a whole number of 16-byte units inside the
-  // record) staged in LDS, then its codes
   if (ok) {
-    const unsigned ulen = (unsigned)len;
-    stage_words(rec + 16 + (hb ? 128 : 0), packed_words(ulen, w), s_w[wave], lane);
+    const unsigned ulen = len;
+    const uint32_t *bits = row + (hb ? 36 : 4);
+    const uint8_t *bm = hb ? reinterpret_cast<const uint8_t *>(row + 4) : nullptr;
     int32_t *codes = reinterpret_cast<int32_t *>(a.out + 64);
     uint32_t carry = 0;
 #pragma unroll
     for (int j = 0; j < kCSub; j++) {  // each sub-block stored as soon as it is decoded
       int32_t out[kCW];
-      record_codes_sub<kCW>(s_w[wave], hb ? rec + 16 : nullptr, w, mode, ulen, lane, j, carry, out);
+      record_codes_sub<kCW>(bits, bm, w, mode, lane, j, carry, out);
       const uint64_t i0 = chunk_value<kCW>(c, j, lane);
       const unsigned l0 = chunk_pos<kCW>(j, lane);  // position in the chunk
       if (l0 + kCW <= ulen) {

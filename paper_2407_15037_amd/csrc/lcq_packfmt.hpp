@@ -29,6 +29,9 @@
 namespace lcq {
 
 constexpr uint32_t kMagicPacked = 0x5051434Cu;  // "LCQP"
+constexpr unsigned kRowPad = 4;  // words past a record's bits in an LDS row (keeps 16-byte rows)
+// Largest record: header, bitmap and 1024 values of 32 bits.
+constexpr unsigned kMaxRecord = 16 + 128 + 4 * (unsigned)kChunk;
 
 __host__ __device__ inline uint64_t packed_table_offset(uint64_t C) { return align16(64 + 8 * C); }
 __host__ __device__ inline uint64_t packed_payload_offset(uint64_t C) {
@@ -209,6 +212,13 @@ __device__ __forceinline__ void write_record_head(uint8_t *rec, unsigned w, unsi
   }
 }
 
+// Whether [off, nxt) of a payload of `payload` bytes can be a record: whole
+// 16-byte units inside the payload, at least a header, at most kMaxRecord.
+__device__ __forceinline__ bool record_extent_ok(uint64_t off, uint64_t nxt, uint64_t payload) {
+  return (off & 15) == 0 && off <= nxt && nxt <= payload && nxt - off >= 16 &&
+         nxt - off <= kMaxRecord && ((nxt - off) & 15) == 0;
+}
+
 // Stage a record's nwords packed words (16-byte aligned at pw) in the
 // wavefront's LDS row with 128-bit loads, then order them before the
 // wavefront's reads.
@@ -229,13 +239,16 @@ __device__ __forceinline__ void stage_words(const uint8_t *pw, unsigned nwords, 
 
 // Codes of sub-block j of a chunk from its staged record bits (row), width
 // w, mode and bitmap bm (null without one): sentinels where the bitmap says
-// so, 0 at positions len and beyond.  carry: the running delta-mode sum,
-// updated for the next sub-block.
+// so.  Positions past the chunk's end get whatever the row holds past the record's
+// bits (their codes are never stored or counted by the callers, and in
+// delta mode they only feed later positions of the same kind).  carry: the
+// running delta-mode sum, updated for the next sub-block.  The row must have one readable word past
+// the chunk's 1024 (kRowPad): the word after a value's first is always
+// read, and only used when the value straddles into it.
 template <int W>
 __device__ __forceinline__ void record_codes_sub(const uint32_t *row, const uint8_t *bm,
-                                                 unsigned w, unsigned mode, unsigned len,
-                                                 int lane, int j, uint32_t &carry,
-                                                 int32_t (&out)[W]) {
+                                                 unsigned w, unsigned mode, int lane, int j,
+                                                 uint32_t &carry, int32_t (&out)[W]) {
   const uint32_t mask = w == 32 ? 0xFFFFFFFFu : ((1u << w) - 1u);
   const unsigned lane_bp = (unsigned)(W * lane) * w;  // the lane's first bit in a sub-block
   const unsigned l0 = chunk_pos<W>(j, lane);         // position in the chunk
@@ -247,8 +260,8 @@ __device__ __forceinline__ void record_codes_sub(const uint32_t *row, const uint
     // then it lies inside the record; otherwise its bits are masked off)
     const unsigned bp = lane_bp + (unsigned)(64 * W * j + e) * w;
     const unsigned q = bp >> 5, sh = bp & 31u;
-    const uint32_t lo = row[q], hi = row[min(q + 1, (unsigned)kChunk - 1)];
-    const uint32_t z = (w && l0 + e < len) ? __builtin_amdgcn_alignbit(hi, lo, sh) & mask : 0u;
+    const uint32_t lo = row[q], hi = row[q + 1];  // (one paired LDS read)
+    const uint32_t z = __builtin_amdgcn_alignbit(hi, lo, sh) & mask;  // (mask 0 when w is 0)
     v[e] = unzigzag(z);
   }
   if (mode) {
@@ -271,15 +284,13 @@ __device__ __forceinline__ void record_codes_sub(const uint32_t *row, const uint
   for (int e = 0; e < W; e++) out[e] = ((fl >> e) & 1u) ? kSent : (int32_t)v[e];
 }
 
-// The codes of every sub-block (record_codes_sub); positions len and
-// beyond are left as extracted (their stores are skipped by the callers).
+// The codes of every sub-block (record_codes_sub).
 template <int W, int NSUB>
 __device__ __forceinline__ void record_codes(const uint32_t *row, const uint8_t *bm, unsigned w,
-                                             unsigned mode, unsigned len, int lane,
-                                             int32_t (&out)[NSUB][W]) {
+                                             unsigned mode, int lane, int32_t (&out)[NSUB][W]) {
   uint32_t carry = 0;
 #pragma unroll
-  for (int j = 0; j < NSUB; j++) record_codes_sub<W>(row, bm, w, mode, len, lane, j, carry, out[j]);
+  for (int j = 0; j < NSUB; j++) record_codes_sub<W>(row, bm, w, mode, lane, j, carry, out[j]);
 }
 
 }  // namespace lcq
