@@ -62,3 +62,59 @@ def test_more_than_2_31_values():
             assert int(table[c + 1].item()) - base == ko
         od = O.dequantize(st, np.float32, xs.size)
         assert np.array_equal(dec[b:e].cpu().numpy().view(np.uint32), od.view(np.uint32)), f"decode of chunk {c}"
+
+
+def test_compress_more_than_2_31_values():
+    """The fused forms at the same size: header and outlier count as the
+    two-call stream's, every sampled chunk's record byte-equal to the
+    oracle's record for that chunk alone (a record depends only on its
+    chunk's codes), its chunk-table entry equal to the LCQ1 stream's, and
+    decompress equal to the oracle's decode of the chunk."""
+    import torch
+    import paper_2407_15037_amd as lcq
+    n = (1 << 31) + 4099
+    eb = 1e-3
+    announce("large field, compress / decompress", n)
+    i = torch.arange(n, dtype=torch.int64, device="cuda")
+    x = torch.sin(i.to(torch.float32) * 1e-6) * 50.0
+    x[(i % 1000003) == 7] = float("nan")
+    x[(i % 999983) == 11] = float("inf")
+    del i
+    pk, pnb = lcq.compress(x, "abs", eb)
+    torch.cuda.synchronize()
+    psize = int(pnb.item())
+    hdr = pk[:64].cpu().numpy()
+    assert int(hdr[8:16].view(np.uint64)[0]) == n
+    k = int(hdr[16:24].view(np.uint64)[0])
+    nchunks = (n + CHUNK - 1) // CHUNK
+    ot = (64 + 8 * nchunks + 15) // 16 * 16
+    pl = (ot + 8 * (nchunks + 1) + 15) // 16 * 16
+    table = pk[64: 64 + 8 * nchunks].view(torch.int64)
+    offs = pk[ot: ot + 8 * (nchunks + 1)].view(torch.int64)
+    payload = int(offs[nchunks].item())
+    assert psize == (pl + payload + 15) // 16 * 16 + 4 * k
+    ws = torch.zeros(64, dtype=torch.uint8, device="cuda")
+    dec = lcq.decompress(pk, torch.float32, n, packed_bytes=psize, ws=ws)
+    assert lcq.stream_status(ws) == 0
+    sample = [0, 1, 2097151, 2097152, 2097153, nchunks // 2, nchunks - 2, nchunks - 1]
+    run = 0
+    for c in sample:
+        b, e = c * CHUNK, min((c + 1) * CHUNK, n)
+        xs = x[b:e].cpu().numpy()
+        st = O.quantize("abs", xs, eb)
+        po = O.pack(st, np.float32, xs.size)
+        # the oracle's single-chunk packed stream: one record at its payload offset
+        ot1 = (64 + 8 + 15) // 16 * 16
+        pl1 = (ot1 + 16 + 15) // 16 * 16
+        rsize = int(po[ot1 + 8: ot1 + 16].view(np.uint64)[0])
+        off = int(offs[c].item())
+        assert int(offs[c + 1].item()) - off == rsize, f"record size of chunk {c}"
+        got = pk[pl + off: pl + off + rsize].cpu().numpy()
+        assert np.array_equal(got, po[pl1: pl1 + rsize]), f"record of chunk {c}"
+        od = O.dequantize(st, np.float32, xs.size)
+        assert np.array_equal(dec[b:e].cpu().numpy().view(np.uint32), od.view(np.uint32)), f"decode of chunk {c}"
+        if c + 1 < nchunks:
+            ko = int(st[16:24].view(np.uint64)[0])
+            assert int(table[c + 1].item()) - int(table[c].item()) == ko
+        run += 1
+    assert run == len(sample)
