@@ -6,18 +6,19 @@
 // outliers are carried over verbatim, so unpacking restores the LCQ1 stream
 // byte for byte.
 //
-// Kernels (one wavefront per chunk, the chunk-per-wavefront mapping):
+// Kernels (one wavefront per chunk, the chunk-per-wavefront mapping; full
+// chunks take code paths without per-position masks):
 //   k_pack_plan   widths, modes and record sizes; one atomic add per
 //                 workgroup into its group's byte count
 //   k_pack_scan   one workgroup per group: record offsets, header, padding,
 //                 packed size
 //   k_pack_write  records (each chunk's packed bits assembled in LDS by
-//                 atomic ORs and stored 128 bits at a time; tiles taken last
-//                 to first, so the codes k_pack_plan read last come from the
-//                 Infinity Cache), chunk table, outliers
-//   k_unpack      per chunk: record checks, bit extraction, inverse zigzag,
-//                 wavefront prefix sum (delta mode), sentinels from the
-//                 bitmap; header, chunk table, outliers
+//                 atomic ORs and stored 128 bits at a time), chunk table,
+//                 outliers
+//   k_unpack      per chunk: the whole record staged in LDS, record checks,
+//                 bit extraction, inverse zigzag, wavefront prefix sum
+//                 (delta mode), sentinels from the bitmap; header, chunk
+//                 table, outliers
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
