@@ -473,12 +473,7 @@ __device__ void quant_finish(const FinishField<T> &f, uint64_t g) {
     const uint64_t c = cb + tid;
     const unsigned cnt = cnt_next;
     cnt_next = cb + kBlock + tid < c1 ? f.counts[cb + kBlock + tid] : 0u;
-    unsigned incl = cnt;
-#pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-      const unsigned t = __shfl_up(incl, o, 64);
-      if (lane >= o) incl += t;
-    }
+    const unsigned incl = wave_incl_add(cnt);
     if (lane == 63) s_wt[wave] = incl;
     __syncthreads();
     uint64_t before = 0, total = 0;

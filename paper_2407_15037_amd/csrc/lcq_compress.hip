@@ -353,15 +353,8 @@ __global__ __launch_bounds__(kBlock) void k_cmp_finish(CmpArgs a) {
     const unsigned cnt = cnt_next, sz = sz_next;
     cnt_next = cb + kBlock + tid < c1 ? a.counts[cb + kBlock + tid] : 0u;
     sz_next = cb + kBlock + tid < c1 ? a.sizes[cb + kBlock + tid] : 0u;
-    unsigned incl = cnt, sincl = sz;  // a batch's record bytes fit 32 bits
-#pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-      const unsigned t = __shfl_up(incl, o, 64), ts = __shfl_up(sincl, o, 64);
-      if (lane >= o) {
-        incl += t;
-        sincl += ts;
-      }
-    }
+    // (a batch's record bytes fit 32 bits)
+    const unsigned incl = wave_incl_add(cnt), sincl = wave_incl_add(sz);
     if (lane == 63) {
       s_wt[0][wave] = incl;
       s_wt[1][wave] = sincl;
@@ -475,7 +468,7 @@ __global__ __launch_bounds__(kBlock) void k_cmp_finish(CmpArgs a) {
 template <typename T, int Q>
 __device__ __forceinline__ uint32_t bin_code(T x, const FieldParams<T> &p, bool outlier) {
   if constexpr (is_rel_q<Q>()) {
-    const T q = rint_t(log2approx_dev(x) * p.inv);
+    const T q = rel_bin(x, p.inv);
     const int32_t b = (int32_t)(outlier ? (T)0 : q);  // in range when not an outlier
     const uint32_t hi = (uint32_t)(to_bits(x) >> (sizeof(T) * 8 - 32));
     const uint32_t code = __builtin_amdgcn_alignbit((uint32_t)b, hi, 31);

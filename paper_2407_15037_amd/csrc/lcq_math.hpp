@@ -81,22 +81,30 @@ template <typename T> LCQ_HD T pow2approx(T y) {
   return from_bits((U)(((U)k << F::kMant) | (to_bits(g) & F::kFracMask)));
 }
 
-// Device forms of the two approximations, value for value the same as
-// log2approx / pow2approx above (the sign bit of log2approx_dev's argument
-// is ignored too), in fewer instructions for float32:
-// - log2: E - 128 is the exponent byte E with its top bit flipped, read as
-//   a signed byte (one xor and one signed bit-field extract);
+// Device forms, value for value the same as the plain ones above, in fewer
+// instructions.
+// - REL's bin rint(log2approx(x) * inv), float32 (rel_bin): with d the
+//   integer (|x| bits) - 127 * 2^23 = (E - 127) 2^23 + fraction field,
+//   log2approx(x) = e + m is d * 2^-23 rounded once to float, i.e. the
+//   int-to-float conversion of d (one rounding to 24 bits, round to nearest
+//   even) scaled by 2^-23.  2d is one shift-and-add of x's bits (the shift
+//   drops the sign; for normal x, 1 <= E <= 254, it fits in an int32), its
+//   conversion is log2approx(x) * 2^24 exactly, and inv * 2^-24 is exact
+//   (inv >= 1/2 here, so no underflow), so the product and its rounding are
+//   those of log2approx(x) * inv.  Non-normal x (stored losslessly whatever
+//   the bin) give some finite bin.
 // - pow2: t is finite here (a finite bin times a finite step), so the clamp
 //   is one median-of-three; for t >= 0, t - (k - 1) = fract(t) + 1 exactly
 //   when t >= 1 (both sides exact) and with the same single rounding of
 //   t + 1 when t < 1 (k = 0).
-template <typename T> __device__ __forceinline__ T log2approx_dev(T a) {
+// (lgoff: -127 * 2^24 mod 2^32, passed in so that a kernel can hold it in a
+// scalar register)
+template <typename T> __device__ __forceinline__ T rel_bin(T x, T inv, uint32_t lgoff = 0x81000000u) {
   if constexpr (sizeof(T) == 4) {
-    const uint32_t u = to_bits(a);
-    const int e = (int)((u ^ 0x40000000u) << 1) >> 24;  // E - 128
-    return from_bits((uint32_t)(0x3F800000u | (u & 0x007FFFFFu))) + (float)e;
+    const int32_t d2 = (int32_t)((to_bits(x) << 1) + lgoff);  // 2d
+    return rint_t((float)d2 * (inv * 0x1p-24f));
   } else {
-    return log2approx(a);
+    return rint_t(log2approx(x) * inv);
   }
 }
 // (emax: the largest exponent field as a value of T, passed in so that a
@@ -167,10 +175,11 @@ template <typename T> struct EncK {
   T emax, bound, low;
   int32_t sent;
   int cls;
+  uint32_t lgoff;  // rel_bin's offset
 };
 template <typename T, int Q>
 __device__ __forceinline__ EncK<T> enc_consts(const FieldParams<T> &p) {
-  return EncK<T>{(T)FT<T>::kExpMask, p.bound, p.low, kSent, class_mask<Q>()};
+  return EncK<T>{(T)FT<T>::kExpMask, p.bound, p.low, kSent, class_mask<Q>(), 0x81000000u};
 }
 // v, held in a vector register from here on (an empty asm the compiler
 // cannot see through, so it keeps the register instead of re-creating v).
@@ -186,6 +195,7 @@ __device__ __forceinline__ EncK<T> enc_consts_pinned(const FieldParams<T> &p) {
   k.low = pin_v(k.low);
   k.sent = pin_v(k.sent);
   k.cls = pin_v(k.cls);
+  asm volatile("" : "+s"(k.lgoff));  // a scalar operand of the shift-and-add
   return k;
 }
 
@@ -206,7 +216,7 @@ __device__ __forceinline__ int32_t encode(T x, const FieldParams<T> &p, const En
     // instruction of its own)
     const T a = abs_t(x);
     // (the approximate log2 reads only the exponent and fraction fields)
-    const T q = rint_t((Q == kREL_LIBM ? lib_log2(a) : log2approx_dev(x)) * p.inv);
+    const T q = Q == kREL_LIBM ? rint_t(lib_log2(a) * p.inv) : rel_bin(x, p.inv, k.lgoff);
     // section 3.3: both range tests, on the float, before any conversion
     ok = ok && (q > (T)-kMaxBin) && (q < (T)kMaxBin);
     // qb is integral and inside (-2^30, 2^30), so (T)(int)qb == qb exactly

@@ -74,9 +74,8 @@ __device__ __forceinline__ void chunk_z(const uint32_t (&cv)[NSUB][W], unsigned 
     const unsigned p = chunk_pos<W>(j, lane);
     uint32_t prev = 0;
     if constexpr (DELTA) {
-      const uint32_t up = __shfl_up(cv[j][W - 1], 1, 64);
-      prev = lane == 0 ? carry : up;
-      carry = __shfl(cv[j][W - 1], 63, 64);
+      prev = lane_up1(cv[j][W - 1], carry);
+      carry = lane63(cv[j][W - 1]);
     }
 #pragma unroll
     for (int e = 0; e < W; e++) {
@@ -93,16 +92,21 @@ __device__ __forceinline__ unsigned zz_width(int32_t lo, int32_t hi) {
   return bitlen(max(zigzag((uint32_t)lo), zigzag((uint32_t)hi)));
 }
 
-__device__ __forceinline__ int32_t wave_max_i(int32_t v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o, 64));
-  return v;
+// Largest / smallest v over the wavefront (uniform): the prefix pattern
+// of wave_incl_add with max / min, lanes without a source keeping their own
+// value, read from lane 63.
+template <bool MAX> __device__ __forceinline__ int32_t wave_ext_i(int32_t v) {
+  const auto f = [](int32_t a, uint32_t b) { return MAX ? max(a, (int32_t)b) : min(a, (int32_t)b); };
+  v = f(v, dpp_mov<dpp::kRowShr1>((uint32_t)v, (uint32_t)v));
+  v = f(v, dpp_mov<dpp::kRowShr2>((uint32_t)v, (uint32_t)v));
+  v = f(v, dpp_mov<dpp::kRowShr4>((uint32_t)v, (uint32_t)v));
+  v = f(v, dpp_mov<dpp::kRowShr8>((uint32_t)v, (uint32_t)v));
+  v = f(v, dpp_mov<dpp::kRowBcast15, 0xa>((uint32_t)v, (uint32_t)v));
+  v = f(v, dpp_mov<dpp::kRowBcast31, 0xc>((uint32_t)v, (uint32_t)v));
+  return (int32_t)lane63((uint32_t)v);
 }
-__device__ __forceinline__ int32_t wave_min_i(int32_t v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v = min(v, __shfl_xor(v, o, 64));
-  return v;
-}
+__device__ __forceinline__ int32_t wave_max_i(int32_t v) { return wave_ext_i<true>(v); }
+__device__ __forceinline__ int32_t wave_min_i(int32_t v) { return wave_ext_i<false>(v); }
 
 // Width and mode of a chunk from its c' values (sentinels already 0; same
 // on every lane), from extremes instead of every z: the plain width is that
@@ -116,9 +120,8 @@ __device__ __forceinline__ void chunk_width(const uint32_t (&cv)[NSUB][W], unsig
   uint32_t carry = 0;  // last c' of the previous sub-block
 #pragma unroll
   for (int j = 0; j < NSUB; j++) {
-    const uint32_t up = __shfl_up(cv[j][W - 1], 1, 64);
-    uint32_t prev = lane == 0 ? carry : up;
-    carry = __shfl(cv[j][W - 1], 63, 64);
+    uint32_t prev = lane_up1(cv[j][W - 1], carry);
+    carry = lane63(cv[j][W - 1]);
     const unsigned p = chunk_pos<W>(j, lane);
 #pragma unroll
     for (int e = 0; e < W; e++) {
@@ -268,16 +271,11 @@ __device__ __forceinline__ void record_codes_sub(const uint32_t *row, const uint
     // prefix sum over the chunk in position order (mod 2^32)
 #pragma unroll
     for (int e = 1; e < W; e++) v[e] += v[e - 1];
-    uint32_t incl = v[W - 1];
-#pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-      const uint32_t t = __shfl_up(incl, o, 64);
-      if (lane >= o) incl += t;
-    }
+    const uint32_t incl = wave_incl_add(v[W - 1]);
     const uint32_t excl = incl - v[W - 1] + carry;
 #pragma unroll
     for (int e = 0; e < W; e++) v[e] += excl;
-    carry += __shfl(incl, 63, 64);
+    carry += lane63(incl);
   }
   const unsigned fl = bm ? (bm[l0 / 8] >> (l0 % 8)) & ((1u << W) - 1u) : 0u;
 #pragma unroll

@@ -44,6 +44,51 @@ __device__ __forceinline__ void store_state(uint64_t *p, uint64_t v) {
   __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// Cross-lane steps on DPP (the data-parallel-primitive operand forms of
+// the gfx9 family): a value from another lane in the same instruction,
+// with no LDS round trip as in a permute shuffle.  A lane whose source is
+// outside its row (row shifts), outside the wavefront (wave shift) or in a
+// row left out by the row mask keeps `old`.
+namespace dpp {
+constexpr int kQuadXor1 = 0xB1, kQuadXor2 = 0x4E;  // quad_perm [1,0,3,2], [2,3,0,1]
+constexpr int kRowShr1 = 0x111, kRowShr2 = 0x112, kRowShr4 = 0x114, kRowShr8 = 0x118;
+constexpr int kRowMirror = 0x140, kRowHalfMirror = 0x141;  // lane i of 16 / of 8 reads 15-i / 7-i
+constexpr int kWaveShr1 = 0x138;    // lane l reads lane l - 1
+constexpr int kRowBcast15 = 0x142;  // row r reads lane 16 r - 1
+constexpr int kRowBcast31 = 0x143;  // rows 2, 3 read lane 31
+}  // namespace dpp
+template <int CTRL, int ROWS = 0xf>
+__device__ __forceinline__ uint32_t dpp_mov(uint32_t old, uint32_t v) {
+  return (uint32_t)__builtin_amdgcn_update_dpp((int)old, (int)v, CTRL, ROWS, 0xf, false);
+}
+// v of lane l - 1; lane 0 gets fill.  fill goes through an empty asm so
+// that the compiler cannot see a constant 0 in it: with one, it folds the
+// shift into the consuming subtraction (v_subrev_u32 with the shifted
+// operand), and that form measured wrong on gfx950 (the difference came
+// out negated on most lanes), while the plain shifted move with `old`, and
+// the folded add and or forms the other helpers compile to, measured right.
+__device__ __forceinline__ uint32_t lane_up1(uint32_t v, uint32_t fill) {
+  asm volatile("" : "+v"(fill));
+  return dpp_mov<dpp::kWaveShr1>(fill, v);
+}
+// Inclusive prefix sum over the wavefront's lanes (mod 2^32): within each
+// row of 16 lanes by shifts of 1, 2, 4 and 8, then rows 1 and 3 add the
+// last lane of the row below them and rows 2 and 3 the last lane of rows
+// 0-1.
+__device__ __forceinline__ uint32_t wave_incl_add(uint32_t v) {
+  v += dpp_mov<dpp::kRowShr1>(0u, v);
+  v += dpp_mov<dpp::kRowShr2>(0u, v);
+  v += dpp_mov<dpp::kRowShr4>(0u, v);
+  v += dpp_mov<dpp::kRowShr8>(0u, v);
+  v += dpp_mov<dpp::kRowBcast15, 0xa>(0u, v);
+  v += dpp_mov<dpp::kRowBcast31, 0xc>(0u, v);
+  return v;
+}
+// v of lane 63 (a uniform value).
+__device__ __forceinline__ uint32_t lane63(uint32_t v) {
+  return (uint32_t)__builtin_amdgcn_readlane((int)v, 63);
+}
+
 __device__ __forceinline__ uint64_t wave_sum(uint64_t v) {
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
@@ -602,9 +647,14 @@ __host__ __device__ inline uint64_t inline_stream_bytes(uint64_t n, uint64_t s) 
 // values are laid out).
 template <int W> __device__ __forceinline__ unsigned gather_flag_word(unsigned m, int lane) {
   constexpr int LANES = 32 / W;
+  static_assert(LANES == 8 || LANES == 16, "groups of 8 or 16 lanes");
   unsigned v = m << (W * (lane & (LANES - 1)));
-#pragma unroll
-  for (int o = 1; o < LANES; o <<= 1) v |= __shfl_xor(v, o, 64);
+  // the OR of each quad (exchanges with lane xor 1, then xor 2), of each 8
+  // lanes (lane i with 7 - i: the other quad), of each 16 (i with 15 - i)
+  v |= dpp_mov<dpp::kQuadXor1>(0u, v);
+  v |= dpp_mov<dpp::kQuadXor2>(0u, v);
+  v |= dpp_mov<dpp::kRowHalfMirror>(0u, v);
+  if constexpr (LANES == 16) v |= dpp_mov<dpp::kRowMirror>(0u, v);
   return v;
 }
 

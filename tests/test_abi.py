@@ -142,6 +142,26 @@ def test_fused_kernels_have_no_fused_or_packed_fp(compress_asm):
     assert modes and all(m == "3" for m in modes), modes
 
 
+@pytest.fixture(scope="module")
+def pack_asm(tmp_path_factory):
+    from paper_2407_15037_amd import build
+    path = str(tmp_path_factory.mktemp("asm") / "lcq_pack.s")
+    build.asm(path, src=os.path.join(ROOT, "paper_2407_15037_amd", "csrc", "lcq_pack.hip"))
+    return open(path).read()
+
+
+# cross-lane (DPP) instruction forms measured right on gfx950 by a lane-layout
+# check; a subtraction with a DPP operand measured wrong there
+DPP_FORMS = {"v_mov_b32_dpp", "v_add_u32_dpp", "v_or_b32_dpp"}
+
+
+def test_only_checked_dpp_forms(device_asm, compress_asm, pack_asm):
+    for asm in (device_asm, compress_asm, pack_asm):
+        used = set(re.findall(r"^\s*(v_\w+_dpp)\b", asm, flags=re.M))
+        assert used <= DPP_FORMS, sorted(used - DPP_FORMS)
+    assert re.search(r"^\s*v_mov_b32_dpp\b.*wave_shr:1", compress_asm, flags=re.M)
+
+
 def test_fused_entry_points_refuse_bad_arguments():
     import paper_2407_15037_amd as lcq
     L = lcq.lib()
