@@ -155,8 +155,14 @@ def pack_asm(tmp_path_factory):
 DPP_FORMS = {"v_mov_b32_dpp", "v_add_u32_dpp", "v_or_b32_dpp"}
 
 
-def test_only_checked_dpp_forms(device_asm, compress_asm, pack_asm):
-    for asm in (device_asm, compress_asm, pack_asm):
+def test_only_checked_dpp_forms(device_asm, compress_asm, pack_asm, tmp_path):
+    from paper_2407_15037_amd import build
+    others = []
+    for name in ("lcq_batch.hip", "lcq_serve.hip"):
+        path = str(tmp_path / (name + ".s"))
+        build.asm(path, src=os.path.join(ROOT, "paper_2407_15037_amd", "csrc", name))
+        others.append(open(path).read())
+    for asm in [device_asm, compress_asm, pack_asm] + others:
         used = set(re.findall(r"^\s*(v_\w+_dpp)\b", asm, flags=re.M))
         assert used <= DPP_FORMS, sorted(used - DPP_FORMS)
     assert re.search(r"^\s*v_mov_b32_dpp\b.*wave_shr:1", compress_asm, flags=re.M)
