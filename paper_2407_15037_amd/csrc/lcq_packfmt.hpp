@@ -86,27 +86,17 @@ __device__ __forceinline__ void chunk_z(const uint32_t (&cv)[NSUB][W], unsigned 
   }
 }
 
-// Bit length of the largest zigzag code of the int32 values in [lo, hi]
-// (zigzag grows with |v| on either side of 0, so the extremes decide).
-__device__ __forceinline__ unsigned zz_width(int32_t lo, int32_t hi) {
-  return bitlen(max(zigzag((uint32_t)lo), zigzag((uint32_t)hi)));
+// OR of v over the wavefront (uniform): the prefix pattern of
+// wave_incl_add with OR, read from lane 63.
+__device__ __forceinline__ uint32_t wave_or_u(uint32_t v) {
+  v |= dpp_mov<dpp::kRowShr1>(0u, v);
+  v |= dpp_mov<dpp::kRowShr2>(0u, v);
+  v |= dpp_mov<dpp::kRowShr4>(0u, v);
+  v |= dpp_mov<dpp::kRowShr8>(0u, v);
+  v |= dpp_mov<dpp::kRowBcast15, 0xa>(0u, v);
+  v |= dpp_mov<dpp::kRowBcast31, 0xc>(0u, v);
+  return lane63(v);
 }
-
-// Largest / smallest v over the wavefront (uniform): the prefix pattern
-// of wave_incl_add with max / min, lanes without a source keeping their own
-// value, read from lane 63.
-template <bool MAX> __device__ __forceinline__ int32_t wave_ext_i(int32_t v) {
-  const auto f = [](int32_t a, uint32_t b) { return MAX ? max(a, (int32_t)b) : min(a, (int32_t)b); };
-  v = f(v, dpp_mov<dpp::kRowShr1>((uint32_t)v, (uint32_t)v));
-  v = f(v, dpp_mov<dpp::kRowShr2>((uint32_t)v, (uint32_t)v));
-  v = f(v, dpp_mov<dpp::kRowShr4>((uint32_t)v, (uint32_t)v));
-  v = f(v, dpp_mov<dpp::kRowShr8>((uint32_t)v, (uint32_t)v));
-  v = f(v, dpp_mov<dpp::kRowBcast15, 0xa>((uint32_t)v, (uint32_t)v));
-  v = f(v, dpp_mov<dpp::kRowBcast31, 0xc>((uint32_t)v, (uint32_t)v));
-  return (int32_t)lane63((uint32_t)v);
-}
-__device__ __forceinline__ int32_t wave_max_i(int32_t v) { return wave_ext_i<true>(v); }
-__device__ __forceinline__ int32_t wave_min_i(int32_t v) { return wave_ext_i<false>(v); }
 
 // Width and mode of a chunk from its c' values (sentinels already 0; same
 // on every lane), from extremes instead of every z: the plain width is that
@@ -135,8 +125,12 @@ __device__ __forceinline__ void chunk_width(const uint32_t (&cv)[NSUB][W], unsig
       prev = cv[j][e];
     }
   }
-  const unsigned wp = zz_width(wave_min_i(plo), wave_max_i(phi));
-  const unsigned wd = zz_width(wave_min_i(dlo), wave_max_i(dhi));
+  // the largest zigzag code of a lane's range [lo, hi] is that of lo or
+  // of hi, and no lane's exceeds that of the chunk's own extremes (lanes
+  // hold them), so the chunk's width is the bit length of the largest
+  // per-lane one -- the bit length of their OR
+  const unsigned wp = bitlen(wave_or_u(max(zigzag((uint32_t)plo), zigzag((uint32_t)phi))));
+  const unsigned wd = bitlen(wave_or_u(max(zigzag((uint32_t)dlo), zigzag((uint32_t)dhi))));
   mode = wd < wp ? 1u : 0u;
   w = mode ? wd : wp;
 }

@@ -48,7 +48,8 @@ __device__ __forceinline__ void store_state(uint64_t *p, uint64_t v) {
 // the gfx9 family): a value from another lane in the same instruction,
 // with no LDS round trip as in a permute shuffle.  A lane whose source is
 // outside its row (row shifts), outside the wavefront (wave shift) or in a
-// row left out by the row mask keeps `old`.
+// row left out by the row mask keeps `old`.  Callers run them with all 64
+// lanes active: a lane reads the others' registers whatever their state.
 namespace dpp {
 constexpr int kQuadXor1 = 0xB1, kQuadXor2 = 0x4E;  // quad_perm [1,0,3,2], [2,3,0,1]
 constexpr int kRowShr1 = 0x111, kRowShr2 = 0x112, kRowShr4 = 0x114, kRowShr8 = 0x118;
