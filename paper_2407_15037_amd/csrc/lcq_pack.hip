@@ -39,7 +39,6 @@ namespace {
 
 constexpr int kCW = 4;                           // codes per lane per sub-block
 constexpr int kCSub = (int)kChunk / (64 * kCW);  // 4 sub-blocks per chunk
-constexpr uint64_t kPackTile = kChunk * kWaves;  // codes per workgroup (4 chunks)
 
 // The LCQ1 header of an input stream describes exactly this call.
 __device__ __forceinline__ bool lcq1_header_ok(const uint8_t *s, uint64_t bytes, int dtype,
@@ -137,13 +136,13 @@ struct PackArgs {
   int dtype;
 };
 
-__global__ __launch_bounds__(kBlock) void k_pack_plan(PackArgs a) {
-  __shared__ unsigned s_tot[kWaves];
+__global__ __launch_bounds__(64 * kStageWaves) void k_pack_plan(PackArgs a) {
+  __shared__ unsigned s_tot[kStageWaves];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const uint64_t n = a.n, nch = n_chunks(n);
   uint64_t k;
   if (!lcq1_header_ok(a.in, a.in_bytes, a.dtype, n, k)) return;  // uniform over the grid
-  const uint64_t c = (uint64_t)blockIdx.x * kWaves + wave;
+  const uint64_t c = (uint64_t)blockIdx.x * kStageWaves + wave;
   unsigned size = 0;
   if (c < nch) {
     const int32_t *codes = reinterpret_cast<const int32_t *>(a.in + 64);
@@ -160,7 +159,7 @@ __global__ __launch_bounds__(kBlock) void k_pack_plan(PackArgs a) {
   if (threadIdx.x == 0) {
     unsigned long long t = 0;
 #pragma unroll
-    for (int i = 0; i < kWaves; i++) t += s_tot[i];
+    for (int i = 0; i < kStageWaves; i++) t += s_tot[i];
     if (t) atomicAdd(a.group + blockIdx.x / a.tiles_per_group, t);
   }
 }
@@ -415,16 +414,19 @@ lcq_status lcq_pack(lcq_dtype t, const void *d_stream, uint64_t stream_bytes, ui
   a.sizes = reinterpret_cast<uint32_t *>(ws + pk_sizes_off());
   a.meta = reinterpret_cast<uint32_t *>(ws + pk_meta_off(C));
   a.group = reinterpret_cast<unsigned long long *>(ws + 256);
-  a.tiles_per_group = tiles_per_group(ntiles, kPackTile / kChunk);
-  a.chunks_per_group = a.tiles_per_group * (kPackTile / kChunk);
-  a.ngroups = std::max<uint64_t>(1, (ntiles + a.tiles_per_group - 1) / a.tiles_per_group);
+  // the plan pass in workgroups of kStageWaves chunks (one group add each)
+  const uint64_t ptiles = (C + kStageWaves - 1) / kStageWaves;
+  a.tiles_per_group = tiles_per_group(ptiles, kStageWaves);
+  a.chunks_per_group = a.tiles_per_group * kStageWaves;
+  a.ngroups = std::max<uint64_t>(1, (ptiles + a.tiles_per_group - 1) / a.tiles_per_group);
   a.status = reinterpret_cast<unsigned long long *>(ws);
   a.epoch = g_pk_epoch.fetch_add(1) + 1;
   a.dtype = (int)t;
   const unsigned cg = (unsigned)std::min<uint64_t>((a.ngroups + kBlock - 1) / kBlock, 1024);
   hipLaunchKernelGGL(k_clear_pk, dim3(cg), dim3(kBlock), 0, stream,
                      reinterpret_cast<uint64_t *>(a.group), a.ngroups);
-  if (ntiles) hipLaunchKernelGGL(k_pack_plan, dim3((unsigned)ntiles), dim3(kBlock), 0, stream, a);
+  if (ntiles)
+    hipLaunchKernelGGL(k_pack_plan, dim3((unsigned)ptiles), dim3(64 * kStageWaves), 0, stream, a);
   hipLaunchKernelGGL(k_pack_scan, dim3((unsigned)a.ngroups), dim3(kBlock), 0, stream, a);
   if (ntiles) hipLaunchKernelGGL(k_pack_write, dim3((unsigned)ntiles), dim3(kBlock), 0, stream, a);
   return check_launch_pk();
