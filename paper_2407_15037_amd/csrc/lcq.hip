@@ -153,7 +153,7 @@ __device__ __forceinline__ FieldParams<T> stage_params(const StageQ &a) {
 }
 
 template <typename T, int Q, int CPW, int PF>
-__global__ __launch_bounds__(64 * kStageWaves) void k_quant_stage(StageQ a) {
+__global__ __launch_bounds__(64 * stage_waves<T>()) void k_quant_stage(StageQ a) {
   using U = typename FT<T>::U;
   StageField<T> f;
   f.in = static_cast<const T *>(a.in);
@@ -307,7 +307,7 @@ void launch_quantize(const PlainQ &a, const StageQ &sq, hipStream_t s) {
   constexpr QShape sh = kQVariants[V];
   if constexpr (sh.cpw > 0) {
     hipLaunchKernelGGL((k_quant_stage<T, Q, sh.cpw, sh.pf>), dim3((unsigned)a.ntiles),
-                       dim3(64 * kStageWaves), 0, s, sq);
+                       dim3(64 * stage_waves<T>()), 0, s, sq);
     if (g_ev_mid) (void)hipEventRecord(g_ev_mid, s);
     hipLaunchKernelGGL((k_quant_finish<T, Q>), dim3((unsigned)sq.ngroups), dim3(kBlock), 0, s,
                        sq);

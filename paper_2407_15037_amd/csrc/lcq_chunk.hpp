@@ -262,14 +262,15 @@ __device__ __forceinline__ unsigned encode_chunk(const StageField<T> &f, uint64_
   return cnt;
 }
 
-// Pass 1 for the CPW * kStageWaves chunks of workgroup `tile`, PF chunks per
+// Pass 1 for the CPW * stage_waves<T>() chunks of workgroup `tile`, PF chunks per
 // wavefront loaded before any is encoded.
 template <typename T, int Q, int CPW, int PF>
 __device__ void quant_chunks(const StageField<T> &f, uint64_t tile) {
   static_assert(PF > 0 && CPW % PF == 0, "whole prefetch groups");
+  constexpr int kSW = stage_waves<T>();
   constexpr int W = ChunkShape<T>::W, NSUB = ChunkShape<T>::NSUB;
-  __shared__ unsigned s_cnt[kStageWaves];
-  __shared__ typename FT<T>::U s_stage[kStageWaves][stage_cap<T>()];  // one row per wavefront
+  __shared__ unsigned s_cnt[kSW];
+  __shared__ typename FT<T>::U s_stage[kSW][stage_cap<T>()];  // one row per wavefront
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // uniform: chunk logic is scalar
   const uint64_t nch = n_chunks(f.n);
@@ -280,12 +281,12 @@ __device__ void quant_chunks(const StageField<T> &f, uint64_t tile) {
     T x[PF][NSUB][W];
 #pragma unroll
     for (int p = 0; p < PF; p++) {
-      const uint64_t c = (tile * CPW + r0 + p) * kStageWaves + wave;
+      const uint64_t c = (tile * CPW + r0 + p) * kSW + wave;
       if (c < nch) load_chunk<T>(f.in, f.n, c, lane, x[p]);
     }
 #pragma unroll
     for (int p = 0; p < PF; p++) {
-      const uint64_t c = (tile * CPW + r0 + p) * kStageWaves + wave;
+      const uint64_t c = (tile * CPW + r0 + p) * kSW + wave;
       if (c < nch) wsum += encode_chunk<T, Q>(f, c, lane, x[p], s_stage[wave], k);  // uniform
     }
   }
@@ -294,7 +295,7 @@ __device__ void quant_chunks(const StageField<T> &f, uint64_t tile) {
   if (tid == 0) {
     unsigned long long t = 0;
 #pragma unroll
-    for (int w = 0; w < kStageWaves; w++) t += s_cnt[w];
+    for (int w = 0; w < kSW; w++) t += s_cnt[w];
     if (t) atomicAdd(f.group + tile / f.tiles_per_group, t);
   }
 }

@@ -131,7 +131,9 @@ constexpr Shape kDVariants[kNumVariants] = {{4, 1}, {2, 2}, {4, 2}, {4, 4}, {2, 
 
 // Values per quantize tile / codes per dequantize tile of a variant.
 inline uint64_t quant_tile_len(lcq_dtype t, int v) {
-  if (kQVariants[v].cpw) return (uint64_t)kChunk * kStageWaves * kQVariants[v].cpw;
+  if (kQVariants[v].cpw)
+    return (uint64_t)kChunk * (t == LCQ_F64 ? stage_waves<double>() : stage_waves<float>()) *
+           kQVariants[v].cpw;
   const uint64_t w = t == LCQ_F64 ? 2 : 4;
   return (uint64_t)kBlock * w * kQVariants[v].slots * kQVariants[v].rounds;
 }

@@ -20,12 +20,15 @@ namespace lcq {
 
 constexpr int kBlock = 256;  // threads per workgroup (4 wave64)
 constexpr int kWaves = kBlock / 64;
-// Wavefronts per workgroup of the quantize first pass (one chunk each): 8
-// halves its group-counter atomic adds against 4 (REL, with outliers in
-// almost every chunk, adds on every workgroup); measured quantize ABS 195 ->
-// 188 us, REL 203 -> 199 us on the 512^3 float32 field; 16 measured slower
-// (REL 249 us).
+// Wavefronts per workgroup of the quantize first pass (one chunk each),
+// per dtype: for float32, 8 halves its group-counter atomic adds against 4
+// (REL, with outliers in almost every chunk, adds on every workgroup):
+// measured quantize ABS 195 -> 188 us, REL 203 -> 199 us on the 512^3 field
+// (16: REL 249 us); for float64 (half the chunks per byte) 8 measured slower
+// than 4 on the 384^3 grid (ABS pass 1 109 -> 112 us), so it keeps 4.  The
+// pack plan takes 8 (kStageWaves).
 constexpr int kStageWaves = 8;
+template <typename T> constexpr int stage_waves() { return sizeof(T) == 4 ? 8 : 4; }
 
 // look-back state word: 2-bit flag | 62-bit count
 constexpr uint64_t kFlagAgg = 1ull << 62;   // the tile's own outlier count
